@@ -1,0 +1,464 @@
+/*
+ * moray_oracle.c -- plain, slow FP64 CPU reference of the single-pass
+ * adaptive ray trace of Wise & Abel (Enzo+Moray).
+ *
+ * TEST INFRASTRUCTURE ONLY: it exists to check the GPU library against and is
+ * called only by the test-suite, the smoke check and the benchmark's CPU
+ * baseline. Nothing here is shared with the GPU library.
+ *
+ * What it computes, in the paper's order (section 3.1, steps 1-3):
+ *   Step 1  For every source and energy group, 12*4^l0 rays on the HEALPix
+ *           nested pixel centres of level l0, each with an equal share of the
+ *           group's photon rate (section 2.1).
+ *   Step 2  All radiation fields start at zero.
+ *   Step 3  Every ray is marched cell by cell. In each cell:
+ *     3b/3d the exit distance t_exit = min over axes of (next boundary plane
+ *           - source coordinate) / direction component (Eq. trace);
+ *     3e    if the ray's solid angle at t_exit exceeds phi_c rays per cell
+ *           face, i.e. 12*4^l < 4*pi*phi_c*t_exit^2 in cell units (Eq. split),
+ *           the ray is replaced by its four nested children 4p..4p+3, which
+ *           keep the radius, take a quarter of the photon rate each and are
+ *           traced next (child 0 first);
+ *     3f    otherwise the segment dr = t_exit - r absorbs
+ *           dP = P (1 - exp(-tau)) with tau = sigma n_H x_HI dr (Eqs. dtau,
+ *           flux); dP is added to the cell's absorbed-photon rate and
+ *           dP (E - E_ion) to its heating rate (Eqs. kph, gamma);
+ *     3h    P -= dP, r = t_exit;
+ *     3i    the ray ends once P < p_min_frac * P0 (its unattenuated share);
+ *     3k    a ray leaving the root grid escapes (isolated boundaries); a ray
+ *           entering a root cell covered by a child grid continues in the
+ *           child at the crossing point (step 3c), and returns to the root
+ *           when it leaves the child.
+ *   Finally k_ph = absorbed / (n_H x_HI V_cell) and heating likewise; the
+ *   time step dt_P cancels because P is a rate (single pass, infinite c).
+ *
+ * Readings of points the paper leaves open (each also listed in the design
+ * notes): the split is tested at the exit radius (step 3e); a split is strict
+ * (<); children may split again at once; a point on a cell plane belongs to
+ * the upper cell when the direction component is >= 0, else the lower one;
+ * exit-axis ties go to the lowest axis; dr = max(0, t_exit - r) and r never
+ * decreases; the residual of a ray cut off by p_min_frac is tallied as
+ * "truncated" so that absorbed + escaped + truncated = emitted.
+ */
+#include "moray_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define EV_ERG 1.602176634e-12
+#define PI_D 3.14159265358979323846
+#define MAX_LEVEL 29
+#define STACK_MAX 512
+
+double orc_const_ev_erg(void) { return EV_ERG; }
+
+/* ---- Neumaier-compensated sum ------------------------------------------ */
+typedef struct { double s, c; } csum;
+static void cs_add(csum* a, double x) {
+  double t = a->s + x;
+  if (fabs(a->s) >= fabs(x)) a->c += (a->s - t) + x;
+  else a->c += (x - t) + a->s;
+  a->s = t;
+}
+static double cs_get(const csum* a) { return a->s + a->c; }
+
+/* ---- HEALPix nested pixel centre (Gorski et al. 2005) ------------------- */
+/* The pixel index is split into base face f and in-face coordinates (ix, iy)
+ * (even bits -> ix, odd bits -> iy). The ring index is j = jr(f)*Ns - ix - iy - 1.
+ * In the polar caps z = 1 - nr^2/(3 Ns^2), in the equatorial belt
+ * z = 2(2Ns - j)/(3Ns); the azimuth is phi = (pi/2)(jp - (s+1)/2)/nr.
+ * z and sin(theta) are formed from exact integers, and cos/sin(phi) are taken
+ * of the angle reduced to the first octant, so multiples of pi/4 come out
+ * exact and the pixel set keeps its mirror symmetries bit for bit. */
+void orc_pix2vec_nest(int level, uint64_t pix, double v[3]) {
+  static const int jrll[12] = {2, 2, 2, 2, 3, 3, 3, 3, 4, 4, 4, 4};
+  static const int jpll[12] = {1, 3, 5, 7, 0, 2, 4, 6, 1, 3, 5, 7};
+  const int64_t ns = (int64_t)1 << level;
+  const uint64_t npface = (uint64_t)ns * (uint64_t)ns;
+  const int face = (int)(pix / npface);
+  const uint64_t ipf = pix % npface;
+  int64_t ix = 0, iy = 0;
+  for (int b = 0; b < level; ++b) {
+    ix |= (int64_t)((ipf >> (2 * b)) & 1u) << b;
+    iy |= (int64_t)((ipf >> (2 * b + 1)) & 1u) << b;
+  }
+  const int64_t jr = (int64_t)jrll[face] * ns - ix - iy - 1;
+  int64_t nr;
+  int kshift;
+  double z, sth;
+  if (jr < ns || jr > 3 * ns) {
+    nr = (jr < ns) ? jr : 4 * ns - jr;
+    const double den = 3.0 * (double)ns * (double)ns;
+    z = (double)(3 * ns * ns - nr * nr) / den;
+    sth = (double)nr * sqrt((double)(6 * ns * ns - nr * nr)) / den;
+    if (jr > 3 * ns) z = -z;
+    kshift = 0;
+  } else {
+    nr = ns;
+    const int64_t m = 2 * (2 * ns - jr);
+    z = (double)m / (3.0 * (double)ns);
+    sth = sqrt((double)(9 * ns * ns - m * m)) / (3.0 * (double)ns);
+    kshift = (int)((jr - ns) & 1);
+  }
+  int64_t jp = ((int64_t)jpll[face] * nr + ix - iy + 1 + kshift) / 2;
+  if (jp > 4 * nr) jp -= 4 * nr;
+  if (jp < 1) jp += 4 * nr;
+  const int64_t num = 2 * jp - kshift - 1, den = 2 * nr;   /* phi / (pi/2) = num/den */
+  const int64_t q = num / den, rem = num % den;
+  double c, s;
+  if (2 * rem == den) {
+    c = s = sqrt(0.5);
+  } else {
+    const int64_t m = (2 * rem < den) ? rem : den - rem;
+    const double beta = ((double)m / (double)den) * (PI_D / 2.0);
+    const double cb = cos(beta), sb = sin(beta);
+    if (2 * rem < den) { c = cb; s = sb; } else { c = sb; s = cb; }
+  }
+  double cx, cy;
+  switch (q & 3) {
+    case 0: cx = c; cy = s; break;
+    case 1: cx = -s; cy = c; break;
+    case 2: cx = -c; cy = -s; break;
+    default: cx = s; cy = -c; break;
+  }
+  v[0] = sth * cx;
+  v[1] = sth * cy;
+  v[2] = z;
+}
+
+/* ---- grid hierarchy ------------------------------------------------------ */
+typedef struct {
+  const orc_grid* g;
+  int n_grids;
+  int* cover;          /* root cell -> index of the child grid over it, or -1 */
+  size_t* cell_off;    /* first cell of grid q in the concatenated outputs */
+  size_t n_cells;
+} hier;
+
+/* Cell containing coordinate x for a ray with direction component n: points on
+ * a plane go to the upper cell when n >= 0 and to the lower cell otherwise. */
+static long cell_rule(double x, double n) { return n >= 0.0 ? (long)floor(x) : (long)ceil(x) - 1; }
+static long floor_half(long c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
+
+static int in_grid(const orc_grid* G, const long c[3]) {
+  return c[0] >= 0 && c[1] >= 0 && c[2] >= 0 && c[0] < G->nx && c[1] < G->ny && c[2] < G->nz;
+}
+
+/* Enter child grid ch from root cell rc at radius r; along the crossing axis
+ * the fine cell follows from the face crossed, along the others from the
+ * position, kept inside the two fine cells under rc. */
+static void enter_child(const hier* H, int ch, const long rc[3], int ax, int dir, const double s[3],
+                        const double n[3], double r, long c[3]) {
+  const orc_grid* G = &H->g[ch];
+  for (int a = 0; a < 3; ++a) {
+    const long lo = 2 * (rc[a] - G->offset[a]);
+    if (a == ax) {
+      c[a] = lo + (dir < 0 ? 1 : 0);
+    } else {
+      const double x = s[a] + r * n[a];
+      long cl = cell_rule(2.0 * (x - (double)G->offset[a]), n[a]);
+      if (cl < lo) cl = lo;
+      if (cl > lo + 1) cl = lo + 1;
+      c[a] = cl;
+    }
+  }
+}
+
+/* Locate the leaf cell holding the point s + r n. Returns -1 outside the root. */
+static int locate(const hier* H, const double s[3], const double n[3], double r, int* q, long c[3]) {
+  const orc_grid* R = &H->g[0];
+  long rc[3];
+  double x[3];
+  for (int a = 0; a < 3; ++a) {
+    x[a] = s[a] + r * n[a];
+    rc[a] = cell_rule(x[a], n[a]);
+  }
+  if (!in_grid(R, rc)) return -1;
+  const int ch = H->cover[rc[0] + (long)R->nx * (rc[1] + (long)R->ny * rc[2])];
+  if (ch < 0) {
+    *q = 0;
+    c[0] = rc[0]; c[1] = rc[1]; c[2] = rc[2];
+    return 0;
+  }
+  const orc_grid* G = &H->g[ch];
+  for (int a = 0; a < 3; ++a) c[a] = cell_rule(2.0 * (x[a] - (double)G->offset[a]), n[a]);
+  *q = ch;
+  return 0;
+}
+
+typedef struct {
+  double* absorbed;
+  double* energy;
+  uint64_t segments, splits, seeded, n_escaped, n_truncated;
+} acc;
+
+typedef struct {
+  const hier* H;
+  const orc_source* src;
+  const orc_spectrum* spec;
+  const orc_params* par;
+  double four_pi_phi_c;
+} job;
+
+typedef struct { int level; uint64_t pix; double r, P, P0; } oray;
+
+/* Trace all seed rays of one (source, group) item, depth first. */
+static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* trunc) {
+  const hier* H = J->H;
+  const orc_source* S = &J->src[si];
+  const double s[3] = {S->x, S->y, S->z};
+  const double sigma = J->spec->sigma_cm2[gi];
+  const double eexc = (J->spec->energy_ev[gi] - J->spec->e_ion_ev) * EV_ERG;
+  const int l0 = J->par->level_init, lmax = J->par->level_max;
+  const uint64_t npix0 = (uint64_t)12 << (2 * l0);
+  const double P0 = J->spec->frac[gi] * S->ndot / (double)npix0;
+
+  oray stack[STACK_MAX];
+  for (uint64_t p0 = 0; p0 < npix0; ++p0) {
+    int sp = 0;
+    stack[sp++] = (oray){l0, p0, 0.0, P0, P0};
+    A->seeded++;
+    while (sp > 0) {
+      oray R = stack[--sp];
+    new_ray:;
+      double n[3];
+      orc_pix2vec_nest(R.level, R.pix, n);
+      int q;
+      long c[3];
+      if (locate(H, s, n, R.r, &q, c) < 0) {   /* starts outside the root grid */
+        cs_add(esc, R.P);
+        A->n_escaped++;
+        continue;
+      }
+      for (;;) {
+        const orc_grid* G = &H->g[q];
+        const double h = (q == 0) ? 1.0 : 2.0;
+        double sl[3];
+        for (int a = 0; a < 3; ++a) sl[a] = (q == 0) ? s[a] : h * (s[a] - (double)G->offset[a]);
+        /* exit distance (root-cell units) and exit axis */
+        double t_exit = INFINITY;
+        int ax = -1;
+        for (int a = 0; a < 3; ++a) {
+          if (n[a] == 0.0) continue;
+          const long b = (n[a] > 0.0) ? c[a] + 1 : c[a];
+          const double ta = (((double)b - sl[a]) / n[a]) / h;
+          if (ta < t_exit) { t_exit = ta; ax = a; }
+        }
+        /* split test at the exit radius, in units of the local cell */
+        if (R.level < lmax) {
+          const double u = t_exit * h;
+          if (ldexp(12.0, 2 * R.level) < J->four_pi_phi_c * (u * u)) {
+            A->splits++;
+            for (int k = 3; k >= 1; --k)
+              stack[sp++] = (oray){R.level + 1, 4 * R.pix + (uint64_t)k, R.r, 0.25 * R.P, 0.25 * R.P0};
+            R = (oray){R.level + 1, 4 * R.pix, R.r, 0.25 * R.P, 0.25 * R.P0};
+            goto new_ray;
+          }
+        }
+        const double dr = t_exit - R.r;
+        if (dr > 0.0) {
+          const size_t cell = (size_t)c[0] + (size_t)G->nx * ((size_t)c[1] + (size_t)G->ny * (size_t)c[2]);
+          const double nabs = (double)G->n_h[cell] * (double)G->x_hi[cell];
+          const double tau = sigma * nabs * ((dr * h) * G->dx_cm);
+          const double dP = R.P * (-expm1(-tau));
+          A->absorbed[H->cell_off[q] + cell] += dP;
+          A->energy[H->cell_off[q] + cell] += dP * eexc;
+          R.P -= dP;
+          A->segments++;
+          R.r = t_exit;
+        }
+        const int dir = (n[ax] > 0.0) ? 1 : -1;
+        c[ax] += dir;
+        if (R.P < J->par->p_min_frac * R.P0) {
+          cs_add(trunc, R.P);
+          A->n_truncated++;
+          break;
+        }
+        if (q == 0) {
+          if (!in_grid(G, c)) {
+            cs_add(esc, R.P);
+            A->n_escaped++;
+            break;
+          }
+          const int ch = H->cover[c[0] + (long)G->nx * (c[1] + (long)G->ny * c[2])];
+          if (ch >= 0) {
+            long rc[3] = {c[0], c[1], c[2]};
+            enter_child(H, ch, rc, ax, dir, s, n, R.r, c);
+            q = ch;
+          }
+        } else if (!in_grid(G, c)) {
+          long rc[3];
+          for (int a = 0; a < 3; ++a) rc[a] = (long)G->offset[a] + floor_half(c[a]);
+          const orc_grid* Rg = &H->g[0];
+          if (!in_grid(Rg, rc)) {
+            cs_add(esc, R.P);
+            A->n_escaped++;
+            break;
+          }
+          const int ch = H->cover[rc[0] + (long)Rg->nx * (rc[1] + (long)Rg->ny * rc[2])];
+          if (ch >= 0) {
+            enter_child(H, ch, rc, ax, dir, s, n, R.r, c);
+            q = ch;
+          } else {
+            q = 0;
+            c[0] = rc[0]; c[1] = rc[1]; c[2] = rc[2];
+          }
+        }
+      }
+    }
+  }
+}
+
+static int finite_nonneg(double x) { return isfinite(x) && x >= 0.0; }
+
+static int validate(const orc_grid* g, int ng, const orc_source* src, int ns, const orc_spectrum* sp,
+                    const orc_params* p) {
+  if (!g || ng < 1 || !sp || !p || ns < 0 || (ns > 0 && !src)) return -1;
+  if (g[0].parent != -1) return -1;
+  for (int q = 0; q < ng; ++q) {
+    const orc_grid* G = &g[q];
+    if (G->nx < 1 || G->ny < 1 || G->nz < 1 || !(G->dx_cm > 0.0) || !isfinite(G->dx_cm)) return -1;
+    if (!G->n_h || !G->x_hi) return -1;
+    const size_t nc = (size_t)G->nx * G->ny * G->nz;
+    for (size_t i = 0; i < nc; ++i) {
+      if (!finite_nonneg(G->n_h[i]) || !finite_nonneg(G->x_hi[i]) || G->x_hi[i] > 1.0f) return -1;
+    }
+    if (q > 0) {
+      if (G->parent != 0 || (G->nx & 1) || (G->ny & 1) || (G->nz & 1)) return -1;
+      if (G->dx_cm != 0.5 * g[0].dx_cm) return -1;
+      if (G->offset[0] < 0 || G->offset[1] < 0 || G->offset[2] < 0) return -1;
+      if (G->offset[0] + G->nx / 2 > g[0].nx || G->offset[1] + G->ny / 2 > g[0].ny ||
+          G->offset[2] + G->nz / 2 > g[0].nz)
+        return -1;
+    }
+  }
+  for (int i = 0; i < ns; ++i) {
+    const orc_source* S = &src[i];
+    if (!(S->x >= 0.0 && S->x < g[0].nx && S->y >= 0.0 && S->y < g[0].ny && S->z >= 0.0 && S->z < g[0].nz))
+      return -1;
+    if (!(S->ndot > 0.0) || !isfinite(S->ndot)) return -1;
+  }
+  if (sp->n_groups < 1 || !sp->energy_ev || !sp->sigma_cm2 || !sp->frac) return -1;
+  double fsum = 0.0;
+  for (int k = 0; k < sp->n_groups; ++k) {
+    if (!finite_nonneg(sp->sigma_cm2[k]) || !finite_nonneg(sp->frac[k])) return -1;
+    if (!(sp->energy_ev[k] >= sp->e_ion_ev) || !isfinite(sp->energy_ev[k])) return -1;
+    fsum += sp->frac[k];
+  }
+  if (fabs(fsum - 1.0) > 1e-12) return -1;
+  if (!finite_nonneg(p->phi_c) || p->level_init < 0 || p->level_init > p->level_max ||
+      p->level_max > MAX_LEVEL || !(p->p_min_frac >= 0.0 && p->p_min_frac < 1.0))
+    return -1;
+  return 0;
+}
+
+int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
+              const orc_params* par, int n_threads, double* absorbed, double* energy, double* k_ph,
+              double* heating, double* escaped_sg, orc_totals* tot) {
+  if (validate(grids, n_grids, src, n_src, spec, par) != 0) return -1;
+  if (!absorbed || !energy || !k_ph || !heating || !tot) return -1;
+  hier H;
+  H.g = grids;
+  H.n_grids = n_grids;
+  H.cell_off = (size_t*)malloc(sizeof(size_t) * (size_t)(n_grids + 1));
+  H.cell_off[0] = 0;
+  for (int q = 0; q < n_grids; ++q)
+    H.cell_off[q + 1] = H.cell_off[q] + (size_t)grids[q].nx * grids[q].ny * grids[q].nz;
+  H.n_cells = H.cell_off[n_grids];
+  const orc_grid* R = &grids[0];
+  const size_t nroot = (size_t)R->nx * R->ny * R->nz;
+  H.cover = (int*)malloc(sizeof(int) * nroot);
+  for (size_t i = 0; i < nroot; ++i) H.cover[i] = -1;
+  for (int q = 1; q < n_grids; ++q) {
+    const orc_grid* G = &grids[q];
+    for (int k = 0; k < G->nz / 2; ++k)
+      for (int j = 0; j < G->ny / 2; ++j)
+        for (int i = 0; i < G->nx / 2; ++i) {
+          const size_t rc = (size_t)(G->offset[0] + i) +
+                            (size_t)R->nx * ((size_t)(G->offset[1] + j) + (size_t)R->ny * (size_t)(G->offset[2] + k));
+          if (H.cover[rc] >= 0) { free(H.cover); free(H.cell_off); return -1; }   /* overlapping children */
+          H.cover[rc] = q;
+        }
+  }
+
+  job J = {&H, src, spec, par, 4.0 * PI_D * par->phi_c};
+  const int n_items = n_src * spec->n_groups;
+  int T = n_threads < 1 ? 1 : n_threads;
+  if (T > n_items && n_items > 0) T = n_items;
+  acc* A = (acc*)calloc((size_t)T, sizeof(acc));
+  for (int t = 0; t < T; ++t) {
+    A[t].absorbed = (double*)calloc(H.n_cells, sizeof(double));
+    A[t].energy = (double*)calloc(H.n_cells, sizeof(double));
+  }
+  csum* esc = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
+  csum* trn = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
+
+#ifdef _OPENMP
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+#else
+  for (int t = 0; t < T; ++t) {
+#endif
+    for (int it = t; it < n_items; it += T)
+      trace_item(&J, it / spec->n_groups, it % spec->n_groups, &A[t], &esc[it], &trn[it]);
+  }
+
+  memset(tot, 0, sizeof(*tot));
+  csum cem = {0, 0}, cab = {0, 0}, ces = {0, 0}, ctr = {0, 0};
+  for (int i = 0; i < n_src; ++i)
+    for (int k = 0; k < spec->n_groups; ++k) cs_add(&cem, spec->frac[k] * src[i].ndot);
+  for (int it = 0; it < n_items; ++it) {
+    cs_add(&ces, cs_get(&esc[it]));
+    cs_add(&ctr, cs_get(&trn[it]));
+    if (escaped_sg) escaped_sg[it] = cs_get(&esc[it]);
+  }
+  for (size_t i = 0; i < H.n_cells; ++i) {
+    double a = 0.0, e = 0.0;
+    for (int t = 0; t < T; ++t) { a += A[t].absorbed[i]; e += A[t].energy[i]; }
+    absorbed[i] = a;
+    energy[i] = e;
+    cs_add(&cab, a);
+  }
+  for (int t = 0; t < T; ++t) {
+    tot->segments += A[t].segments;
+    tot->splits += A[t].splits;
+    tot->rays_seeded += A[t].seeded;
+    tot->rays_escaped += A[t].n_escaped;
+    tot->rays_truncated += A[t].n_truncated;
+    free(A[t].absorbed);
+    free(A[t].energy);
+  }
+  tot->emitted = cs_get(&cem);
+  tot->absorbed = cs_get(&cab);
+  tot->escaped = cs_get(&ces);
+  tot->truncated = cs_get(&ctr);
+
+  /* k_ph and heating per absorber (Eqs. kph, gamma with dt_P cancelled) */
+  for (int q = 0; q < n_grids; ++q) {
+    const orc_grid* G = &grids[q];
+    const double vol = G->dx_cm * G->dx_cm * G->dx_cm;
+    const size_t nc = (size_t)G->nx * G->ny * G->nz;
+    for (size_t i = 0; i < nc; ++i) {
+      const double nabs = (double)G->n_h[i] * (double)G->x_hi[i];
+      const size_t o = H.cell_off[q] + i;
+      if (nabs > 0.0) {
+        k_ph[o] = absorbed[o] / (nabs * vol);
+        heating[o] = energy[o] / (nabs * vol);
+      } else {
+        k_ph[o] = 0.0;
+        heating[o] = 0.0;
+      }
+    }
+  }
+  free(A);
+  free(esc);
+  free(trn);
+  free(H.cover);
+  free(H.cell_off);
+  return 0;
+}

@@ -1,0 +1,76 @@
+/*
+ * moray_oracle.h -- plain FP64 CPU reference of the single-pass adaptive ray
+ * trace (Wise & Abel, Enzo+Moray: section 2.1 adaptive ray tracing, section
+ * 2.2 radiation field, section 3.1 steps 1-3).
+ *
+ * TEST INFRASTRUCTURE ONLY. This library exists to check the GPU library
+ * against. Only the test-suite, the smoke check and the benchmark's CPU
+ * baseline may call it; the product path never links or loads it. It shares
+ * no code, header, table or helper with the GPU library.
+ *
+ * Units: positions and radii in cells of the root grid; dx in cm; densities
+ * in cm^-3; photon rates in photons/s; energies in eV on input, erg on output.
+ * Fields are float32, x fastest (index i + nx*(j + ny*k)).
+ */
+#ifndef MORAY_ORACLE_H
+#define MORAY_ORACLE_H
+#include <stdint.h>
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  int nx, ny, nz;          /* cells */
+  double dx_cm;            /* cell width */
+  const float* n_h;        /* hydrogen density */
+  const float* x_hi;       /* neutral fraction */
+  int parent;              /* -1 root, 0 child of the root (refinement 2) */
+  int offset[3];           /* lower corner in root cells (children only) */
+} orc_grid;
+
+typedef struct { double x, y, z, ndot; } orc_source;   /* root cells; photons/s */
+
+typedef struct {
+  int n_groups;
+  const double* energy_ev;
+  const double* sigma_cm2;
+  const double* frac;      /* photon-number fraction of each group */
+  double e_ion_ev;
+} orc_spectrum;
+
+typedef struct {
+  double phi_c;            /* split when fewer than phi_c rays cross a cell face */
+  int level_init;          /* HEALPix level of the seed rays */
+  int level_max;           /* rays at this level are never split */
+  double p_min_frac;       /* a ray ends once P < p_min_frac * P0 */
+} orc_params;
+
+typedef struct {
+  double emitted, absorbed, escaped, truncated;       /* photons/s, compensated sums */
+  uint64_t segments, rays_seeded, splits, rays_escaped, rays_truncated;
+} orc_totals;
+
+/* Trace every (source, group, seed pixel) ray tree of one problem.
+ * Outputs (caller-allocated, concatenated over grids in grid order, every one
+ * overwritten): absorbed [photons/s per cell], energy [erg/s per cell], k_ph
+ * [1/s per absorber], heating [erg/s per absorber]; escaped_sg
+ * [n_src*n_groups] escaped photons/s per (source, group) (may be NULL).
+ * n_threads > 1 splits (source, group) items cyclically over OpenMP threads,
+ * each with private accumulators summed in thread order.
+ * Returns 0, or -1 on invalid input (nothing written). */
+int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_src,
+              const orc_spectrum* spec, const orc_params* par, int n_threads,
+              double* absorbed, double* energy, double* k_ph, double* heating,
+              double* escaped_sg, orc_totals* tot);
+
+/* HEALPix nested-scheme pixel centre as a unit vector (z = polar axis,
+ * phi = 0 along +x). */
+void orc_pix2vec_nest(int level, uint64_t pix, double v[3]);
+
+/* Constants the oracle uses (for the unit pins). */
+double orc_const_ev_erg(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

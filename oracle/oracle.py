@@ -1,0 +1,154 @@
+"""ctypes front end of the plain FP64 CPU oracle (moray_oracle.c).
+
+TEST INFRASTRUCTURE ONLY: the tests, the smoke check and the benchmark's CPU
+baseline call this to check the GPU library against; the product path never
+imports it. It imports nothing from the GPU package: a problem is any object
+with the attributes ``grids`` (each with ``n_h``, ``x_hi``, ``dx_cm``,
+``parent``, ``offset``), ``sources`` (S x 4: x, y, z in root cells, ndot),
+``spectrum`` (``energy_ev``, ``sigma_cm2``, ``frac``, ``e_ion_ev``) and
+``params`` (``phi_c``, ``level_init``, ``level_max``, ``p_min_frac``).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "moray_oracle.c")
+_LIB_PATH = os.environ.get("MORAY_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB_PATH):
+        tmp = _LIB_PATH + ".tmp"
+        subprocess.check_call(["gcc", "-std=c11", "-O2", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+                               "-fno-fast-math", "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"])
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+class _Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx_cm", ctypes.c_double),
+                ("n_h", ctypes.POINTER(ctypes.c_float)), ("x_hi", ctypes.POINTER(ctypes.c_float)),
+                ("parent", ctypes.c_int), ("offset", ctypes.c_int * 3)]
+
+
+class _Source(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double), ("ndot", ctypes.c_double)]
+
+
+class _Spectrum(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int), ("energy_ev", ctypes.POINTER(ctypes.c_double)),
+                ("sigma_cm2", ctypes.POINTER(ctypes.c_double)), ("frac", ctypes.POINTER(ctypes.c_double)),
+                ("e_ion_ev", ctypes.c_double)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("phi_c", ctypes.c_double), ("level_init", ctypes.c_int), ("level_max", ctypes.c_int),
+                ("p_min_frac", ctypes.c_double)]
+
+
+class _Totals(ctypes.Structure):
+    _fields_ = [("emitted", ctypes.c_double), ("absorbed", ctypes.c_double), ("escaped", ctypes.c_double),
+                ("truncated", ctypes.c_double), ("segments", ctypes.c_uint64), ("rays_seeded", ctypes.c_uint64),
+                ("splits", ctypes.c_uint64), ("rays_escaped", ctypes.c_uint64), ("rays_truncated", ctypes.c_uint64)]
+
+
+_lib = None
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB_PATH):
+            build()
+        lib = ctypes.CDLL(_LIB_PATH)
+        dp = ctypes.POINTER(ctypes.c_double)
+        lib.orc_trace.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.POINTER(_Source), ctypes.c_int,
+                                  ctypes.POINTER(_Spectrum), ctypes.POINTER(_Params), ctypes.c_int,
+                                  dp, dp, dp, dp, dp, ctypes.POINTER(_Totals)]
+        lib.orc_trace.restype = ctypes.c_int
+        lib.orc_pix2vec_nest.argtypes = [ctypes.c_int, ctypes.c_uint64, dp]
+        lib.orc_pix2vec_nest.restype = None
+        lib.orc_const_ev_erg.restype = ctypes.c_double
+        _lib = lib
+    return _lib
+
+
+def ev_erg() -> float:
+    return _load().orc_const_ev_erg()
+
+
+def pix2vec(level: int, pix: int) -> np.ndarray:
+    v = np.zeros(3)
+    _load().orc_pix2vec_nest(int(level), int(pix), v.ctypes.data_as(ctypes.POINTER(ctypes.c_double)))
+    return v
+
+
+def pix2vec_all(level: int) -> np.ndarray:
+    return np.array([pix2vec(level, p) for p in range(12 * 4 ** level)])
+
+
+class OracleError(ValueError):
+    pass
+
+
+def trace(problem, n_threads: int = 1) -> dict:
+    """Run the oracle on one problem; returns per-grid fields and totals."""
+    lib = _load()
+    keep = []
+    grids = (_Grid * len(problem.grids))()
+    for q, g in enumerate(problem.grids):
+        n_h = np.ascontiguousarray(g.n_h, dtype=np.float32)
+        x_hi = np.ascontiguousarray(g.x_hi, dtype=np.float32)
+        keep += [n_h, x_hi]
+        nz, ny, nx = n_h.shape
+        grids[q].nx, grids[q].ny, grids[q].nz = nx, ny, nz
+        grids[q].dx_cm = float(g.dx_cm)
+        grids[q].n_h = n_h.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        grids[q].x_hi = x_hi.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        grids[q].parent = int(g.parent)
+        for a in range(3):
+            grids[q].offset[a] = int(g.offset[a])
+    S = np.asarray(problem.sources, dtype=np.float64).reshape(-1, 4)
+    srcs = (_Source * max(1, len(S)))()
+    for i, row in enumerate(S):
+        srcs[i].x, srcs[i].y, srcs[i].z, srcs[i].ndot = (float(v) for v in row)
+    sp = problem.spectrum
+    e = np.ascontiguousarray(sp.energy_ev, dtype=np.float64)
+    sg = np.ascontiguousarray(sp.sigma_cm2, dtype=np.float64)
+    fr = np.ascontiguousarray(sp.frac, dtype=np.float64)
+    keep += [e, sg, fr]
+    dp = ctypes.POINTER(ctypes.c_double)
+    spec = _Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
+    pr = problem.params
+    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac))
+    n_cells = sum(int(np.asarray(g.n_h).size) for g in problem.grids)
+    absorbed = np.zeros(n_cells)
+    energy = np.zeros(n_cells)
+    k_ph = np.zeros(n_cells)
+    heating = np.zeros(n_cells)
+    esc = np.zeros(max(1, len(S) * len(e)))
+    tot = _Totals()
+    rc = lib.orc_trace(grids, len(problem.grids), srcs, len(S), ctypes.byref(spec), ctypes.byref(par),
+                       int(n_threads), absorbed.ctypes.data_as(dp), energy.ctypes.data_as(dp),
+                       k_ph.ctypes.data_as(dp), heating.ctypes.data_as(dp), esc.ctypes.data_as(dp),
+                       ctypes.byref(tot))
+    if rc != 0:
+        raise OracleError("oracle rejected the problem")
+
+    def split(a):
+        out, o = [], 0
+        for g in problem.grids:
+            n = int(np.asarray(g.n_h).size)
+            out.append(a[o:o + n].reshape(np.asarray(g.n_h).shape))
+            o += n
+        return out
+
+    totals = {name: getattr(tot, name) for name, _ in _Totals._fields_}
+    return {"absorbed": split(absorbed), "energy": split(energy), "k_ph": split(k_ph), "heating": split(heating),
+            "escaped_sg": esc[:len(S) * len(e)].reshape(len(S), len(e)), "totals": totals}
