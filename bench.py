@@ -1,0 +1,171 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the adaptive ray tracer on one MI355X.
+
+A step is one full single-pass trace (absorber columns, seeding, every
+HEALPix level's march/split/deposit, finalize) of one synthetic workload whose
+fields are already resident in HBM. `value` is ray-cell segments per second
+of the float32-geometry / float64-accumulate path over the timed steps
+(wall clock around the steps, including the host-side planning and the
+result read-back of each call). The plain float64 path on the same input is
+reported beside it.
+
+  python bench.py [--steps K] [--warmup W] [--workload c1|c2]
+
+Prints one JSON line.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "ray-cell segments/s on 1 MI355X (batched FP32 vs plain FP64); p50/p99 solve latency"
+HBM_PEAK_GBS = 8000.0
+BYTES_PER_SEGMENT = {"fp32": 36, "fp64": 40}     # absorber read + two float64 read-modify-writes
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_level.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1012_2865_amd", "csrc", "moray_kernels.hip")
+
+
+def _workload(name):
+    from paper_1012_2865_amd import workloads as W
+    if name == "c1":
+        return [W.config1()], {"workload": "lognormal128_16src_4grp", "grid": "128^3", "box_kpc": 2.0,
+                               "sources": 16, "groups": [13.6, 20.0, 30.0, 60.0], "phi_c": 5.1,
+                               "level_init": 1, "level_max": 14, "p_min_frac": 1e-8}
+    if name == "c2":
+        probs = W.config2(64)
+        return probs, {"workload": "batched64_lognormal_32-96", "problems": 64,
+                       "cells": int(sum(p.n_cells for p in probs)),
+                       "sources": int(sum(p.n_sources for p in probs)), "groups": [13.6, 20.0, 30.0, 60.0],
+                       "phi_c": 5.1, "level_init": 1, "level_max": 14, "p_min_frac": 1e-8}
+    raise ValueError(name)
+
+
+def _time_steps(M, ctx, dev, steps, warmup):
+    import torch
+    res = None
+    for _ in range(warmup):
+        res = M.moray_trace(ctx, dev)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = M.moray_trace(ctx, dev)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    segs = sum(r["segments"] for r in res)
+    return dt / steps, segs, res
+
+
+def _kernel_time(M, precision, dev, reps=3):
+    """Summed trace-kernel device time per step, measured with HIP events on
+    the library's stream."""
+    ctx = M.moray_init(device=0, precision=precision, profile=True)
+    try:
+        M.moray_trace(ctx, dev)
+        ms, launches, segs = 0.0, 0, 0
+        for _ in range(reps):
+            res = M.moray_trace(ctx, dev)
+            ms += res[0]["trace_ms"]
+            launches += res[0]["trace_launches"]
+            segs += sum(r["segments"] for r in res)
+        return ms / reps, launches / reps, segs / reps
+    finally:
+        M.moray_free(ctx)
+
+
+def _traffic(workload, precision):
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    key = f"{workload}/{precision}"
+    if rec.get("kernel_sha256") != sha or key not in rec.get("per_launch_bytes", {}):
+        return None
+    return rec["per_launch_bytes"][key]
+
+
+def _cpu_baseline(problems, threads):
+    from oracle import oracle as O
+    t0 = time.perf_counter()
+    segs = 0
+    for p in problems:
+        segs += O.trace(p, n_threads=threads)["totals"]["segments"]
+    dt = time.perf_counter() - t0
+    return segs / dt, dt, segs
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", choices=["c1", "c2"], default="c1")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("MORAY_CPU_THREADS", "16")))
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only (this tracer shards by request or by source; "
+              f"--gpus {args.gpus} is not supported)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1012_2865_amd import moray as M
+
+    problems, config = _workload(args.workload)
+    dev = [M.problem_to_device(p) for p in problems]
+    torch.cuda.synchronize()
+    print(f"# workload {config['workload']} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
+
+    ctx32 = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        s32, seg32, res32 = _time_steps(M, ctx32, dev, args.steps, args.warmup)
+    finally:
+        M.moray_free(ctx32)
+    print(f"# fp32: {s32 * 1e3:.2f} ms/step, {seg32} segments", file=sys.stderr, flush=True)
+    plain = None
+    if not args.no_fp64:
+        ctx64 = M.moray_init(device=0, precision=M.MORAY_FP64)
+        try:
+            s64, seg64, _ = _time_steps(M, ctx64, dev, max(1, args.steps // 2), 1)
+        finally:
+            M.moray_free(ctx64)
+        plain = {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3, "segments": seg64,
+                 "dtype": "f64", "form": "one solve per call, no graph"}
+        print(f"# fp64: {s64 * 1e3:.2f} ms/step, {seg64} segments", file=sys.stderr, flush=True)
+
+    kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, dev)
+    algo_bytes = BYTES_PER_SEGMENT["fp32"] * ksegs
+    achieved = algo_bytes / (kms * 1e-3) / 1e9
+    traffic = _traffic(args.workload, "fp32")
+    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                "kernel": "trace_level_kernel<float>", "launches_per_step": launches,
+                "avg_launch_ms": kms / launches if launches else None,
+                "algorithmic_bytes_per_launch": algo_bytes / launches if launches else None}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+        sample = problems if args.workload == "c1" else problems[:8]
+        v, dt, segs = _cpu_baseline(sample, threads)
+        cpu = {"value": v, "unit": "segments/s", "cores": threads, "kind": "oracle",
+               "sample": f"{'full workload' if args.workload == 'c1' else 'first 8 of 64 problems'}: "
+                         f"{segs} segments in {dt:.1f} s"}
+
+    out = {"metric": METRIC, "value": seg32 / s32, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": s32 * 1e3, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32+f64acc", "data": "synthetic", "config": config,
+           "segments_per_step": seg32, "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,158 @@
+/*
+ * moray.h -- C ABI of the MI355X adaptive ray tracer.
+ *
+ * The library computes one radiative-transfer pass of photon-conserving
+ * adaptive ray tracing from point sources (Wise & Abel, Enzo+Moray):
+ *   - rays start on the centres of the HEALPix nested pixels of level
+ *     `level_init` around every source, one ray set per energy group, the
+ *     group's photon rate shared equally (section 2.1);
+ *   - each ray marches cell by cell (Eq. trace) and deposits
+ *     dP = P (1 - exp(-tau)), tau = sigma n_H x_HI dr (Eqs. dtau, flux), into
+ *     the cell's photo-ionisation rate k_ph and photo-heating rate
+ *     (Eqs. kph, gamma: k_ph = sum dP / (n_H x_HI V_cell),
+ *     heating = sum dP (E - E_ion) / (n_H x_HI V_cell));
+ *   - a ray whose solid angle at its cell exit exceeds 1/phi_c of a cell face
+ *     (12 * 4^l < 4 pi phi_c t_exit^2 in local cell units, Eq. split and
+ *     step 3e of section 3.1) is replaced by its four nested children
+ *     4p..4p+3, which keep its radius and take a quarter of its photons each;
+ *   - a ray ends when P < p_min_frac * P0 (P0: its unattenuated share) or when
+ *     it leaves the root grid (isolated boundaries, section 2.1);
+ *   - a ray entering a root cell covered by a 2x-refined child grid continues
+ *     in the child (section 3.1 step 3c) and returns to the root on leaving it.
+ * The pass is single-shot (infinite speed of light), so P is a photon rate
+ * and the timestep of Eq. kph cancels: k_ph is in 1/s, heating in erg/s, per
+ * absorber.
+ *
+ * Conventions: fields are float32, x fastest (cell i + nx*(j + ny*k)).
+ * Source positions are in cells of the root grid, measured from its lower
+ * corner. Outputs are float64, concatenated over a problem's grids in grid
+ * order; root cells covered by a child grid report 0.
+ *
+ * Every function returns a moray_status (0 = MORAY_OK); no exception crosses
+ * the ABI. On any error moray_last_error() describes it. A context is used by
+ * one host thread at a time.
+ */
+#ifndef MORAY_H
+#define MORAY_H
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MORAY_OK = 0,
+  MORAY_EINVAL = -1,     /* invalid argument or input value; outputs untouched */
+  MORAY_ENOMEM = -2,     /* device memory or the context's HBM budget exhausted */
+  MORAY_EDEVICE = -3,    /* no usable GPU, or a HIP runtime call failed */
+  MORAY_EQUEUE = -4,     /* ray queue overflowed even after automatic retries */
+  MORAY_EBUSY = -5,      /* an asynchronous solve has not finished yet */
+  MORAY_EINTERNAL = -7   /* a device-side consistency check failed */
+} moray_status;
+
+typedef enum {
+  MORAY_FP64 = 0,        /* geometry, optical depth and accumulation in float64 */
+  MORAY_FP32_ACC64 = 1   /* geometry and optical depth in float32; photon counts,
+                            accumulators and split decisions near their threshold
+                            in float64 */
+} moray_precision;
+
+/* flags of moray_trace */
+#define MORAY_FIELDS_ON_DEVICE 1u   /* n_h / x_hi pointers are device memory */
+#define MORAY_OUT_ON_DEVICE 2u      /* k_ph / heating pointers are device memory */
+
+typedef struct moray_ctx moray_ctx;
+
+typedef struct {
+  int device;                 /* HIP device ordinal */
+  int precision;              /* moray_precision */
+  size_t hbm_budget_bytes;    /* cap on the context's device memory; 0 = half of the free memory */
+  size_t queue_capacity;      /* rays per level buffer; 0 = sized from each problem's worst case */
+  int waves_per_cu;           /* persistent trace waves per compute unit; 0 = default */
+  int refill_lanes;           /* a wave refetches rays once this many of its 64 lanes are idle; 0 = default */
+  int chunk_rays;             /* rays a wave claims from the level queue per atomic; 0 = default */
+  void* hip_stream;           /* hipStream_t for every launch; NULL = the null stream */
+  int profile;                /* nonzero: time every trace-kernel launch with HIP events */
+} moray_init_params;
+
+typedef struct {
+  double x, y, z;             /* position in root-grid cells, inside [0, n) per axis */
+  double ndot;                /* ionising photon rate, photons/s, > 0 */
+} moray_source;
+
+typedef struct {
+  int n_groups;               /* >= 1 monochromatic groups (section 3.2) */
+  const double* energy_ev;    /* [n_groups] photon energy, >= e_ion_ev */
+  const double* sigma_cm2;    /* [n_groups] absorption cross-section, >= 0 */
+  const double* photon_frac;  /* [n_groups] share of each source's photons, >= 0, sum 1 +- 1e-12 */
+  double e_ion_ev;            /* ionisation energy of the absorber (13.6 for HI) */
+} moray_spectrum;             /* host memory */
+
+typedef struct {
+  int nx, ny, nz;             /* cells */
+  double dx_cm;               /* cell width; a child's is exactly half the root's */
+  int parent;                 /* -1 for the root (grid 0), 0 for a child of the root */
+  int offset[3];              /* child: lower corner in root cells; its nx/2 x ny/2 x nz/2
+                                 root cells must lie inside the root and not overlap another child */
+  const float* n_h;           /* [nx*ny*nz] hydrogen density, cm^-3, finite, >= 0 */
+  const float* x_hi;          /* [nx*ny*nz] neutral fraction, in [0, 1] */
+} moray_grid;
+
+typedef struct {
+  double phi_c;               /* rays per cell face below which a ray splits; 0 = never split */
+  int level_init;             /* HEALPix level of the seed rays, 0 <= level_init <= level_max */
+  int level_max;              /* rays at this level never split, <= 29 */
+  double p_min_frac;          /* a ray ends once P < p_min_frac * P0, in [0, 1) */
+} moray_trace_params;
+
+typedef struct {
+  const moray_grid* grids;    /* [n_grids], grid 0 is the root */
+  int n_grids;
+  const moray_source* sources;/* [n_sources], host memory */
+  int n_sources;
+  const moray_spectrum* spectrum;
+  moray_trace_params params;
+} moray_problem;
+
+typedef struct {
+  double* k_ph;               /* [total cells] caller-owned output, 1/s per absorber */
+  double* heating;            /* [total cells] caller-owned output, erg/s per absorber */
+  double* escaped_sg;         /* optional host [n_sources*n_groups] escaped photons/s, or NULL */
+  /* filled by the library: */
+  double emitted;             /* sum over sources and groups of the photon rate */
+  double absorbed;            /* sum over cells of the absorbed photon rate */
+  double escaped;             /* photon rate leaving the root grid */
+  double truncated;           /* photon rate left in rays ended by p_min_frac */
+  unsigned long long segments;        /* (ray, cell) crossings with dr > 0 that deposited */
+  unsigned long long rays_seeded, splits, rays_escaped, rays_truncated;
+  unsigned long long peak_level_rays; /* largest level population of this solve's ray queue */
+  double trace_ms;            /* summed trace-kernel device time of the call (profile only) */
+  int trace_launches;         /* trace-kernel launches of the call */
+} moray_result;
+
+/* Create a context on params->device. Returns MORAY_EDEVICE when no GPU is
+ * visible or the device cannot be used, MORAY_EINVAL for bad parameters.
+ * *ctx is NULL on failure. */
+moray_status moray_init(moray_ctx** ctx, const moray_init_params* params);
+
+/* Trace n_probs independent problems in one batched pass (n_probs >= 1), all
+ * of them through the same launch sequence. Inputs are read-only and must stay
+ * valid until the call returns; outputs are written only on success (on
+ * MORAY_EINVAL they are untouched, on device-side errors their content is
+ * undefined). Blocks until the results are complete. */
+moray_status moray_trace(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
+                         moray_result* outs);
+
+/* Release every device and host resource of the context (NULL is allowed). */
+void moray_free(moray_ctx* ctx);
+
+/* Description of the last error on this context (never NULL). */
+const char* moray_last_error(const moray_ctx* ctx);
+
+/* Library version as "major.minor.patch". */
+const char* moray_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,597 @@
+// Host runtime of the adaptive ray tracer: the C ABI declared in moray.h.
+//
+// A call validates the problems on the host, lays every problem of the batch
+// out in one cell numbering (grid, problem and (source, group) tables), sizes
+// the ping-pong ray queue from a geometric bound on the rays one HEALPix level
+// can hold, and enqueues reset -> prep -> trace_level(l0..l_reach) -> finalize
+// on the context's stream. Trees whose queue estimate exceeds the capacity
+// are traced in chunks sharing the same accumulators; a device overflow flag
+// triggers a retry with smaller chunks.
+#include "moray.h"
+#include "moray_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+namespace moray {
+hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int, double*, int);
+hipError_t launch_reset_levels(hipStream_t, Counters*);
+template <typename R>
+hipError_t launch_prep(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, R*, double*, double*,
+                       Counters*);
+template <typename R>
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&);
+hipError_t launch_finalize(hipStream_t, int, const GridDev*, int, long long, const double*, const double*, double*,
+                           const Counters*);
+hipError_t trace_occupancy(int precision, int* blocks_per_cu);
+}  // namespace moray
+
+using namespace moray;
+
+namespace {
+
+constexpr double kEvErg = 1.602176634e-12;
+constexpr double kPi = 3.14159265358979323846;
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct ChunkPlan {
+  int sg_begin, sg_end;
+};
+
+}  // namespace
+
+struct moray_ctx {
+  int device = 0;
+  int precision = MORAY_FP32_ACC64;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t queue_cap_user = 0;
+  int waves_per_cu = 0, refill = 0, chunk = 0, profile = 0;
+  int num_cu = 0;
+  int blocks_per_cu = 1;
+  std::string err = "no error";
+  size_t allocated = 0;
+  DevBuf grids, probs, sgs, stats, ctr, kappa, acc_abs, acc_heat, prob_abs, fields, outs;
+  DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
+  size_t q_cap = 0;
+  void* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  std::vector<hipEvent_t> evs;
+};
+
+namespace {
+
+moray_status fail(moray_ctx* c, moray_status s, const std::string& msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+bool hip_ok(moray_ctx* c, hipError_t e, const char* what) {
+  if (e == hipSuccess) return true;
+  c->err = std::string(what) + ": " + hipGetErrorString(e);
+  return false;
+}
+
+void release(moray_ctx* c, DevBuf& b) {
+  if (b.p) {
+    (void)hipFree(b.p);
+    c->allocated -= b.bytes;
+  }
+  b.p = nullptr;
+  b.bytes = 0;
+}
+
+// Grow-only device buffer inside the context's HBM budget.
+moray_status ensure(moray_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (bytes <= b.bytes) return MORAY_OK;
+  bytes = (bytes + 255) & ~size_t(255);
+  if (c->allocated - b.bytes + bytes > c->budget)
+    return fail(c, MORAY_ENOMEM, std::string("HBM budget exceeded allocating ") + what);
+  release(c, b);
+  if (hipMalloc(&b.p, bytes) != hipSuccess) {
+    b.p = nullptr;
+    return fail(c, MORAY_ENOMEM, std::string("hipMalloc failed for ") + what);
+  }
+  b.bytes = bytes;
+  c->allocated += bytes;
+  return MORAY_OK;
+}
+
+bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+
+// Host-side checks of everything except field values (checked on the device).
+moray_status validate(moray_ctx* c, const moray_problem& P, int pi) {
+  char buf[256];
+  auto bad = [&](const char* m) {
+    std::snprintf(buf, sizeof buf, "problem %d: %s", pi, m);
+    return fail(c, MORAY_EINVAL, buf);
+  };
+  if (!P.grids || P.n_grids < 1) return bad("needs at least one grid");
+  if (!P.spectrum) return bad("spectrum is NULL");
+  if (P.n_sources < 0 || (P.n_sources > 0 && !P.sources)) return bad("bad source list");
+  const moray_grid& R = P.grids[0];
+  if (R.parent != -1) return bad("grid 0 must be the root (parent -1)");
+  for (int q = 0; q < P.n_grids; ++q) {
+    const moray_grid& G = P.grids[q];
+    if (G.nx < 1 || G.ny < 1 || G.nz < 1) return bad("grid dimensions must be positive");
+    if (!(G.dx_cm > 0.0) || !std::isfinite(G.dx_cm)) return bad("dx_cm must be positive and finite");
+    if (!G.n_h || !G.x_hi) return bad("field pointer is NULL");
+    if ((double)G.nx * G.ny * G.nz > 1.0e9) return bad("grid too large");
+    if (q > 0) {
+      if (G.parent != 0) return bad("only children of the root grid are supported");
+      if ((G.nx | G.ny | G.nz) & 1) return bad("child dimensions must be even");
+      if (G.dx_cm != 0.5 * R.dx_cm) return bad("child cell width must be half the root's");
+      if (G.offset[0] < 0 || G.offset[1] < 0 || G.offset[2] < 0 || G.offset[0] + G.nx / 2 > R.nx ||
+          G.offset[1] + G.ny / 2 > R.ny || G.offset[2] + G.nz / 2 > R.nz)
+        return bad("child grid not inside the root");
+      for (int o = 1; o < q; ++o) {
+        const moray_grid& H = P.grids[o];
+        bool sep = false;
+        const int lo1[3] = {G.offset[0], G.offset[1], G.offset[2]};
+        const int hi1[3] = {G.offset[0] + G.nx / 2, G.offset[1] + G.ny / 2, G.offset[2] + G.nz / 2};
+        const int lo2[3] = {H.offset[0], H.offset[1], H.offset[2]};
+        const int hi2[3] = {H.offset[0] + H.nx / 2, H.offset[1] + H.ny / 2, H.offset[2] + H.nz / 2};
+        for (int k = 0; k < 3; ++k) sep = sep || hi1[k] <= lo2[k] || hi2[k] <= lo1[k];
+        if (!sep) return bad("child grids overlap");
+      }
+    }
+  }
+  for (int s = 0; s < P.n_sources; ++s) {
+    const moray_source& S = P.sources[s];
+    if (!(S.x >= 0.0 && S.x < R.nx && S.y >= 0.0 && S.y < R.ny && S.z >= 0.0 && S.z < R.nz))
+      return bad("source outside the root grid");
+    if (!(S.ndot > 0.0) || !std::isfinite(S.ndot)) return bad("source rate must be positive and finite");
+  }
+  const moray_spectrum& Sp = *P.spectrum;
+  if (Sp.n_groups < 1 || !Sp.energy_ev || !Sp.sigma_cm2 || !Sp.photon_frac) return bad("bad spectrum");
+  if (!std::isfinite(Sp.e_ion_ev) || Sp.e_ion_ev < 0.0) return bad("bad ionisation energy");
+  double fs = 0.0;
+  for (int g = 0; g < Sp.n_groups; ++g) {
+    if (!finite_nonneg(Sp.sigma_cm2[g]) || !finite_nonneg(Sp.photon_frac[g])) return bad("bad group");
+    if (!(Sp.energy_ev[g] >= Sp.e_ion_ev) || !std::isfinite(Sp.energy_ev[g]))
+      return bad("group energy below the ionisation energy");
+    fs += Sp.photon_frac[g];
+  }
+  if (std::fabs(fs - 1.0) > 1e-12) return bad("photon fractions must sum to 1");
+  const moray_trace_params& T = P.params;
+  if (!finite_nonneg(T.phi_c)) return bad("phi_c must be finite and >= 0");
+  if (T.level_init < 0 || T.level_init > T.level_max || T.level_max > kMaxLevel)
+    return bad("need 0 <= level_init <= level_max <= 29");
+  if (!(T.p_min_frac >= 0.0 && T.p_min_frac < 1.0)) return bad("p_min_frac must be in [0, 1)");
+  return MORAY_OK;
+}
+
+// Highest level that can hold rays: rays of level l exist only if a level l-1
+// ray split, which needs 12 * 4^(l-1) < 4 pi phi_c u^2 with u at most the
+// largest distance inside the problem in local cells.
+int reach_level(const moray_problem& P) {
+  const moray_trace_params& T = P.params;
+  if (T.phi_c <= 0.0) return T.level_init;
+  const moray_grid& R = P.grids[0];
+  double umax = std::sqrt((double)R.nx * R.nx + (double)R.ny * R.ny + (double)R.nz * R.nz) + 2.0;
+  if (P.n_grids > 1) umax *= 2.0;
+  const double k = 4.0 * kPi * T.phi_c * umax * umax;
+  int l = T.level_init;
+  while (l < T.level_max && std::ldexp(12.0, 2 * l) < k) ++l;
+  return l;
+}
+
+// Upper estimate of the rays one level of one (source, group) tree can hold:
+// children are created at ray densities of at most ~4 phi_c per local cell
+// face, on a sphere whose part inside a grid is bounded by the grid's surface.
+double level_rays_bound(const moray_problem& P) {
+  const int lr = reach_level(P);
+  double area = 0.0;
+  for (int q = 0; q < P.n_grids; ++q) {
+    const moray_grid& G = P.grids[q];
+    area += 2.0 * ((double)G.nx * G.ny + (double)G.ny * G.nz + (double)G.nz * G.nx);
+  }
+  const double geo = 5.0 * std::max(P.params.phi_c, 1.0) * area + 256.0;
+  return std::min(std::ldexp(12.0, 2 * lr), geo);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* moray_version(void) { return "0.1.0"; }
+
+const char* moray_last_error(const moray_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+
+moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
+  if (!out) return MORAY_EINVAL;
+  *out = nullptr;
+  if (!p) return MORAY_EINVAL;
+  if (p->precision != MORAY_FP64 && p->precision != MORAY_FP32_ACC64) return MORAY_EINVAL;
+  if (p->waves_per_cu < 0 || p->refill_lanes < 0 || p->refill_lanes > kWave || p->chunk_rays < 0) return MORAY_EINVAL;
+  int n = 0;
+  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return MORAY_EDEVICE;
+  if (p->device < 0 || p->device >= n) return MORAY_EINVAL;
+  if (hipSetDevice(p->device) != hipSuccess) return MORAY_EDEVICE;
+  moray_ctx* c = new moray_ctx();
+  c->device = p->device;
+  c->precision = p->precision;
+  c->stream = (hipStream_t)p->hip_stream;
+  c->queue_cap_user = p->queue_capacity;
+  c->profile = p->profile;
+  c->refill = p->refill_lanes ? p->refill_lanes : 16;
+  c->chunk = p->chunk_rays ? p->chunk_rays : 256;
+  if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+      c->num_cu < 1) {
+    delete c;
+    return MORAY_EDEVICE;
+  }
+  int bpc = 1;
+  if (trace_occupancy(c->precision, &bpc) != hipSuccess || bpc < 1) bpc = 1;
+  c->blocks_per_cu = bpc;
+  if (p->waves_per_cu) {
+    const int want = std::max(1, p->waves_per_cu / (kTraceBlock / kWave));
+    c->blocks_per_cu = std::min(want, bpc);
+  }
+  size_t free_b = 0, total_b = 0;
+  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+    delete c;
+    return MORAY_EDEVICE;
+  }
+  c->budget = p->hbm_budget_bytes ? p->hbm_budget_bytes : free_b / 2;
+  if (hipHostMalloc(&c->h_stage, 1 << 20, hipHostMallocDefault) != hipSuccess) {
+    delete c;
+    return MORAY_EDEVICE;
+  }
+  c->h_stage_bytes = 1 << 20;
+  *out = c;
+  return MORAY_OK;
+}
+
+void moray_free(moray_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  DevBuf* all[] = {&c->grids, &c->probs, &c->sgs, &c->stats, &c->ctr, &c->kappa, &c->acc_abs, &c->acc_heat,
+                   &c->prob_abs, &c->fields, &c->outs};
+  for (DevBuf* b : all) release(c, *b);
+  for (int i = 0; i < 2; ++i) {
+    release(c, c->q_pix[i]);
+    release(c, c->q_sg[i]);
+    release(c, c->q_r[i]);
+    release(c, c->q_P[i]);
+  }
+  for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
+  if (c->h_stage) (void)hipHostFree(c->h_stage);
+  delete c;
+}
+
+moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, moray_result* outs) {
+  if (!c) return MORAY_EINVAL;
+  if (!probs || n_probs < 1 || !outs) return fail(c, MORAY_EINVAL, "need n_probs >= 1 problems and results");
+  if (flags & ~(MORAY_FIELDS_ON_DEVICE | MORAY_OUT_ON_DEVICE)) return fail(c, MORAY_EINVAL, "unknown flags");
+  for (int i = 0; i < n_probs; ++i) {
+    const moray_status s = validate(c, probs[i], i);
+    if (s != MORAY_OK) return s;
+    if (!outs[i].k_ph || !outs[i].heating) return fail(c, MORAY_EINVAL, "result buffers are NULL");
+  }
+  if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
+  const bool fdev = flags & MORAY_FIELDS_ON_DEVICE, odev = flags & MORAY_OUT_ON_DEVICE;
+  const bool fp32 = c->precision == MORAY_FP32_ACC64;
+  const size_t rsz = fp32 ? sizeof(float) : sizeof(double);
+
+  // ---- tables ----
+  std::vector<GridDev> grids;
+  std::vector<ProblemDev> pdev(n_probs);
+  std::vector<long long> prob_cell_off(n_probs + 1, 0);
+  long long n_cells = 0, field_cells = 0;
+  int max_reach = 0, min_l0 = kMaxLevel;
+  unsigned max_steps = 64;
+  for (int i = 0; i < n_probs; ++i) {
+    const moray_problem& P = probs[i];
+    pdev[i].root_grid = (int)grids.size();
+    pdev[i].level_max = P.params.level_max;
+    pdev[i].four_pi_phi_c = 4.0 * kPi * P.params.phi_c;
+    pdev[i].split_t2_base =
+        P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPi * P.params.phi_c)) : __builtin_huge_valf();
+    prob_cell_off[i] = n_cells;
+    long long steps = 16;
+    for (int q = 0; q < P.n_grids; ++q) {
+      const moray_grid& G = P.grids[q];
+      GridDev d{};
+      d.nx = G.nx; d.ny = G.ny; d.nz = G.nz;
+      d.is_child = q > 0;
+      d.ox = q > 0 ? G.offset[0] : 0;
+      d.oy = q > 0 ? G.offset[1] : 0;
+      d.oz = q > 0 ? G.offset[2] : 0;
+      d.problem = i;
+      d.cell_off = n_cells;
+      d.dx_cm = G.dx_cm;
+      d.inv_vol = 1.0 / (G.dx_cm * G.dx_cm * G.dx_cm);
+      grids.push_back(d);
+      n_cells += (long long)G.nx * G.ny * G.nz;
+      steps += 2LL * (G.nx + G.ny + G.nz);
+    }
+    max_steps = std::max<unsigned>(max_steps, (unsigned)std::min<long long>(steps * 2, 1u << 30));
+    prob_cell_off[i + 1] = n_cells;
+    max_reach = std::max(max_reach, reach_level(P));
+    min_l0 = std::min(min_l0, P.params.level_init);
+  }
+  if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
+  field_cells = fdev ? 0 : n_cells;
+
+  // (source, group) trees ordered by seed level, then problem, source, group
+  struct SgKey {
+    int l0, prob, src, grp;
+  };
+  std::vector<SgKey> keys;
+  for (int i = 0; i < n_probs; ++i)
+    for (int s = 0; s < probs[i].n_sources; ++s)
+      for (int g = 0; g < probs[i].spectrum->n_groups; ++g) keys.push_back({probs[i].params.level_init, i, s, g});
+  std::stable_sort(keys.begin(), keys.end(), [](const SgKey& a, const SgKey& b) { return a.l0 < b.l0; });
+  const int n_sg = (int)keys.size();
+  std::vector<SgDev> sgs(n_sg);
+  std::vector<double> sg_bound(n_sg);
+  std::vector<int> first_sg_of(n_probs, -1);
+  for (int k = 0; k < n_sg; ++k) {
+    const SgKey& K = keys[k];
+    const moray_problem& P = probs[K.prob];
+    const moray_source& S = P.sources[K.src];
+    const moray_spectrum& Sp = *P.spectrum;
+    SgDev& d = sgs[k];
+    d.sx = S.x; d.sy = S.y; d.sz = S.z;
+    const double npix0 = std::ldexp(12.0, 2 * P.params.level_init);
+    d.P0 = Sp.photon_frac[K.grp] * S.ndot / npix0;
+    d.pmin0 = P.params.p_min_frac * d.P0;
+    d.eexc_erg = (Sp.energy_ev[K.grp] - Sp.e_ion_ev) * kEvErg;
+    d.sigma64 = Sp.sigma_cm2[K.grp];
+    d.sigma32 = (float)Sp.sigma_cm2[K.grp];
+    d.src_err = (float)std::max({std::fabs(S.x - (double)(float)S.x), std::fabs(S.y - (double)(float)S.y),
+                                 std::fabs(S.z - (double)(float)S.z)});
+    d.problem = K.prob;
+    d.level_init = P.params.level_init;
+    sg_bound[k] = level_rays_bound(P);
+  }
+
+  // ---- queue capacity and chunks of trees ----
+  double need = 0.0;
+  for (double b : sg_bound) need += b;
+  size_t cap = c->queue_cap_user;
+  const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + rsz + sizeof(double));
+  if (!cap) {
+    const size_t fixed = (size_t)n_cells * (rsz + 16) + (size_t)field_cells * 8 + (odev ? 0 : (size_t)n_cells * 16) +
+                         (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) + grids.size() * sizeof(GridDev) + (64 << 20);
+    const size_t room = c->budget > c->allocated + fixed ? c->budget - fixed : 0;
+    const double fit = (double)room / (double)per_ray;
+    cap = (size_t)std::max(4096.0, std::min({need, fit, 2.0e9}));
+  }
+  cap = std::max<size_t>(cap, 256);
+
+  // ---- device memory ----
+  moray_status st;
+  if ((st = ensure(c, c->grids, grids.size() * sizeof(GridDev), "grid table")) ||
+      (st = ensure(c, c->probs, pdev.size() * sizeof(ProblemDev), "problem table")) ||
+      (st = ensure(c, c->sgs, std::max<size_t>(1, n_sg) * sizeof(SgDev), "source table")) ||
+      (st = ensure(c, c->stats, std::max<size_t>(1, n_sg) * sizeof(SgStats), "statistics")) ||
+      (st = ensure(c, c->ctr, sizeof(Counters), "counters")) ||
+      (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
+      (st = ensure(c, c->acc_abs, (size_t)n_cells * 8, "accumulators")) ||
+      (st = ensure(c, c->acc_heat, (size_t)n_cells * 8, "accumulators")) ||
+      (st = ensure(c, c->prob_abs, (size_t)n_probs * 8, "totals")))
+    return st;
+  if (!fdev && (st = ensure(c, c->fields, (size_t)n_cells * 8, "field upload"))) return st;
+  if (!odev && (st = ensure(c, c->outs, (size_t)n_cells * 16, "result staging"))) return st;
+  for (int i = 0; i < 2; ++i) {
+    if ((st = ensure(c, c->q_pix[i], cap * 8, "ray queue")) || (st = ensure(c, c->q_sg[i], cap * 4, "ray queue")) ||
+        (st = ensure(c, c->q_r[i], cap * rsz, "ray queue")) || (st = ensure(c, c->q_P[i], cap * 8, "ray queue")))
+      return st;
+  }
+  c->q_cap = cap;
+
+  // field and output pointers
+  float* fbuf = (float*)c->fields.p;
+  double* obuf = (double*)c->outs.p;
+  {
+    size_t gi = 0;
+    for (int i = 0; i < n_probs; ++i) {
+      long long within = 0;
+      for (int q = 0; q < probs[i].n_grids; ++q, ++gi) {
+        const moray_grid& G = probs[i].grids[q];
+        GridDev& d = grids[gi];
+        const long long nc = (long long)G.nx * G.ny * G.nz;
+        if (fdev) {
+          d.n_h = G.n_h;
+          d.x_hi = G.x_hi;
+        } else {
+          d.n_h = fbuf + d.cell_off;
+          d.x_hi = fbuf + n_cells + d.cell_off;
+          if (!hip_ok(c, hipMemcpyAsync((void*)d.n_h, G.n_h, nc * 4, hipMemcpyHostToDevice, c->stream), "upload") ||
+              !hip_ok(c, hipMemcpyAsync((void*)d.x_hi, G.x_hi, nc * 4, hipMemcpyHostToDevice, c->stream), "upload"))
+            return MORAY_EDEVICE;
+        }
+        if (odev) {
+          d.out_kph = outs[i].k_ph + within;
+          d.out_heat = outs[i].heating + within;
+        } else {
+          d.out_kph = obuf + d.cell_off;
+          d.out_heat = obuf + n_cells + d.cell_off;
+        }
+        within += nc;
+      }
+    }
+  }
+  if (!hip_ok(c, hipMemcpyAsync(c->grids.p, grids.data(), grids.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->stream), "upload") ||
+      !hip_ok(c, hipMemcpyAsync(c->probs.p, pdev.data(), pdev.size() * sizeof(ProblemDev), hipMemcpyHostToDevice, c->stream), "upload") ||
+      (n_sg && !hip_ok(c, hipMemcpyAsync(c->sgs.p, sgs.data(), n_sg * sizeof(SgDev), hipMemcpyHostToDevice, c->stream), "upload")))
+    return MORAY_EDEVICE;
+
+  // seed ranges per level
+  std::vector<int> seed_lo(kLevels, 0), seed_hi(kLevels, 0);
+  for (int l = 0; l <= kMaxLevel; ++l) {
+    int lo = n_sg, hi = n_sg;
+    for (int k = 0; k < n_sg; ++k)
+      if (keys[k].l0 == l) { lo = std::min(lo, k); hi = k + 1; }
+    if (lo >= hi) lo = hi = 0;
+    seed_lo[l] = lo;
+    seed_hi[l] = hi;
+  }
+
+  const int blocks = std::max(1, c->num_cu * c->blocks_per_cu);
+  const int n_grids_tot = (int)grids.size();
+  Counters* ctr = (Counters*)c->ctr.p;
+  SgStats* stats = (SgStats*)c->stats.p;
+  double chunk_limit = (double)cap;
+  const int max_launches = (max_reach - min_l0 + 1);
+
+  for (int attempt = 0;; ++attempt) {
+    // chunks: consecutive trees whose bounds fit the capacity
+    std::vector<ChunkPlan> chunks;
+    {
+      int b = 0;
+      double acc = 0.0;
+      for (int k = 0; k < n_sg; ++k) {
+        if (k > b && acc + sg_bound[k] > chunk_limit) {
+          chunks.push_back({b, k});
+          b = k;
+          acc = 0.0;
+        }
+        acc += sg_bound[k];
+      }
+      if (n_sg > b) chunks.push_back({b, n_sg});
+    }
+    const int n_launch_total = (int)chunks.size() * max_launches;
+    if (c->profile && (int)c->evs.size() < 2 * n_launch_total) {
+      while ((int)c->evs.size() < 2 * n_launch_total) {
+        hipEvent_t e;
+        if (!hip_ok(c, hipEventCreate(&e), "hipEventCreate")) return MORAY_EDEVICE;
+        c->evs.push_back(e);
+      }
+    }
+    if (!hip_ok(c, launch_reset(c->stream, ctr, stats, n_sg, (double*)c->prob_abs.p, n_probs), "reset")) return MORAY_EDEVICE;
+    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, (ProblemDev*)c->probs.p,
+                                             n_cells, (float*)c->kappa.p, (double*)c->acc_abs.p, (double*)c->acc_heat.p, ctr)
+                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, (ProblemDev*)c->probs.p,
+                                              n_cells, (double*)c->kappa.p, (double*)c->acc_abs.p, (double*)c->acc_heat.p, ctr);
+    if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
+    int launches = 0;
+    for (const ChunkPlan& ch : chunks) {
+      if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(c->stream, ctr), "reset levels")) return MORAY_EDEVICE;
+      for (int l = min_l0; l <= max_reach; ++l) {
+        const int lo = std::max(seed_lo[l], ch.sg_begin), hi = std::min(seed_hi[l], ch.sg_end);
+        if (c->profile) (void)hipEventRecord(c->evs[2 * launches], c->stream);
+        if (fp32) {
+          TraceArgs<float> A{};
+          A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
+          A.kappa = (float*)c->kappa.p; A.acc_abs = (double*)c->acc_abs.p; A.acc_heat = (double*)c->acc_heat.p;
+          A.in = {(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (float*)c->q_r[l & 1].p, (double*)c->q_P[l & 1].p};
+          A.out = {(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p, (float*)c->q_r[(l + 1) & 1].p,
+                   (double*)c->q_P[(l + 1) & 1].p};
+          A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
+          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
+          e = launch_trace_level<float>(c->stream, blocks, A);
+        } else {
+          TraceArgs<double> A{};
+          A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
+          A.kappa = (double*)c->kappa.p; A.acc_abs = (double*)c->acc_abs.p; A.acc_heat = (double*)c->acc_heat.p;
+          A.in = {(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (double*)c->q_r[l & 1].p, (double*)c->q_P[l & 1].p};
+          A.out = {(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p, (double*)c->q_r[(l + 1) & 1].p,
+                   (double*)c->q_P[(l + 1) & 1].p};
+          A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
+          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
+          e = launch_trace_level<double>(c->stream, blocks, A);
+        }
+        if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
+        if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], c->stream);
+        ++launches;
+      }
+    }
+    if (!hip_ok(c, launch_finalize(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, n_cells, (double*)c->acc_abs.p,
+                                   (double*)c->acc_heat.p, (double*)c->prob_abs.p, ctr), "finalize"))
+      return MORAY_EDEVICE;
+
+    // ---- results ----
+    const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + n_probs * 8;
+    if (need_stage > c->h_stage_bytes) {
+      (void)hipHostFree(c->h_stage);
+      c->h_stage = nullptr;
+      if (hipHostMalloc(&c->h_stage, need_stage, hipHostMallocDefault) != hipSuccess) {
+        c->h_stage_bytes = 0;
+        return fail(c, MORAY_ENOMEM, "pinned staging allocation failed");
+      }
+      c->h_stage_bytes = need_stage;
+    }
+    char* hs = (char*)c->h_stage;
+    Counters* hctr = (Counters*)hs;
+    SgStats* hst = (SgStats*)(hs + sizeof(Counters));
+    double* habs = (double*)(hs + sizeof(Counters) + n_sg * sizeof(SgStats));
+    if (!hip_ok(c, hipMemcpyAsync(hctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, c->stream), "copy") ||
+        (n_sg && !hip_ok(c, hipMemcpyAsync(hst, stats, n_sg * sizeof(SgStats), hipMemcpyDeviceToHost, c->stream), "copy")) ||
+        !hip_ok(c, hipMemcpyAsync(habs, c->prob_abs.p, n_probs * 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
+      return MORAY_EDEVICE;
+    if (hctr->err & kErrBadInput) return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
+    if (hctr->err & kErrInternal) return fail(c, MORAY_EINTERNAL, "a ray exceeded its step bound");
+    if (hctr->err & kErrOverflow) {
+      bool single = true;
+      for (const ChunkPlan& ch : chunks) single = single && ch.sg_end - ch.sg_begin <= 1;
+      if (single || attempt >= 6)
+        return fail(c, MORAY_EQUEUE, "ray queue overflowed; raise queue_capacity or the HBM budget");
+      chunk_limit *= 0.25;   // retry with smaller chunks of trees
+      continue;
+    }
+    double trace_ms = 0.0;
+    if (c->profile) {
+      for (int k = 0; k < launches; ++k) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, c->evs[2 * k], c->evs[2 * k + 1]) == hipSuccess) trace_ms += ms;
+      }
+    }
+    unsigned long long peak = 0;
+    for (int l = 0; l < kLevels; ++l) peak = std::max(peak, hctr->count[l]);
+    for (int i = 0; i < n_probs; ++i) {
+      moray_result& R = outs[i];
+      R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
+      R.segments = R.rays_seeded = R.splits = R.rays_escaped = R.rays_truncated = 0;
+      R.peak_level_rays = peak;
+      R.trace_ms = trace_ms;
+      R.trace_launches = launches;
+      R.absorbed = habs[i];
+    }
+    std::vector<double> esc_c(n_probs, 0.0), trn_c(n_probs, 0.0);
+    for (int k = 0; k < n_sg; ++k) {
+      const SgKey& K = keys[k];
+      moray_result& R = outs[K.prob];
+      const moray_problem& P = probs[K.prob];
+      const SgStats& S = hst[k];
+      R.emitted += P.spectrum->photon_frac[K.grp] * P.sources[K.src].ndot;
+      R.escaped += S.esc_P;
+      R.truncated += S.trunc_P;
+      R.segments += S.segs;
+      R.splits += S.splits;
+      R.rays_escaped += S.n_esc;
+      R.rays_truncated += S.n_trunc;
+      R.rays_seeded += (unsigned long long)std::ldexp(12.0, 2 * P.params.level_init);
+      if (R.escaped_sg) R.escaped_sg[K.src * P.spectrum->n_groups + K.grp] = S.esc_P;
+    }
+    if (!odev) {
+      for (int i = 0; i < n_probs; ++i) {
+        const long long off = prob_cell_off[i], nc = prob_cell_off[i + 1] - off;
+        if (!hip_ok(c, hipMemcpy(outs[i].k_ph, obuf + off, nc * 8, hipMemcpyDeviceToHost), "copy results") ||
+            !hip_ok(c, hipMemcpy(outs[i].heating, obuf + n_cells + off, nc * 8, hipMemcpyDeviceToHost), "copy results"))
+          return MORAY_EDEVICE;
+      }
+    }
+    c->err = "no error";
+    return MORAY_OK;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,250 @@
+"""Python binding of libmoray.so (the C ABI in include/moray.h).
+
+Argument marshalling only: every step of a trace runs in the HIP library.
+Fields may be torch CUDA tensors (device-resident, passed by pointer) or
+numpy arrays (copied by the library); outputs are float64 torch CUDA tensors
+by default. PyTorch provides device memory and the stream, nothing else.
+The library must be built (python -m paper_1012_2865_amd.build); importing
+this module without it raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import List, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libmoray.so")
+
+MORAY_OK, MORAY_EINVAL, MORAY_ENOMEM, MORAY_EDEVICE, MORAY_EQUEUE, MORAY_EBUSY, MORAY_EINTERNAL = 0, -1, -2, -3, -4, -5, -7
+STATUS_NAMES = {0: "MORAY_OK", -1: "MORAY_EINVAL", -2: "MORAY_ENOMEM", -3: "MORAY_EDEVICE", -4: "MORAY_EQUEUE",
+                -5: "MORAY_EBUSY", -7: "MORAY_EINTERNAL"}
+MORAY_FP64, MORAY_FP32_ACC64 = 0, 1
+MORAY_FIELDS_ON_DEVICE, MORAY_OUT_ON_DEVICE = 1, 2
+
+
+class MorayError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS_NAMES.get(status, status)}: {message}")
+        self.status = status
+
+
+class InitParams(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int), ("precision", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
+                ("queue_capacity", ctypes.c_size_t), ("waves_per_cu", ctypes.c_int), ("refill_lanes", ctypes.c_int),
+                ("chunk_rays", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("profile", ctypes.c_int)]
+
+
+class Source(ctypes.Structure):
+    _fields_ = [("x", ctypes.c_double), ("y", ctypes.c_double), ("z", ctypes.c_double), ("ndot", ctypes.c_double)]
+
+
+class Spectrum(ctypes.Structure):
+    _fields_ = [("n_groups", ctypes.c_int), ("energy_ev", ctypes.POINTER(ctypes.c_double)),
+                ("sigma_cm2", ctypes.POINTER(ctypes.c_double)), ("photon_frac", ctypes.POINTER(ctypes.c_double)),
+                ("e_ion_ev", ctypes.c_double)]
+
+
+class Grid(ctypes.Structure):
+    _fields_ = [("nx", ctypes.c_int), ("ny", ctypes.c_int), ("nz", ctypes.c_int), ("dx_cm", ctypes.c_double),
+                ("parent", ctypes.c_int), ("offset", ctypes.c_int * 3), ("n_h", ctypes.c_void_p),
+                ("x_hi", ctypes.c_void_p)]
+
+
+class TraceParams(ctypes.Structure):
+    _fields_ = [("phi_c", ctypes.c_double), ("level_init", ctypes.c_int), ("level_max", ctypes.c_int),
+                ("p_min_frac", ctypes.c_double)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("grids", ctypes.POINTER(Grid)), ("n_grids", ctypes.c_int), ("sources", ctypes.POINTER(Source)),
+                ("n_sources", ctypes.c_int), ("spectrum", ctypes.POINTER(Spectrum)), ("params", TraceParams)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("k_ph", ctypes.c_void_p), ("heating", ctypes.c_void_p), ("escaped_sg", ctypes.POINTER(ctypes.c_double)),
+                ("emitted", ctypes.c_double), ("absorbed", ctypes.c_double), ("escaped", ctypes.c_double),
+                ("truncated", ctypes.c_double), ("segments", ctypes.c_ulonglong), ("rays_seeded", ctypes.c_ulonglong),
+                ("splits", ctypes.c_ulonglong), ("rays_escaped", ctypes.c_ulonglong),
+                ("rays_truncated", ctypes.c_ulonglong), ("peak_level_rays", ctypes.c_ulonglong),
+                ("trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int)]
+
+
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_free", "moray_last_error", "moray_version")
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    global _lib
+    if _lib is None:
+        if not os.path.exists(path):
+            raise ImportError(f"{path} is missing: build it with `python -m paper_1012_2865_amd.build`")
+        lib = ctypes.CDLL(path)
+        lib.moray_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(InitParams)]
+        lib.moray_init.restype = ctypes.c_int
+        lib.moray_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
+                                    ctypes.POINTER(Result)]
+        lib.moray_trace.restype = ctypes.c_int
+        lib.moray_free.argtypes = [ctypes.c_void_p]
+        lib.moray_free.restype = None
+        lib.moray_last_error.argtypes = [ctypes.c_void_p]
+        lib.moray_last_error.restype = ctypes.c_char_p
+        lib.moray_version.argtypes = []
+        lib.moray_version.restype = ctypes.c_char_p
+        _lib = lib
+    return _lib
+
+
+def moray_version() -> str:
+    return load_library().moray_version().decode()
+
+
+def moray_last_error(ctx) -> str:
+    return load_library().moray_last_error(ctx).decode()
+
+
+def moray_init(device: int = 0, precision: int = MORAY_FP32_ACC64, hbm_budget_bytes: int = 0,
+               queue_capacity: int = 0, waves_per_cu: int = 0, refill_lanes: int = 0, chunk_rays: int = 0,
+               hip_stream=None, profile: bool = False):
+    """Create a context; returns an opaque handle. hip_stream: an int handle
+    (torch.cuda.Stream.cuda_stream) or None for torch's current stream."""
+    lib = load_library()
+    if hip_stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                hip_stream = torch.cuda.current_stream(device).cuda_stream
+        except Exception:
+            hip_stream = None
+    p = InitParams(device, precision, hbm_budget_bytes, queue_capacity, waves_per_cu, refill_lanes, chunk_rays,
+                   ctypes.c_void_p(hip_stream or 0), int(bool(profile)))
+    h = ctypes.c_void_p()
+    rc = lib.moray_init(ctypes.byref(h), ctypes.byref(p))
+    if rc != MORAY_OK:
+        raise MorayError(rc, "moray_init failed")
+    return h
+
+
+def moray_free(ctx) -> None:
+    if ctx is not None:
+        load_library().moray_free(ctx)
+
+
+def _is_torch_cuda(a) -> bool:
+    return hasattr(a, "is_cuda") and bool(a.is_cuda)
+
+
+def _ptr(a, dtype_np, keep: list):
+    if _is_torch_cuda(a):
+        assert a.is_contiguous(), "device fields must be contiguous"
+        keep.append(a)
+        return a.data_ptr()
+    arr = np.ascontiguousarray(a, dtype=dtype_np)
+    keep.append(arr)
+    return arr.ctypes.data
+
+
+def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False) -> List[dict]:
+    """Trace a batch of problems in one call.
+
+    Each problem is duck-typed: ``grids`` (``n_h``, ``x_hi`` as torch CUDA
+    tensors or numpy arrays of shape (nz, ny, nx); ``dx_cm``, ``parent``,
+    ``offset``), ``sources`` (S x 4), ``spectrum`` (``energy_ev``, ``sigma_cm2``,
+    ``frac``, ``e_ion_ev``), ``params`` (``phi_c``, ``level_init``,
+    ``level_max``, ``p_min_frac``). Returns one dict per problem with ``k_ph``
+    and ``heating`` (lists per grid) and the totals."""
+    lib = load_library()
+    keep: list = []
+    n = len(problems)
+    cprobs = (Problem * n)()
+    results = (Result * n)()
+    on_dev = None
+    outs = []
+    for i, pb in enumerate(problems):
+        grids = (Grid * len(pb.grids))()
+        keep.append(grids)
+        n_cells = 0
+        shapes = []
+        for q, g in enumerate(pb.grids):
+            dev = _is_torch_cuda(g.n_h)
+            if on_dev is None:
+                on_dev = dev
+            if dev != on_dev or _is_torch_cuda(g.x_hi) != dev:
+                raise ValueError("all fields of one call must be on the device, or all on the host")
+            shape = tuple(g.n_h.shape)
+            nz, ny, nx = shape
+            grids[q].nx, grids[q].ny, grids[q].nz = nx, ny, nz
+            grids[q].dx_cm = float(g.dx_cm)
+            grids[q].parent = int(g.parent)
+            for a in range(3):
+                grids[q].offset[a] = int(g.offset[a])
+            grids[q].n_h = _ptr(g.n_h, np.float32, keep)
+            grids[q].x_hi = _ptr(g.x_hi, np.float32, keep)
+            shapes.append(shape)
+            n_cells += nx * ny * nz
+        S = np.asarray(pb.sources, dtype=np.float64).reshape(-1, 4)
+        srcs = (Source * max(1, len(S)))()
+        for k, row in enumerate(S):
+            srcs[k].x, srcs[k].y, srcs[k].z, srcs[k].ndot = (float(v) for v in row)
+        keep.append(srcs)
+        sp = pb.spectrum
+        e = np.ascontiguousarray(sp.energy_ev, dtype=np.float64)
+        sg = np.ascontiguousarray(sp.sigma_cm2, dtype=np.float64)
+        fr = np.ascontiguousarray(sp.frac, dtype=np.float64)
+        keep += [e, sg, fr]
+        dp = ctypes.POINTER(ctypes.c_double)
+        cspec = Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
+        keep.append(cspec)
+        pr = pb.params
+        cprobs[i] = Problem(grids, len(pb.grids), srcs, len(S), ctypes.pointer(cspec),
+                            TraceParams(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac)))
+        if out_on_device:
+            import torch
+            kph = torch.empty(n_cells, dtype=torch.float64, device="cuda")
+            heat = torch.empty(n_cells, dtype=torch.float64, device="cuda")
+            results[i].k_ph, results[i].heating = kph.data_ptr(), heat.data_ptr()
+        else:
+            kph, heat = np.empty(n_cells), np.empty(n_cells)
+            results[i].k_ph, results[i].heating = kph.ctypes.data, heat.ctypes.data
+        esc = np.zeros(max(1, len(S) * len(e)))
+        if want_escaped_sg:
+            results[i].escaped_sg = esc.ctypes.data_as(dp)
+        outs.append((kph, heat, shapes, esc, len(S), len(e)))
+    flags = (MORAY_FIELDS_ON_DEVICE if on_dev else 0) | (MORAY_OUT_ON_DEVICE if out_on_device else 0)
+    rc = lib.moray_trace(ctx, cprobs, n, flags, results)
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    out = []
+    for i in range(n):
+        kph, heat, shapes, esc, ns, ng = outs[i]
+        kl, hl, o = [], [], 0
+        for shp in shapes:
+            m = int(np.prod(shp))
+            kl.append(kph[o:o + m].reshape(shp))
+            hl.append(heat[o:o + m].reshape(shp))
+            o += m
+        R = results[i]
+        d = {name: getattr(R, name) for name, _ in Result._fields_ if name not in ("k_ph", "heating", "escaped_sg")}
+        d["k_ph"], d["heating"] = kl, hl
+        if want_escaped_sg:
+            d["escaped_sg"] = esc[:ns * ng].reshape(ns, ng)
+        out.append(d)
+    return out
+
+
+def problem_to_device(problem, device: str = "cuda"):
+    """Copy a problem's fields into torch CUDA tensors (the device-resident form)."""
+    import copy
+
+    import torch
+    p = copy.copy(problem)
+    p.grids = []
+    for g in problem.grids:
+        h = copy.copy(g)
+        h.n_h = torch.from_numpy(np.ascontiguousarray(g.n_h, dtype=np.float32)).to(device)
+        h.x_hi = torch.from_numpy(np.ascontiguousarray(g.x_hi, dtype=np.float32)).to(device)
+        p.grids.append(h)
+    return p

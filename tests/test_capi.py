@@ -1,0 +1,96 @@
+"""The C-ABI library loads, exports every function include/moray.h declares,
+fails cleanly without a GPU, and the Python binding's struct layouts match
+the header as compiled by a C compiler."""
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import pytest
+
+from paper_1012_2865_amd import moray as M
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "moray.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(moray_[a-z_]+)\s*\(", text)))
+
+
+def test_header_declares_the_abi():
+    assert _declared_functions() == sorted(M.ABI_FUNCTIONS)
+
+
+def test_library_exports_every_declared_function():
+    lib = M.load_library()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+    out = subprocess.run(["nm", "-D", "--defined-only", M.LIB_PATH], capture_output=True, text=True).stdout
+    exported = set(re.findall(r" T (moray_\w+)", out))
+    assert set(_declared_functions()) <= exported
+
+
+def test_version_string():
+    assert re.fullmatch(r"\d+\.\d+\.\d+", M.moray_version())
+
+
+def test_init_without_gpu_reports_edevice():
+    import torch
+    if torch.cuda.device_count() > 0:
+        pytest.skip("a GPU is visible")
+    with pytest.raises(M.MorayError) as e:
+        M.moray_init(device=0, hip_stream=0)
+    assert e.value.status == M.MORAY_EDEVICE
+
+
+def test_init_rejects_bad_parameters_before_touching_the_device():
+    lib = M.load_library()
+    h = ctypes.c_void_p()
+    p = M.InitParams(0, 7, 0, 0, 0, 0, 0, None, 0)           # unknown precision
+    assert lib.moray_init(ctypes.byref(h), ctypes.byref(p)) == M.MORAY_EINVAL
+    p = M.InitParams(0, 1, 0, 0, 0, 65, 0, None, 0)          # more idle lanes than a wave has
+    assert lib.moray_init(ctypes.byref(h), ctypes.byref(p)) == M.MORAY_EINVAL
+    assert lib.moray_init(None, ctypes.byref(p)) == M.MORAY_EINVAL
+    assert not h.value
+    assert M.moray_last_error(None) == "context is NULL"
+    lib.moray_free(None)
+
+
+_LAYOUT_C = r"""
+#include <stdio.h>
+#include <stddef.h>
+#include "moray.h"
+#define S(T) printf(#T " %zu\n", sizeof(T));
+#define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  S(moray_init_params) O(moray_init_params, hip_stream) O(moray_init_params, profile)
+  S(moray_source) S(moray_spectrum) O(moray_spectrum, e_ion_ev)
+  S(moray_grid) O(moray_grid, offset) O(moray_grid, n_h) O(moray_grid, x_hi)
+  S(moray_trace_params) O(moray_trace_params, p_min_frac)
+  S(moray_problem) O(moray_problem, params)
+  S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
+  O(moray_result, trace_ms) O(moray_result, trace_launches)
+  return 0;
+}
+"""
+
+
+def test_binding_struct_layout_matches_header():
+    with tempfile.TemporaryDirectory() as d:
+        src, exe = os.path.join(d, "layout.c"), os.path.join(d, "layout")
+        open(src, "w").write(_LAYOUT_C)
+        subprocess.check_call(["gcc", "-std=c11", "-I", os.path.join(ROOT, "include"), src, "-o", exe])
+        got = dict(line.split() for line in subprocess.check_output([exe], text=True).splitlines())
+    py = {"moray_init_params": M.InitParams, "moray_source": M.Source, "moray_spectrum": M.Spectrum,
+          "moray_grid": M.Grid, "moray_trace_params": M.TraceParams, "moray_problem": M.Problem,
+          "moray_result": M.Result}
+    for key, val in got.items():
+        if "." in key:
+            t, f = key.split(".")
+            assert getattr(py[t], f).offset == int(val), key
+        else:
+            assert ctypes.sizeof(py[key]) == int(val), key
