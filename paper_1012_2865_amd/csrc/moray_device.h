@@ -10,6 +10,8 @@ constexpr int kMaxLevel = 29;
 constexpr int kLevels = kMaxLevel + 2;
 constexpr int kWave = 64;
 constexpr int kTraceBlock = 256;
+constexpr int kFinalBlock = 256;
+constexpr int kFinalCellsPerThread = 4;
 
 // One uniform grid patch of one problem, in the batch-wide cell numbering.
 struct GridDev {
@@ -17,9 +19,8 @@ struct GridDev {
   int ox, oy, oz;          // lower corner in root cells (children), 0 for roots
   int is_child;            // 0: root (unit scale), 1: 2x-refined child of the root
   int problem;
-  long long cell_off;      // first cell of this grid in the batch-wide arrays
+  long long cell_off;      // first cell of this grid in the batch-wide numbering
   double dx_cm;            // local cell width
-  double inv_vol;          // 1 / dx^3
   const float* n_h;        // device copies (or caller device memory) of the inputs
   const float* x_hi;
   double* out_kph;         // where finalize writes this grid's k_ph and heating
@@ -28,22 +29,28 @@ struct GridDev {
 
 struct ProblemDev {
   int root_grid;           // index of the root grid in the grid table
-  int level_max;
-  double four_pi_phi_c;    // 4 pi phi_c, the canonical split constant
-  float split_t2_base;     // 12 / (4 pi phi_c) as float (local-cell units^2 at level 0), inf if phi_c = 0
+  int n_groups;
+  long long cell_off;      // first cell of the problem
+  long long n_cells;       // cells of all its grids
+  long long acc_off;       // first accumulator slot: group g of cell c is acc_off + g*n_cells + (c - cell_off)
+  int eexc_off;            // first of its n_groups (E - E_ion) values in erg
+  int pad;
 };
 
 // One (source, group) ray tree.
 struct SgDev {
   double sx, sy, sz;       // source position, root cells
   double P0;               // photon rate of one seed ray
-  double pmin0;            // p_min_frac * P0 (halved twice per level below the seeds)
-  double eexc_erg;         // (E - E_ion) in erg
+  double pmin0;            // p_min_frac * P0 (quartered per level below the seeds)
   double sigma64;          // cross-section, cm^2
+  double four_pi_phi_c;    // 4 pi phi_c of its problem
+  long long acc_slot;      // accumulator of cell c (batch numbering) is acc[acc_slot + c]
   float sigma32;
-  float src_err;           // |s - float(s)| max over axes (0 for sources on the 2^-12 lattice)
+  float split_t2_base;     // 12 / (4 pi phi_c), float; FLT_MAX when the problem never splits
   int problem;
   int level_init;
+  int level_max;
+  int pad;
 };
 
 struct SgStats {
@@ -63,14 +70,14 @@ struct Counters {
 
 constexpr unsigned kErrOverflow = 1u;
 constexpr unsigned kErrBadInput = 2u;
-constexpr unsigned kErrNonFinite = 4u;
 constexpr unsigned kErrInternal = 8u;
 
-template <typename R>
+// Level queue, structure of arrays. The radius is float64 in both precision
+// modes so a child starts exactly where its parent's exit distance put it.
 struct RayQueue {
   uint64_t* pix;
   uint32_t* sg;
-  R* r;
+  double* r;
   double* P;
 };
 
@@ -80,9 +87,8 @@ struct TraceArgs {
   const ProblemDev* probs;
   const SgDev* sgs;
   const R* kappa;          // n_H x_HI dx_root per leaf cell; -(child+1) on covered root cells
-  double* acc_abs;         // absorbed photons/s per leaf cell (batch-wide)
-  double* acc_heat;        // absorbed energy erg/s per leaf cell
-  RayQueue<R> in, out;
+  double* acc;             // absorbed photons/s per (problem, group, leaf cell)
+  RayQueue in, out;
   unsigned long long capacity;
   Counters* ctr;
   SgStats* stats;
@@ -91,6 +97,13 @@ struct TraceArgs {
   int chunk;                           // rays claimed per atomic
   int refill;                          // idle lanes that trigger a refill
   unsigned max_steps;                  // hard cap on cells per ray (never reached)
+};
+
+// One finalize block: cells [first, first + count) of one grid.
+struct FinalBlock {
+  int grid;
+  int count;
+  long long first;
 };
 
 }  // namespace moray

@@ -12,14 +12,16 @@
 //
 // Inside trace_level the grid is persistent: every wave keeps 64 rays in
 // flight, one per lane, marches them cell by cell (Eq. trace), tests the split
-// criterion at each cell exit (Eq. split), deposits P (1 - e^-tau) with two
-// float64 atomics per segment (Eqs. dtau, flux, kph, gamma), and refills idle
-// lanes from a private chunk of the level queue claimed with one atomic.
-// Children of splitting lanes are compacted with a wave ballot and written as
-// four consecutive structure-of-arrays records per parent.
+// criterion at each cell exit (Eq. split), deposits P (1 - e^-tau) with one
+// float64 atomic per segment into the (problem, group) accumulator of the cell
+// (Eqs. dtau, flux, kph; heating is the group-weighted sum formed in finalize,
+// Eq. gamma), and refills idle lanes from a private chunk of the level queue
+// claimed with one atomic. Children of splitting lanes are compacted with a
+// wave ballot and written as four consecutive structure-of-arrays records.
 #include "moray_device.h"
 
 #include <hip/hip_runtime.h>
+#include <cfloat>
 #include <cmath>
 #include <cstdint>
 
@@ -98,73 +100,181 @@ __device__ void healpix_dir(int level, uint64_t pix, double& vx, double& vy, dou
   vz = z;
 }
 
-// ---------------------------------------------------------------------------
-// Precision-specific arithmetic. Float64 geometry mirrors the definition
-// exactly (no contraction, true division); float32 geometry multiplies by a
-// per-ray reciprocal.
-// ---------------------------------------------------------------------------
-template <typename R> struct Arith;
-
-template <> struct Arith<double> {
-  static __device__ __forceinline__ double mul(double a, double b) { return __dmul_rn(a, b); }
-  static __device__ __forceinline__ double add(double a, double b) { return __dadd_rn(a, b); }
-  static __device__ __forceinline__ double inv(double) { return 0.0; }
-  // exit distance to plane b, root units: ((b - s) / d) * hinv
-  static __device__ __forceinline__ double tplane(double b, double s, double d, double, double hinv) {
-    return ((b - s) / d) * hinv;
-  }
-  static __device__ __forceinline__ double neg_expm1(double tau) { return -expm1(-tau); }
-  static __device__ __forceinline__ double inf() { return __builtin_huge_val(); }
-};
-
-template <> struct Arith<float> {
-  static __device__ __forceinline__ float mul(float a, float b) { return __fmul_rn(a, b); }
-  static __device__ __forceinline__ float add(float a, float b) { return __fadd_rn(a, b); }
-  static __device__ __forceinline__ float inv(float d) { return 1.0f / d; }
-  static __device__ __forceinline__ float tplane(float b, float s, float, float id, float hinv) {
-    return ((b - s) * id) * hinv;
-  }
-  static __device__ __forceinline__ double neg_expm1(float tau) { return (double)(-expm1f(-tau)); }
-  static __device__ __forceinline__ float inf() { return __builtin_huge_valf(); }
-};
-
-__device__ __forceinline__ int cell_rule_d(double x, double d) {
-  return d >= 0.0 ? (int)floor(x) : (int)ceil(x) - 1;
-}
-__device__ __forceinline__ int cell_rule_f(float x, float d) {
-  return d >= 0.0f ? (int)floorf(x) : (int)ceilf(x) - 1;
-}
-template <typename R> __device__ __forceinline__ int cell_rule(R x, R d);
-template <> __device__ __forceinline__ int cell_rule<double>(double x, double d) { return cell_rule_d(x, d); }
-template <> __device__ __forceinline__ int cell_rule<float>(float x, float d) { return cell_rule_f(x, d); }
-
-template <typename R> __device__ __forceinline__ R rmin(R a, R b) { return b < a ? b : a; }
-
+// A point on a cell plane belongs to the upper cell when the direction
+// component is >= 0, else to the lower one.
+__device__ __forceinline__ int cell_rule(double x, double d) { return d >= 0.0 ? (int)floor(x) : (int)ceil(x) - 1; }
 __device__ __forceinline__ int floor_half(int c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
+template <typename T> __device__ __forceinline__ T sel3(int k, T a, T b, T c) { return k == 0 ? a : (k == 1 ? b : c); }
+
+// ---------------------------------------------------------------------------
+// Geometry, float64: the definition's expressions (true division, no
+// contraction), so every decision equals the reference's.
+// ---------------------------------------------------------------------------
+struct Geom64 {
+  double d0, d1, d2;       // direction
+  double s0, s1, s2;       // source in local cells
+  double t0, t1, t2;       // distance to the next plane per axis, root cells
+  double r;                // radius, root cells
+  double hinv, hloc;
+
+  __device__ void set_dir(const double v[3]) { d0 = v[0]; d1 = v[1]; d2 = v[2]; }
+  __device__ double dir64(int k) const { return sel3(k, d0, d1, d2); }
+  __device__ float dirf(int k) const { return (float)sel3(k, d0, d1, d2); }
+  __device__ void set_radius(double r64) { r = r64; }
+  __device__ double radius64() const { return r; }
+  __device__ double plane(double d, double s, int c) const {
+    if (d == 0.0) return __builtin_huge_val();
+    return (((double)(c + (d > 0.0 ? 1 : 0)) - s) / d) * hinv;
+  }
+  __device__ void set_frame(const double sl[3], int c0, int c1, int c2, bool child) {
+    s0 = sl[0]; s1 = sl[1]; s2 = sl[2];
+    hinv = child ? 0.5 : 1.0;
+    hloc = child ? 2.0 : 1.0;
+    t0 = plane(d0, s0, c0); t1 = plane(d1, s1, c1); t2 = plane(d2, s2, c2);
+  }
+  __device__ int exit_axis() const {
+    int ax = 0;
+    double b = t0;
+    if (t1 < b) { ax = 1; b = t1; }
+    if (t2 < b) ax = 2;
+    return ax;
+  }
+  __device__ double te(int ax) const { return sel3(ax, t0, t1, t2); }
+  __device__ double chord(int ax) const { return te(ax) - r; }
+  __device__ bool positive(double dr, int) const { return dr > 0.0; }
+  __device__ void advance(int ax) { r = te(ax); }
+  __device__ double local_u(int ax) const { return te(ax) * hloc; }
+  __device__ void step(int ax, int cnew) {
+    if (ax == 0) t0 = plane(d0, s0, cnew);
+    else if (ax == 1) t1 = plane(d1, s1, cnew);
+    else t2 = plane(d2, s2, cnew);
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Geometry, float32: every plane distance is a pair hi + lo of floats.
+// The source coordinate is split into a 2^-12-lattice part q (so b - q is
+// exact) and a residual e; the reciprocal of the float64 direction into
+// i + j. Then t = (b - q - e)(i + j) = hi + lo, hi = (b-q) i rounded, lo =
+// its exact fma residual + (b-q) j - e i. Chords are differences of such
+// pairs, accurate to ~1e-14 t, so float32 arithmetic places every segment
+// where float64 would.
+// ---------------------------------------------------------------------------
+struct Geom32 {
+  float d0, d1, d2;
+  float i0, i1, i2, j0, j1, j2;      // 1/d = i + j
+  float q0, q1, q2, e0, e1, e2;      // local source = q + e
+  float h0, h1, h2, l0, l1, l2;      // plane distance = h + l (root cells)
+  float rh, rl;                      // radius = rh + rl
+  float hinv, hloc;
+
+  __device__ void set_dir(const double v[3]) {
+    d0 = (float)v[0]; d1 = (float)v[1]; d2 = (float)v[2];
+    split_inv(v[0], i0, j0); split_inv(v[1], i1, j1); split_inv(v[2], i2, j2);
+  }
+  static __device__ void split_inv(double d, float& i, float& j) {
+    if (d == 0.0) { i = 0.0f; j = 0.0f; return; }
+    const double inv = 1.0 / d;
+    i = (float)inv;
+    j = (float)(inv - (double)i);
+  }
+  __device__ double dir64(int k) const {
+    const float dk = sel3(k, d0, d1, d2);
+    if (dk == 0.0f) return 0.0;
+    return 1.0 / ((double)sel3(k, i0, i1, i2) + (double)sel3(k, j0, j1, j2));
+  }
+  __device__ float dirf(int k) const { return sel3(k, d0, d1, d2); }
+  __device__ void set_radius(double r64) { rh = (float)r64; rl = (float)(r64 - (double)rh); }
+  __device__ double radius64() const { return (double)rh + (double)rl; }
+  __device__ void plane(float d, float i, float j, float q, float e, int c, float& h, float& l) const {
+    if (d == 0.0f) { h = __builtin_huge_valf(); l = 0.0f; return; }
+    const float bs = (float)(c + (d > 0.0f ? 1 : 0)) - q;     // exact
+    const float th = bs * i;
+    float tl = fmaf(bs, i, -th);
+    tl = fmaf(bs, j, tl);
+    tl = fmaf(-e, i, tl);
+    h = th * hinv;
+    l = tl * hinv;
+  }
+  static __device__ void split_src(double s, float& q, float& e) {
+    const double qd = rint(s * 4096.0) * (1.0 / 4096.0);
+    q = (float)qd;
+    e = (float)(s - (double)q);
+  }
+  __device__ void set_frame(const double sl[3], int c0, int c1, int c2, bool child) {
+    split_src(sl[0], q0, e0); split_src(sl[1], q1, e1); split_src(sl[2], q2, e2);
+    hinv = child ? 0.5f : 1.0f;
+    hloc = child ? 2.0f : 1.0f;
+    plane(d0, i0, j0, q0, e0, c0, h0, l0);
+    plane(d1, i1, j1, q1, e1, c1, h1, l1);
+    plane(d2, i2, j2, q2, e2, c2, h2, l2);
+  }
+  // (ah + al) < (bh + bl), exact enough to order distinct planes
+  static __device__ bool lt(float ah, float al, float bh, float bl) { return ((ah - bh) + (al - bl)) < 0.0f; }
+  __device__ int exit_axis() const {
+    int ax = 0;
+    float bh = h0, bl = l0;
+    if (lt(h1, l1, bh, bl)) { ax = 1; bh = h1; bl = l1; }
+    if (lt(h2, l2, bh, bl)) ax = 2;
+    return ax;
+  }
+  __device__ float chord(int ax) const {
+    return (sel3(ax, h0, h1, h2) - rh) + (sel3(ax, l0, l1, l2) - rl);
+  }
+  // a pair resolves distances to ~2^-46 t: anything below 2^-40 t is a plane tie (dr = 0 in float64)
+  __device__ bool positive(float dr, int ax) const { return dr > sel3(ax, h0, h1, h2) * 9.094947e-13f; }
+  __device__ void advance(int ax) { rh = sel3(ax, h0, h1, h2); rl = sel3(ax, l0, l1, l2); }
+  __device__ float local_u(int ax) const { return sel3(ax, h0, h1, h2) * hloc; }
+  __device__ void step(int ax, int cnew) {
+    if (ax == 0) plane(d0, i0, j0, q0, e0, cnew, h0, l0);
+    else if (ax == 1) plane(d1, i1, j1, q1, e1, cnew, h1, l1);
+    else plane(d2, i2, j2, q2, e2, cnew, h2, l2);
+  }
+};
+
+template <typename R> struct GeomOf;
+template <> struct GeomOf<double> { using type = Geom64; };
+template <> struct GeomOf<float> { using type = Geom32; };
+
+// Photons removed in a segment of optical depth tau: dP = P (1 - e^-tau)
+// (Eq. flux), P -= dP. Float64 takes the definition literally. Float32 keeps
+// both parts accurate to its own precision: 1 - e^-tau as -expm1f for thin
+// segments, and for thick ones (tau > ln 2) the transmitted part P e^-tau
+// from expf, the absorbed part as the float64 difference, so dP + P_new = P
+// holds to float64 rounding either way.
+__device__ __forceinline__ double absorb(double& P, double tau) {
+  const double dP = P * -expm1(-tau);
+  P -= dP;
+  return dP;
+}
+__device__ __forceinline__ double absorb(double& P, float tau) {
+  if (tau < 0.6931472f) {
+    const double dP = P * (double)(-expm1f(-tau));
+    P -= dP;
+    return dP;
+  }
+  const double Pt = P * (double)expf(-tau);
+  const double dP = P - Pt;
+  P = Pt;
+  return dP;
+}
 
 // Per-lane ray state.
 template <typename R>
 struct Ray {
+  typename GeomOf<R>::type g;
   uint64_t pix;
   uint32_t sg;
-  int level_max;
-  double P, pmin, eexc;
-  R sigma;
-  R r;                    // radius (root cells)
-  R split_t2;             // split when (t_exit in local cells)^2 > split_t2 (float path)
-  R eps_u;                // float path: bound on the source-position error in local cells / |d|
-  double four_pi_phi_c;
-  // direction and its reciprocal
-  R d0, d1, d2, i0, i1, i2;
-  // grid frame
   int q;                  // grid index
   int c0, c1, c2;         // local cell
   int n0, n1, n2;         // grid dims
   int lin;                // batch-wide cell index
-  R s0, s1, s2;           // source in local cells
-  R hinv, hloc;           // 1/scale, scale (1 root, 2 child)
-  R t0, t1, t2;           // distance to the next plane per axis (root cells)
+  double P, pmin;
+  double* acc;            // acc[lin] is this ray's (problem, group) slot of cell lin
+  R sigma;
   R kap;                  // absorber column per root-cell length of the current cell
+  R split_t;              // float path: split when u^2 > split_t; float64 path: 12*4^l (inf: never)
+  double fpp;             // 4 pi phi_c (float64 path)
   unsigned segs;
 };
 
@@ -173,37 +283,34 @@ struct Tracer {
   const TraceArgs<R>& a;
   __device__ explicit Tracer(const TraceArgs<R>& args) : a(args) {}
 
-  // Load grid q's frame and the exit distances from local cell (c0, c1, c2).
   __device__ void set_frame(Ray<R>& L, int q) const {
     const GridDev& G = a.grids[q];
     const SgDev& S = a.sgs[L.sg];
     L.q = q;
     L.n0 = G.nx; L.n1 = G.ny; L.n2 = G.nz;
+    double sl[3];
     if (G.is_child) {
-      L.hinv = (R)0.5; L.hloc = (R)2;
-      L.s0 = (R)(2.0 * (S.sx - (double)G.ox));
-      L.s1 = (R)(2.0 * (S.sy - (double)G.oy));
-      L.s2 = (R)(2.0 * (S.sz - (double)G.oz));
+      sl[0] = 2.0 * (S.sx - (double)G.ox);
+      sl[1] = 2.0 * (S.sy - (double)G.oy);
+      sl[2] = 2.0 * (S.sz - (double)G.oz);
     } else {
-      L.hinv = (R)1; L.hloc = (R)1;
-      L.s0 = (R)S.sx; L.s1 = (R)S.sy; L.s2 = (R)S.sz;
+      sl[0] = S.sx; sl[1] = S.sy; sl[2] = S.sz;
     }
-    const R inf = Arith<R>::inf();
-    L.t0 = L.d0 == (R)0 ? inf : Arith<R>::tplane((R)(L.c0 + (L.d0 > (R)0)), L.s0, L.d0, L.i0, L.hinv);
-    L.t1 = L.d1 == (R)0 ? inf : Arith<R>::tplane((R)(L.c1 + (L.d1 > (R)0)), L.s1, L.d1, L.i1, L.hinv);
-    L.t2 = L.d2 == (R)0 ? inf : Arith<R>::tplane((R)(L.c2 + (L.d2 > (R)0)), L.s2, L.d2, L.i2, L.hinv);
+    L.g.set_frame(sl, L.c0, L.c1, L.c2, G.is_child != 0);
     L.lin = (int)G.cell_off + L.c0 + G.nx * (L.c1 + G.ny * L.c2);
   }
 
   // Enter child grid `ch` from root cell (rc0, rc1, rc2) across axis `ax`
-  // moving in direction `dir`, at the current radius.
+  // moving in direction `dir`, at the current radius: along the crossing axis
+  // the fine cell follows from the face, along the others from the position,
+  // kept among the two fine cells under the root cell.
   __device__ void enter_child(Ray<R>& L, int ch, int rc0, int rc1, int rc2, int ax, int dir) const {
     const GridDev& G = a.grids[ch];
     const SgDev& S = a.sgs[L.sg];
     const int rc[3] = {rc0, rc1, rc2};
     const int o[3] = {G.ox, G.oy, G.oz};
-    const R sr[3] = {(R)S.sx, (R)S.sy, (R)S.sz};
-    const R d[3] = {L.d0, L.d1, L.d2};
+    const double sr[3] = {S.sx, S.sy, S.sz};
+    const double r = L.g.radius64();
     int c[3];
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
@@ -211,18 +318,19 @@ struct Tracer {
       if (k == ax) {
         c[k] = lo + (dir < 0 ? 1 : 0);
       } else {
-        const R x = Arith<R>::add(sr[k], Arith<R>::mul(L.r, d[k]));
-        int cl = cell_rule<R>((R)2 * (x - (R)o[k]), d[k]);
-        cl = cl < lo ? lo : (cl > lo + 1 ? lo + 1 : cl);
-        c[k] = cl;
+        const double dk = L.g.dir64(k);
+        const double x = __dadd_rn(sr[k], __dmul_rn(r, dk));
+        const int cl = cell_rule(2.0 * (x - (double)o[k]), dk);
+        c[k] = cl < lo ? lo : (cl > lo + 1 ? lo + 1 : cl);
       }
     }
     L.c0 = c[0]; L.c1 = c[1]; L.c2 = c[2];
     set_frame(L, ch);
   }
 
-  // After a step along `ax` by `dir`: resolve leaving the current grid and
-  // entering a covered root cell. Returns false when the ray left the root.
+  // After a step along `ax` by `dir` out of the current grid, or into a root
+  // cell covered by a child: find the new leaf cell. Returns false when the
+  // ray left the root grid.
   __device__ bool settle(Ray<R>& L, int ax, int dir) const {
     const GridDev& G = a.grids[L.q];
     if (!G.is_child) {
@@ -241,7 +349,6 @@ struct Tracer {
       L.kap = a.kappa[L.lin];
       return true;
     }
-    // leave the child for the root cell beyond its face
     const int rc0 = G.ox + floor_half(L.c0), rc1 = G.oy + floor_half(L.c1), rc2 = G.oz + floor_half(L.c2);
     const int root = a.probs[G.problem].root_grid;
     const GridDev& Rg = a.grids[root];
@@ -264,51 +371,45 @@ struct Tracer {
   // Returns false when it starts outside the root grid (escaped at once).
   __device__ bool start(Ray<R>& L, unsigned long long idx, unsigned long long n_children) const {
     const int level = a.level;
+    double r64;
     if (idx < n_children) {
       L.pix = a.in.pix[idx];
       L.sg = a.in.sg[idx];
-      L.r = a.in.r[idx];
+      r64 = a.in.r[idx];
       L.P = a.in.P[idx];
     } else {
       const unsigned long long j = idx - n_children;
       const unsigned long long npix = 12ull << (2 * level);
       L.sg = (uint32_t)(a.seed_sg_begin + j / npix);
       L.pix = j % npix;
-      L.r = (R)0;
+      r64 = 0.0;
       L.P = a.sgs[L.sg].P0;
     }
     const SgDev& S = a.sgs[L.sg];
-    const ProblemDev& Pb = a.probs[S.problem];
-    const int dl = level - S.level_init;
-    L.pmin = ldexp(S.pmin0, -2 * dl);
-    L.eexc = S.eexc_erg;
-    L.level_max = Pb.level_max;
-    L.four_pi_phi_c = Pb.four_pi_phi_c;
+    L.pmin = ldexp(S.pmin0, -2 * (level - S.level_init));
+    L.acc = a.acc + S.acc_slot;
     L.segs = 0;
+    const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.sigma = S.sigma32;
-      L.split_t2 = ldexpf(Pb.split_t2_base, 2 * level);
+      L.split_t = can_split ? ldexpf(S.split_t2_base, 2 * level) : FLT_MAX;
+      L.fpp = 0.0;
     } else {
       L.sigma = S.sigma64;
-      L.split_t2 = 0.0;
+      L.split_t = can_split ? ldexp(12.0, 2 * level) : __builtin_huge_val();
+      L.fpp = S.four_pi_phi_c;
     }
-    double v0, v1, v2;
-    healpix_dir(level, L.pix, v0, v1, v2);
-    L.d0 = (R)v0; L.d1 = (R)v1; L.d2 = (R)v2;
-    L.i0 = Arith<R>::inv(L.d0); L.i1 = Arith<R>::inv(L.d1); L.i2 = Arith<R>::inv(L.d2);
-    if constexpr (sizeof(R) == 4) {
-      const float im = fmaxf(fabsf(L.i0), fmaxf(fabsf(L.i1), fabsf(L.i2)));
-      L.eps_u = S.src_err * 2.0f * im;   // child frames double the source error
-    } else {
-      L.eps_u = 0.0;
-    }
+    double v[3];
+    healpix_dir(level, L.pix, v[0], v[1], v[2]);
+    L.g.set_dir(v);
+    L.g.set_radius(r64);
     // locate the leaf cell holding s + r d
-    const int root = Pb.root_grid;
+    const int root = a.probs[S.problem].root_grid;
     const GridDev& Rg = a.grids[root];
-    const R x0 = Arith<R>::add((R)S.sx, Arith<R>::mul(L.r, L.d0));
-    const R x1 = Arith<R>::add((R)S.sy, Arith<R>::mul(L.r, L.d1));
-    const R x2 = Arith<R>::add((R)S.sz, Arith<R>::mul(L.r, L.d2));
-    const int rc0 = cell_rule<R>(x0, L.d0), rc1 = cell_rule<R>(x1, L.d1), rc2 = cell_rule<R>(x2, L.d2);
+    const double x0 = __dadd_rn(S.sx, __dmul_rn(r64, v[0]));
+    const double x1 = __dadd_rn(S.sy, __dmul_rn(r64, v[1]));
+    const double x2 = __dadd_rn(S.sz, __dmul_rn(r64, v[2]));
+    const int rc0 = cell_rule(x0, v[0]), rc1 = cell_rule(x1, v[1]), rc2 = cell_rule(x2, v[2]);
     if ((unsigned)rc0 >= (unsigned)Rg.nx || (unsigned)rc1 >= (unsigned)Rg.ny || (unsigned)rc2 >= (unsigned)Rg.nz)
       return false;
     const int rlin = (int)Rg.cell_off + rc0 + Rg.nx * (rc1 + Rg.ny * rc2);
@@ -318,9 +419,9 @@ struct Tracer {
       const GridDev& G = a.grids[ch];
       // the fine cell lies under root cell rc (exact in floating point; kept in range regardless)
       const int f0 = 2 * (rc0 - G.ox), f1 = 2 * (rc1 - G.oy), f2 = 2 * (rc2 - G.oz);
-      L.c0 = min(max(cell_rule<R>((R)2 * (x0 - (R)G.ox), L.d0), f0), f0 + 1);
-      L.c1 = min(max(cell_rule<R>((R)2 * (x1 - (R)G.oy), L.d1), f1), f1 + 1);
-      L.c2 = min(max(cell_rule<R>((R)2 * (x2 - (R)G.oz), L.d2), f2), f2 + 1);
+      L.c0 = min(max(cell_rule(2.0 * (x0 - (double)G.ox), v[0]), f0), f0 + 1);
+      L.c1 = min(max(cell_rule(2.0 * (x1 - (double)G.oy), v[1]), f1), f1 + 1);
+      L.c2 = min(max(cell_rule(2.0 * (x2 - (double)G.oz), v[2]), f2), f2 + 1);
       set_frame(L, ch);
       L.kap = a.kappa[L.lin];
     } else {
@@ -352,7 +453,21 @@ struct Tracer {
       te = t < te ? t : te;
     }
     const double u = te * h;
-    return ldexp(12.0, 2 * a.level) < L.four_pi_phi_c * (u * u);
+    return ldexp(12.0, 2 * a.level) < S.four_pi_phi_c * (u * u);
+  }
+
+  __device__ bool split_test(const Ray<R>& L, int ax) const {
+    if constexpr (sizeof(R) == 4) {
+      const float u = L.g.local_u(ax);
+      const float gap = u * u - L.split_t;
+      const float tol = L.split_t * 9.6e-7f;   // 16 float ulp: beyond every rounding of u^2
+      if (gap > tol) return true;
+      if (gap < -tol) return false;
+      return split_exact(L);
+    } else {
+      const double u = L.g.local_u(ax);
+      return L.split_t < L.fpp * (u * u);
+    }
   }
 };
 
@@ -378,7 +493,6 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 
 template <typename R>
 __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a) {
-  using A = Arith<R>;
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if (a.ctr->err & kErrBadInput) return;
@@ -428,21 +542,9 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       continue;
     }
     if (active) {
-      // ---- one cell: exit distance, split test, deposit, step ----
-      const R te = rmin(L.t0, rmin(L.t1, L.t2));
-      const int ax = (L.t0 == te) ? 0 : ((L.t1 == te) ? 1 : 2);
-      bool split = false;
-      if (level < L.level_max) {
-        if constexpr (sizeof(R) == 4) {
-          const float u = te * L.hloc;
-          const float gap = u * u - L.split_t2;
-          const float tol = fmaf(2.0f * u + L.eps_u, L.eps_u, L.split_t2 * 9.6e-7f);
-          split = fabsf(gap) <= tol ? T.split_exact(L) : gap > 0.0f;
-        } else {
-          const double u = te * L.hloc;
-          split = ldexp(12.0, 2 * level) < L.four_pi_phi_c * (u * u);
-        }
-      }
+      // ---- one cell: exit plane, split test, deposit, step ----
+      const int ax = L.g.exit_axis();
+      const bool split = T.split_test(L, ax);
       const unsigned long long smask = __ballot(split);
       if (smask) {
         const int leader = __ffsll((unsigned long long)smask) - 1;
@@ -453,11 +555,12 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
           const unsigned long long dst = base + 4ull * (unsigned long long)__popcll(smask & below);
           if (dst + 4 <= a.capacity) {
             const double Pc = 0.25 * L.P;
+            const double r64 = L.g.radius64();
 #pragma unroll
             for (int k = 0; k < 4; ++k) {
               a.out.pix[dst + k] = 4ull * L.pix + (uint64_t)k;
               a.out.sg[dst + k] = L.sg;
-              a.out.r[dst + k] = L.r;
+              a.out.r[dst + k] = r64;
               a.out.P[dst + k] = Pc;
             }
           } else {
@@ -470,34 +573,33 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         }
       }
       if (!split) {
-        const R dr = te - L.r;
-        if (dr > (R)0) {
+        const R dr = L.g.chord(ax);
+        if (L.g.positive(dr, ax)) {
           const R tau = L.kap * L.sigma * dr;
-          const double dP = L.P * A::neg_expm1(tau);
-          unsafeAtomicAdd(&a.acc_abs[L.lin], dP);
-          if (L.eexc != 0.0) unsafeAtomicAdd(&a.acc_heat[L.lin], dP * L.eexc);
-          L.P -= dP;
+          const double dP = absorb(L.P, tau);
+          unsafeAtomicAdd(&L.acc[L.lin], dP);
           L.segs++;
-          L.r = te;
+          L.g.advance(ax);
         }
         // step across the exit face
-        int dir;
+        int dir, cnew, nax;
         if (ax == 0) {
-          dir = L.d0 > (R)0 ? 1 : -1;
-          L.c0 += dir;
+          dir = L.g.dirf(0) > 0.0f ? 1 : -1;
+          cnew = (L.c0 += dir);
+          nax = L.n0;
           L.lin += dir;
-          L.t0 = A::tplane((R)(L.c0 + (dir > 0)), L.s0, L.d0, L.i0, L.hinv);
         } else if (ax == 1) {
-          dir = L.d1 > (R)0 ? 1 : -1;
-          L.c1 += dir;
+          dir = L.g.dirf(1) > 0.0f ? 1 : -1;
+          cnew = (L.c1 += dir);
+          nax = L.n1;
           L.lin += dir * L.n0;
-          L.t1 = A::tplane((R)(L.c1 + (dir > 0)), L.s1, L.d1, L.i1, L.hinv);
         } else {
-          dir = L.d2 > (R)0 ? 1 : -1;
-          L.c2 += dir;
+          dir = L.g.dirf(2) > 0.0f ? 1 : -1;
+          cnew = (L.c2 += dir);
+          nax = L.n2;
           L.lin += dir * L.n0 * L.n1;
-          L.t2 = A::tplane((R)(L.c2 + (dir > 0)), L.s2, L.d2, L.i2, L.hinv);
         }
+        L.g.step(ax, cnew);
         if (L.P < L.pmin) {
           flush_end(a, L, 1);
           active = false;
@@ -507,9 +609,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
           flush_end(a, L, 0);
           active = false;
         } else {
-          const int cax = ax == 0 ? L.c0 : (ax == 1 ? L.c1 : L.c2);
-          const int nax = ax == 0 ? L.n0 : (ax == 1 ? L.n1 : L.n2);
-          const R k = ((unsigned)cax < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
+          const R k = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
           if (k < (R)0) {
             if (!T.settle(L, ax, dir)) {
               flush_end(a, L, 0);
@@ -536,14 +636,13 @@ __device__ __forceinline__ int grid_of(const GridDev* grids, int n_grids, long l
   return lo;
 }
 
-__global__ void reset_kernel(Counters* ctr, SgStats* stats, int n_sg, double* prob_abs, int n_prob) {
+__global__ void reset_kernel(Counters* ctr, SgStats* stats, int n_sg) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i == 0) {
     for (int l = 0; l < kLevels; ++l) { ctr->count[l] = 0; ctr->head[l] = 0; }
     ctr->lost_rays = 0; ctr->lost_P = 0.0; ctr->err = 0;
   }
   if (i < n_sg) stats[i] = SgStats{0.0, 0.0, 0ull, 0ull, 0ull, 0ull};
-  if (i < n_prob) prob_abs[i] = 0.0;
 }
 
 __global__ void reset_levels_kernel(Counters* ctr) {
@@ -553,12 +652,13 @@ __global__ void reset_levels_kernel(Counters* ctr) {
 
 // Absorber column per root-cell length, input checks, zeroed accumulators.
 template <typename R>
-__global__ void prep_kernel(const GridDev* grids, int n_grids, const ProblemDev* probs, long long n_cells,
-                            R* kappa, double* acc_abs, double* acc_heat, Counters* ctr) {
+__global__ void prep_kernel(const GridDev* grids, int n_grids, const ProblemDev* probs, long long n_cells, R* kappa,
+                            double* acc, Counters* ctr) {
   for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n_cells;
        c += (long long)gridDim.x * blockDim.x) {
     const int g = grid_of(grids, n_grids, c);
     const GridDev& G = grids[g];
+    const ProblemDev& P = probs[G.problem];
     const long long local = c - G.cell_off;
     const float nh = G.n_h[local], xh = G.x_hi[local];
     if (!(nh >= 0.0f) || !(xh >= 0.0f) || !(xh <= 1.0f) || !isfinite(nh)) atomicOr(&ctr->err, kErrBadInput);
@@ -574,23 +674,35 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, const ProblemDev*
       }
     }
     kappa[c] = k;
-    acc_abs[c] = 0.0;
-    acc_heat[c] = 0.0;
+    const long long base = P.acc_off + (c - P.cell_off);
+    for (int gr = 0; gr < P.n_groups; ++gr) acc[base + gr * P.n_cells] = 0.0;
   }
 }
 
-// k_ph and heating per absorber; per-problem absorbed totals.
-__global__ void finalize_kernel(const GridDev* grids, int n_grids, long long n_cells, const double* acc_abs,
-                                const double* acc_heat, double* prob_abs, const Counters* ctr) {
+// k_ph = sum_g absorbed_g / (n_H x_HI V); heating = sum_g absorbed_g (E_g - E_ion) / (n_H x_HI V);
+// per-block sums of the absorbed rate (no atomics).
+__global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* grids, const ProblemDev* probs,
+                                                               const FinalBlock* blocks, const double* acc,
+                                                               const double* eexc, double* partial,
+                                                               const Counters* ctr) {
+  __shared__ double red[kFinalBlock / kWave];
   if (ctr->err & kErrBadInput) return;
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n_cells;
-       c += (long long)gridDim.x * blockDim.x) {
-    const int g = grid_of(grids, n_grids, c);
-    const GridDev& G = grids[g];
-    const long long local = c - G.cell_off;
+  const FinalBlock B = blocks[blockIdx.x];
+  const GridDev& G = grids[B.grid];
+  const ProblemDev& P = probs[G.problem];
+  const double vol = G.dx_cm * G.dx_cm * G.dx_cm;
+  double sum = 0.0;
+  for (int t = threadIdx.x; t < B.count; t += kFinalBlock) {
+    const long long local = B.first + t;
+    const long long c = G.cell_off + local;
+    const long long base = P.acc_off + (c - P.cell_off);
+    double ab = 0.0, he = 0.0;
+    for (int gr = 0; gr < P.n_groups; ++gr) {
+      const double v = acc[base + gr * P.n_cells];
+      ab += v;
+      he += v * eexc[P.eexc_off + gr];
+    }
     const double nabs = (double)G.n_h[local] * (double)G.x_hi[local];
-    const double vol = G.dx_cm * G.dx_cm * G.dx_cm;
-    const double ab = acc_abs[c], he = acc_heat[c];
     double k = 0.0, h = 0.0;
     if (nabs > 0.0) {
       k = ab / (nabs * vol);
@@ -598,17 +710,24 @@ __global__ void finalize_kernel(const GridDev* grids, int n_grids, long long n_c
     }
     G.out_kph[local] = k;
     G.out_heat[local] = h;
-    if (ab != 0.0) unsafeAtomicAdd(&prob_abs[G.problem], ab);
+    sum += ab;
+  }
+  for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = sum;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s = 0.0;
+    for (int w = 0; w < kFinalBlock / kWave; ++w) s += red[w];
+    partial[blockIdx.x] = s;
   }
 }
 
 // ---------------------------------------------------------------------------
 // Host-side launchers (called by the runtime on its stream).
 // ---------------------------------------------------------------------------
-hipError_t launch_reset(hipStream_t s, Counters* ctr, SgStats* stats, int n_sg, double* prob_abs, int n_prob) {
-  const int n = n_sg > n_prob ? n_sg : n_prob;
-  const int blocks = (n > 0 ? n : 1) / 256 + 1;
-  hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, ctr, stats, n_sg, prob_abs, n_prob);
+hipError_t launch_reset(hipStream_t s, Counters* ctr, SgStats* stats, int n_sg) {
+  const int blocks = (n_sg > 0 ? n_sg : 1) / 256 + 1;
+  hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, ctr, stats, n_sg);
   return hipGetLastError();
 }
 
@@ -619,12 +738,12 @@ hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
 
 template <typename R>
 hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, const ProblemDev* probs,
-                       long long n_cells, R* kappa, double* acc_abs, double* acc_heat, Counters* ctr) {
+                       long long n_cells, R* kappa, double* acc, Counters* ctr) {
   long long blocks = (n_cells + 255) / 256;
   if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(prep_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, probs, n_cells, kappa,
-                     acc_abs, acc_heat, ctr);
+                     acc, ctr);
   return hipGetLastError();
 }
 
@@ -634,20 +753,19 @@ hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& arg
   return hipGetLastError();
 }
 
-hipError_t launch_finalize(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, long long n_cells,
-                           const double* acc_abs, const double* acc_heat, double* prob_abs, const Counters* ctr) {
-  long long blocks = (n_cells + 255) / 256;
-  if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
-  if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(finalize_kernel, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, n_cells, acc_abs,
-                     acc_heat, prob_abs, ctr);
+hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, const ProblemDev* probs,
+                           const FinalBlock* blocks, const double* acc, const double* eexc, double* partial,
+                           const Counters* ctr) {
+  if (n_blocks < 1) return hipSuccess;
+  hipLaunchKernelGGL(finalize_kernel, dim3(n_blocks), dim3(kFinalBlock), 0, s, grids, probs, blocks, acc, eexc,
+                     partial, ctr);
   return hipGetLastError();
 }
 
 template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, float*,
-                                       double*, double*, Counters*);
+                                       double*, Counters*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, double*,
-                                        double*, double*, Counters*);
+                                        double*, Counters*);
 template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&);
 template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&);
 

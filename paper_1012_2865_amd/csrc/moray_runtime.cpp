@@ -13,6 +13,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cfloat>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -20,15 +21,14 @@
 #include <vector>
 
 namespace moray {
-hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int, double*, int);
+hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
 hipError_t launch_reset_levels(hipStream_t, Counters*);
 template <typename R>
-hipError_t launch_prep(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, R*, double*, double*,
-                       Counters*);
+hipError_t launch_prep(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, R*, double*, Counters*);
 template <typename R>
 hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&);
-hipError_t launch_finalize(hipStream_t, int, const GridDev*, int, long long, const double*, const double*, double*,
-                           const Counters*);
+hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
+                           const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, int* blocks_per_cu);
 }  // namespace moray
 
@@ -61,7 +61,7 @@ struct moray_ctx {
   int blocks_per_cu = 1;
   std::string err = "no error";
   size_t allocated = 0;
-  DevBuf grids, probs, sgs, stats, ctr, kappa, acc_abs, acc_heat, prob_abs, fields, outs;
+  DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial, fields, outs;
   DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
   size_t q_cap = 0;
   void* h_stage = nullptr;
@@ -258,8 +258,8 @@ void moray_free(moray_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  DevBuf* all[] = {&c->grids, &c->probs, &c->sgs, &c->stats, &c->ctr, &c->kappa, &c->acc_abs, &c->acc_heat,
-                   &c->prob_abs, &c->fields, &c->outs};
+  DevBuf* all[] = {&c->grids, &c->probs, &c->sgs,     &c->stats,   &c->ctr,    &c->kappa,
+                   &c->acc,   &c->eexc,  &c->fblocks, &c->partial, &c->fields, &c->outs};
   for (DevBuf* b : all) release(c, *b);
   for (int i = 0; i < 2; ++i) {
     release(c, c->q_pix[i]);
@@ -286,21 +286,22 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const bool fp32 = c->precision == MORAY_FP32_ACC64;
   const size_t rsz = fp32 ? sizeof(float) : sizeof(double);
 
-  // ---- tables ----
+  // ---- tables: grids, problems, per-group energies ----
   std::vector<GridDev> grids;
   std::vector<ProblemDev> pdev(n_probs);
-  std::vector<long long> prob_cell_off(n_probs + 1, 0);
-  long long n_cells = 0, field_cells = 0;
+  std::vector<double> eexc;
+  long long n_cells = 0, n_acc = 0;
   int max_reach = 0, min_l0 = kMaxLevel;
   unsigned max_steps = 64;
   for (int i = 0; i < n_probs; ++i) {
     const moray_problem& P = probs[i];
-    pdev[i].root_grid = (int)grids.size();
-    pdev[i].level_max = P.params.level_max;
-    pdev[i].four_pi_phi_c = 4.0 * kPi * P.params.phi_c;
-    pdev[i].split_t2_base =
-        P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPi * P.params.phi_c)) : __builtin_huge_valf();
-    prob_cell_off[i] = n_cells;
+    ProblemDev& pd = pdev[i];
+    pd.root_grid = (int)grids.size();
+    pd.n_groups = P.spectrum->n_groups;
+    pd.cell_off = n_cells;
+    pd.eexc_off = (int)eexc.size();
+    for (int g = 0; g < P.spectrum->n_groups; ++g)
+      eexc.push_back((P.spectrum->energy_ev[g] - P.spectrum->e_ion_ev) * kEvErg);
     long long steps = 16;
     for (int q = 0; q < P.n_grids; ++q) {
       const moray_grid& G = P.grids[q];
@@ -313,18 +314,33 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       d.problem = i;
       d.cell_off = n_cells;
       d.dx_cm = G.dx_cm;
-      d.inv_vol = 1.0 / (G.dx_cm * G.dx_cm * G.dx_cm);
       grids.push_back(d);
       n_cells += (long long)G.nx * G.ny * G.nz;
       steps += 2LL * (G.nx + G.ny + G.nz);
     }
+    pd.n_cells = n_cells - pd.cell_off;
+    pd.acc_off = n_acc;
+    n_acc += pd.n_cells * pd.n_groups;
     max_steps = std::max<unsigned>(max_steps, (unsigned)std::min<long long>(steps * 2, 1u << 30));
-    prob_cell_off[i + 1] = n_cells;
     max_reach = std::max(max_reach, reach_level(P));
     min_l0 = std::min(min_l0, P.params.level_init);
   }
   if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
-  field_cells = fdev ? 0 : n_cells;
+
+  // finalize blocks: each covers up to kFinalBlock*kFinalCellsPerThread cells of one grid
+  std::vector<FinalBlock> fblocks;
+  std::vector<int> fblock_first(n_probs + 1, 0);
+  {
+    const long long per = (long long)kFinalBlock * kFinalCellsPerThread;
+    for (size_t q = 0; q < grids.size(); ++q) {
+      const GridDev& G = grids[q];
+      if (q == 0 || grids[q - 1].problem != G.problem) fblock_first[G.problem] = (int)fblocks.size();
+      const long long nc = (long long)G.nx * G.ny * G.nz;
+      for (long long f = 0; f < nc; f += per)
+        fblocks.push_back({(int)q, (int)std::min(per, nc - f), f});
+    }
+    fblock_first[n_probs] = (int)fblocks.size();
+  }
 
   // (source, group) trees ordered by seed level, then problem, source, group
   struct SgKey {
@@ -338,35 +354,37 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const int n_sg = (int)keys.size();
   std::vector<SgDev> sgs(n_sg);
   std::vector<double> sg_bound(n_sg);
-  std::vector<int> first_sg_of(n_probs, -1);
   for (int k = 0; k < n_sg; ++k) {
     const SgKey& K = keys[k];
     const moray_problem& P = probs[K.prob];
     const moray_source& S = P.sources[K.src];
     const moray_spectrum& Sp = *P.spectrum;
+    const ProblemDev& pd = pdev[K.prob];
     SgDev& d = sgs[k];
     d.sx = S.x; d.sy = S.y; d.sz = S.z;
     const double npix0 = std::ldexp(12.0, 2 * P.params.level_init);
     d.P0 = Sp.photon_frac[K.grp] * S.ndot / npix0;
     d.pmin0 = P.params.p_min_frac * d.P0;
-    d.eexc_erg = (Sp.energy_ev[K.grp] - Sp.e_ion_ev) * kEvErg;
     d.sigma64 = Sp.sigma_cm2[K.grp];
     d.sigma32 = (float)Sp.sigma_cm2[K.grp];
-    d.src_err = (float)std::max({std::fabs(S.x - (double)(float)S.x), std::fabs(S.y - (double)(float)S.y),
-                                 std::fabs(S.z - (double)(float)S.z)});
+    d.four_pi_phi_c = 4.0 * kPi * P.params.phi_c;
+    d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPi * P.params.phi_c)) : FLT_MAX;
+    d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
     d.problem = K.prob;
     d.level_init = P.params.level_init;
+    d.level_max = P.params.phi_c > 0.0 ? P.params.level_max : P.params.level_init;
     sg_bound[k] = level_rays_bound(P);
   }
 
-  // ---- queue capacity and chunks of trees ----
+  // ---- queue capacity ----
   double need = 0.0;
   for (double b : sg_bound) need += b;
   size_t cap = c->queue_cap_user;
-  const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + rsz + sizeof(double));
+  const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
+  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_acc * 8 + (fdev ? 0 : (size_t)n_cells * 8) +
+                       (odev ? 0 : (size_t)n_cells * 16) + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
+                       grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) + (64 << 20);
   if (!cap) {
-    const size_t fixed = (size_t)n_cells * (rsz + 16) + (size_t)field_cells * 8 + (odev ? 0 : (size_t)n_cells * 16) +
-                         (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) + grids.size() * sizeof(GridDev) + (64 << 20);
     const size_t room = c->budget > c->allocated + fixed ? c->budget - fixed : 0;
     const double fit = (double)room / (double)per_ray;
     cap = (size_t)std::max(4096.0, std::min({need, fit, 2.0e9}));
@@ -381,15 +399,16 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       (st = ensure(c, c->stats, std::max<size_t>(1, n_sg) * sizeof(SgStats), "statistics")) ||
       (st = ensure(c, c->ctr, sizeof(Counters), "counters")) ||
       (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
-      (st = ensure(c, c->acc_abs, (size_t)n_cells * 8, "accumulators")) ||
-      (st = ensure(c, c->acc_heat, (size_t)n_cells * 8, "accumulators")) ||
-      (st = ensure(c, c->prob_abs, (size_t)n_probs * 8, "totals")))
+      (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_acc) * 8, "accumulators")) ||
+      (st = ensure(c, c->eexc, eexc.size() * 8, "group energies")) ||
+      (st = ensure(c, c->fblocks, fblocks.size() * sizeof(FinalBlock), "finalize blocks")) ||
+      (st = ensure(c, c->partial, fblocks.size() * 8, "partial sums")))
     return st;
   if (!fdev && (st = ensure(c, c->fields, (size_t)n_cells * 8, "field upload"))) return st;
   if (!odev && (st = ensure(c, c->outs, (size_t)n_cells * 16, "result staging"))) return st;
   for (int i = 0; i < 2; ++i) {
     if ((st = ensure(c, c->q_pix[i], cap * 8, "ray queue")) || (st = ensure(c, c->q_sg[i], cap * 4, "ray queue")) ||
-        (st = ensure(c, c->q_r[i], cap * rsz, "ray queue")) || (st = ensure(c, c->q_P[i], cap * 8, "ray queue")))
+        (st = ensure(c, c->q_r[i], cap * 8, "ray queue")) || (st = ensure(c, c->q_P[i], cap * 8, "ray queue")))
       return st;
   }
   c->q_cap = cap;
@@ -426,9 +445,13 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       }
     }
   }
-  if (!hip_ok(c, hipMemcpyAsync(c->grids.p, grids.data(), grids.size() * sizeof(GridDev), hipMemcpyHostToDevice, c->stream), "upload") ||
-      !hip_ok(c, hipMemcpyAsync(c->probs.p, pdev.data(), pdev.size() * sizeof(ProblemDev), hipMemcpyHostToDevice, c->stream), "upload") ||
-      (n_sg && !hip_ok(c, hipMemcpyAsync(c->sgs.p, sgs.data(), n_sg * sizeof(SgDev), hipMemcpyHostToDevice, c->stream), "upload")))
+  auto up = [&](DevBuf& b, const void* src, size_t bytes) {
+    return bytes == 0 || hip_ok(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, c->stream), "upload");
+  };
+  if (!up(c->grids, grids.data(), grids.size() * sizeof(GridDev)) ||
+      !up(c->probs, pdev.data(), pdev.size() * sizeof(ProblemDev)) ||
+      !up(c->sgs, sgs.data(), n_sg * sizeof(SgDev)) || !up(c->eexc, eexc.data(), eexc.size() * 8) ||
+      !up(c->fblocks, fblocks.data(), fblocks.size() * sizeof(FinalBlock)))
     return MORAY_EDEVICE;
 
   // seed ranges per level
@@ -473,25 +496,26 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         c->evs.push_back(e);
       }
     }
-    if (!hip_ok(c, launch_reset(c->stream, ctr, stats, n_sg, (double*)c->prob_abs.p, n_probs), "reset")) return MORAY_EDEVICE;
-    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, (ProblemDev*)c->probs.p,
-                                             n_cells, (float*)c->kappa.p, (double*)c->acc_abs.p, (double*)c->acc_heat.p, ctr)
-                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, (ProblemDev*)c->probs.p,
-                                              n_cells, (double*)c->kappa.p, (double*)c->acc_abs.p, (double*)c->acc_heat.p, ctr);
+    if (!hip_ok(c, launch_reset(c->stream, ctr, stats, n_sg), "reset")) return MORAY_EDEVICE;
+    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot,
+                                             (ProblemDev*)c->probs.p, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
+                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot,
+                                              (ProblemDev*)c->probs.p, n_cells, (double*)c->kappa.p, (double*)c->acc.p, ctr);
     if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
     int launches = 0;
     for (const ChunkPlan& ch : chunks) {
       if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(c->stream, ctr), "reset levels")) return MORAY_EDEVICE;
       for (int l = min_l0; l <= max_reach; ++l) {
         const int lo = std::max(seed_lo[l], ch.sg_begin), hi = std::min(seed_hi[l], ch.sg_end);
+        const RayQueue qin{(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (double*)c->q_r[l & 1].p,
+                           (double*)c->q_P[l & 1].p};
+        const RayQueue qout{(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p,
+                            (double*)c->q_r[(l + 1) & 1].p, (double*)c->q_P[(l + 1) & 1].p};
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches], c->stream);
         if (fp32) {
           TraceArgs<float> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
-          A.kappa = (float*)c->kappa.p; A.acc_abs = (double*)c->acc_abs.p; A.acc_heat = (double*)c->acc_heat.p;
-          A.in = {(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (float*)c->q_r[l & 1].p, (double*)c->q_P[l & 1].p};
-          A.out = {(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p, (float*)c->q_r[(l + 1) & 1].p,
-                   (double*)c->q_P[(l + 1) & 1].p};
+          A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
@@ -499,10 +523,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
-          A.kappa = (double*)c->kappa.p; A.acc_abs = (double*)c->acc_abs.p; A.acc_heat = (double*)c->acc_heat.p;
-          A.in = {(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (double*)c->q_r[l & 1].p, (double*)c->q_P[l & 1].p};
-          A.out = {(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p, (double*)c->q_r[(l + 1) & 1].p,
-                   (double*)c->q_P[(l + 1) & 1].p};
+          A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
@@ -513,12 +534,14 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         ++launches;
       }
     }
-    if (!hip_ok(c, launch_finalize(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, n_cells, (double*)c->acc_abs.p,
-                                   (double*)c->acc_heat.p, (double*)c->prob_abs.p, ctr), "finalize"))
+    if (!hip_ok(c, launch_finalize(c->stream, (int)fblocks.size(), (GridDev*)c->grids.p, (ProblemDev*)c->probs.p,
+                                   (FinalBlock*)c->fblocks.p, (double*)c->acc.p, (double*)c->eexc.p,
+                                   (double*)c->partial.p, ctr),
+                "finalize"))
       return MORAY_EDEVICE;
 
     // ---- results ----
-    const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + n_probs * 8;
+    const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + fblocks.size() * 8;
     if (need_stage > c->h_stage_bytes) {
       (void)hipHostFree(c->h_stage);
       c->h_stage = nullptr;
@@ -531,10 +554,11 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     char* hs = (char*)c->h_stage;
     Counters* hctr = (Counters*)hs;
     SgStats* hst = (SgStats*)(hs + sizeof(Counters));
-    double* habs = (double*)(hs + sizeof(Counters) + n_sg * sizeof(SgStats));
+    double* hpart = (double*)(hs + sizeof(Counters) + n_sg * sizeof(SgStats));
     if (!hip_ok(c, hipMemcpyAsync(hctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, c->stream), "copy") ||
         (n_sg && !hip_ok(c, hipMemcpyAsync(hst, stats, n_sg * sizeof(SgStats), hipMemcpyDeviceToHost, c->stream), "copy")) ||
-        !hip_ok(c, hipMemcpyAsync(habs, c->prob_abs.p, n_probs * 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
+        (!fblocks.empty() &&
+         !hip_ok(c, hipMemcpyAsync(hpart, c->partial.p, fblocks.size() * 8, hipMemcpyDeviceToHost, c->stream), "copy")) ||
         !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
       return MORAY_EDEVICE;
     if (hctr->err & kErrBadInput) return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
@@ -563,9 +587,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       R.peak_level_rays = peak;
       R.trace_ms = trace_ms;
       R.trace_launches = launches;
-      R.absorbed = habs[i];
+      for (int b = fblock_first[i]; b < fblock_first[i + 1]; ++b) R.absorbed += hpart[b];
     }
-    std::vector<double> esc_c(n_probs, 0.0), trn_c(n_probs, 0.0);
     for (int k = 0; k < n_sg; ++k) {
       const SgKey& K = keys[k];
       moray_result& R = outs[K.prob];
@@ -583,7 +606,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     }
     if (!odev) {
       for (int i = 0; i < n_probs; ++i) {
-        const long long off = prob_cell_off[i], nc = prob_cell_off[i + 1] - off;
+        const long long off = pdev[i].cell_off, nc = pdev[i].n_cells;
         if (!hip_ok(c, hipMemcpy(outs[i].k_ph, obuf + off, nc * 8, hipMemcpyDeviceToHost), "copy results") ||
             !hip_ok(c, hipMemcpy(outs[i].heating, obuf + n_cells + off, nc * 8, hipMemcpyDeviceToHost), "copy results"))
           return MORAY_EDEVICE;
