@@ -12,6 +12,9 @@ constexpr int kWave = 64;
 constexpr int kTraceBlock = 256;
 constexpr int kFinalBlock = 256;
 constexpr int kFinalCellsPerThread = 4;
+constexpr unsigned long long kReserveMax = 256;   // next-level queue slots a wave reserves per atomic
+constexpr uint32_t kNoTree = 0xffffffffu;      // tree index of an empty queue slot
+constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 
 // One uniform grid patch of one problem, in the batch-wide cell numbering.
 struct GridDev {
@@ -97,6 +100,7 @@ struct TraceArgs {
   int chunk;                           // rays claimed per atomic
   int refill;                          // idle lanes that trigger a refill
   unsigned max_steps;                  // hard cap on cells per ray (never reached)
+  unsigned long long reserve;          // next-level slots a wave reserves at once (multiple of 4)
 };
 
 // One finalize block: cells [first, first + count) of one grid.

@@ -368,13 +368,15 @@ struct Tracer {
   }
 
   // Start ray `idx` of this level: from the queue or synthesised as a seed.
-  // Returns false when it starts outside the root grid (escaped at once).
-  __device__ bool start(Ray<R>& L, unsigned long long idx, unsigned long long n_children) const {
+  // Returns kSkip for an unused queue slot, kEscaped when the ray starts
+  // outside the root grid, kStarted otherwise.
+  __device__ int start(Ray<R>& L, unsigned long long idx, unsigned long long n_children) const {
     const int level = a.level;
     double r64;
     if (idx < n_children) {
-      L.pix = a.in.pix[idx];
       L.sg = a.in.sg[idx];
+      if (L.sg == kNoTree) return kSkip;
+      L.pix = a.in.pix[idx];
       r64 = a.in.r[idx];
       L.P = a.in.P[idx];
     } else {
@@ -411,7 +413,7 @@ struct Tracer {
     const double x2 = __dadd_rn(S.sz, __dmul_rn(r64, v[2]));
     const int rc0 = cell_rule(x0, v[0]), rc1 = cell_rule(x1, v[1]), rc2 = cell_rule(x2, v[2]);
     if ((unsigned)rc0 >= (unsigned)Rg.nx || (unsigned)rc1 >= (unsigned)Rg.ny || (unsigned)rc2 >= (unsigned)Rg.nz)
-      return false;
+      return kEscaped;
     const int rlin = (int)Rg.cell_off + rc0 + Rg.nx * (rc1 + Rg.ny * rc2);
     const R k = a.kappa[rlin];
     if (k < (R)0) {
@@ -429,7 +431,7 @@ struct Tracer {
       set_frame(L, root);
       L.kap = k;
     }
-    return true;
+    return kStarted;
   }
 
   // Float64 re-evaluation of the split test for the current cell, in the
@@ -471,20 +473,46 @@ struct Tracer {
   }
 };
 
-template <typename R>
-__device__ __forceinline__ void flush_end(const TraceArgs<R>& a, const Ray<R>& L, int kind) {
-  SgStats& st = a.stats[L.sg];
-  if (L.segs) atomicAdd(&st.segs, (unsigned long long)L.segs);
-  if (kind == 0) {                       // escaped
-    unsafeAtomicAdd(&st.esc_P, L.P);
-    atomicAdd(&st.n_esc, 1ull);
-  } else if (kind == 1) {                // truncated
-    unsafeAtomicAdd(&st.trunc_P, L.P);
-    atomicAdd(&st.n_trunc, 1ull);
-  } else {                               // split
-    atomicAdd(&st.splits, 1ull);
+// Per-lane statistics of the rays a lane has finished, for one tree at a
+// time: flushed to that tree's counters only when the lane moves on to a ray
+// of another tree, and when the launch ends.
+struct Tally {
+  uint32_t sg;
+  unsigned segs, splits, n_esc, n_trunc;
+  double esc_P, trunc_P;
+
+  __device__ void clear(uint32_t tree) {
+    sg = tree;
+    segs = splits = n_esc = n_trunc = 0u;
+    esc_P = trunc_P = 0.0;
   }
-}
+  __device__ void flush(SgStats* stats) const {
+    if (sg == kNoTree) return;
+    SgStats& st = stats[sg];
+    if (segs) atomicAdd(&st.segs, (unsigned long long)segs);
+    if (splits) atomicAdd(&st.splits, (unsigned long long)splits);
+    if (n_esc) {
+      atomicAdd(&st.n_esc, (unsigned long long)n_esc);
+      unsafeAtomicAdd(&st.esc_P, esc_P);
+    }
+    if (n_trunc) {
+      atomicAdd(&st.n_trunc, (unsigned long long)n_trunc);
+      unsafeAtomicAdd(&st.trunc_P, trunc_P);
+    }
+  }
+  // kind: 0 escaped, 1 truncated, 2 split
+  template <typename R>
+  __device__ void end(SgStats* stats, const Ray<R>& L, int kind) {
+    if (L.sg != sg) {
+      flush(stats);
+      clear(L.sg);
+    }
+    segs += L.segs;
+    if (kind == 0) { ++n_esc; esc_P += L.P; }
+    else if (kind == 1) { ++n_trunc; trunc_P += L.P; }
+    else ++splits;
+  }
+};
 
 __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int src) {
   const unsigned lo = __shfl((unsigned)v, src), hi = __shfl((unsigned)(v >> 32), src);
@@ -504,9 +532,12 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   if (total == 0) return;
   const Tracer<R> T(a);
   Ray<R> L;
+  Tally tally;
+  tally.clear(kNoTree);
   bool active = false;
   unsigned steps = 0;
-  unsigned long long w_next = 0, w_end = 0;
+  unsigned long long w_next = 0, w_end = 0;     // the wave's claimed input slots
+  unsigned long long o_next = 0, o_end = 0;     // the wave's reserved output slots
   bool drained = false;
 
   for (;;) {
@@ -528,11 +559,12 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         const bool take = !active && idx < w_end;
         w_next += __popcll(__ballot(take));
         if (take) {
-          if (T.start(L, idx, n_children)) {
+          const int st = T.start(L, idx, n_children);
+          if (st == kStarted) {
             active = true;
             steps = 0;
-          } else {
-            flush_end(a, L, 0);
+          } else if (st == kEscaped) {
+            tally.end(a.stats, L, 0);
           }
         }
       }
@@ -541,38 +573,57 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       if (drained) break;
       continue;
     }
+    // ---- one cell: exit plane, split test, deposit, step ----
+    int ax = 0;
+    bool split = false;
     if (active) {
-      // ---- one cell: exit plane, split test, deposit, step ----
-      const int ax = L.g.exit_axis();
-      const bool split = T.split_test(L, ax);
-      const unsigned long long smask = __ballot(split);
-      if (smask) {
-        const int leader = __ffsll((unsigned long long)smask) - 1;
-        unsigned long long base = 0;
-        if (lane == leader) base = atomicAdd(&a.ctr->count[level + 1], 4ull * (unsigned long long)__popcll(smask));
-        base = bcast64(base, leader);
-        if (split) {
-          const unsigned long long dst = base + 4ull * (unsigned long long)__popcll(smask & below);
-          if (dst + 4 <= a.capacity) {
-            const double Pc = 0.25 * L.P;
-            const double r64 = L.g.radius64();
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-              a.out.pix[dst + k] = 4ull * L.pix + (uint64_t)k;
-              a.out.sg[dst + k] = L.sg;
-              a.out.r[dst + k] = r64;
-              a.out.P[dst + k] = Pc;
-            }
-          } else {
-            atomicOr(&a.ctr->err, kErrOverflow);
-            atomicAdd(&a.ctr->lost_rays, 4ull);
-            unsafeAtomicAdd(&a.ctr->lost_P, L.P);
-          }
-          flush_end(a, L, 2);
-          active = false;
-        }
+      ax = L.g.exit_axis();
+      split = T.split_test(L, ax);
+    }
+    // split children go to the wave's reserved block of the next level's queue;
+    // a fresh block of `reserve` slots costs one atomic per reserve/4 splits (blocks and
+    // requests are multiples of 4, so no parent's children straddle two blocks).
+    // Every lane runs this part so the reservation stays uniform across the wave.
+    const unsigned long long smask = __ballot(split);
+    if (smask) {
+      const unsigned long long need = 4ull * (unsigned long long)__popcll(smask);
+      const unsigned long long rem = o_end - o_next;
+      const unsigned long long grab = need > a.reserve ? need : a.reserve;   // covers need - rem
+      unsigned long long fresh = 0;
+      if (need > rem) {
+        if (lane == 0) fresh = atomicAdd(&a.ctr->count[level + 1], grab);
+        fresh = bcast64(fresh, 0);
       }
-      if (!split) {
+      const unsigned long long k4 = 4ull * (unsigned long long)__popcll(smask & below);
+      const unsigned long long dst = k4 < rem ? o_next + k4 : fresh + (k4 - rem);
+      if (need > rem) {
+        o_next = fresh + (need - rem);
+        o_end = fresh + grab;
+      } else {
+        o_next += need;
+      }
+      if (split) {
+        if (dst + 4 <= a.capacity) {
+          const double Pc = 0.25 * L.P;
+          const double r64 = L.g.radius64();
+#pragma unroll
+          for (int k = 0; k < 4; ++k) {
+            a.out.pix[dst + k] = 4ull * L.pix + (uint64_t)k;
+            a.out.sg[dst + k] = L.sg;
+            a.out.r[dst + k] = r64;
+            a.out.P[dst + k] = Pc;
+          }
+        } else {
+          atomicOr(&a.ctr->err, kErrOverflow);
+          atomicAdd(&a.ctr->lost_rays, 4ull);
+          unsafeAtomicAdd(&a.ctr->lost_P, L.P);
+        }
+        tally.end(a.stats, L, 2);
+        active = false;
+      }
+    }
+    if (active) {
+      {
         const R dr = L.g.chord(ax);
         if (L.g.positive(dr, ax)) {
           const R tau = L.kap * L.sigma * dr;
@@ -601,18 +652,18 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         }
         L.g.step(ax, cnew);
         if (L.P < L.pmin) {
-          flush_end(a, L, 1);
+          tally.end(a.stats, L, 1);
           active = false;
         } else if (++steps > a.max_steps) {
           // cell indices move monotonically, so this bound is never reached by a correct trace
           atomicOr(&a.ctr->err, kErrInternal);
-          flush_end(a, L, 0);
+          tally.end(a.stats, L, 0);
           active = false;
         } else {
           const R k = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
           if (k < (R)0) {
             if (!T.settle(L, ax, dir)) {
-              flush_end(a, L, 0);
+              tally.end(a.stats, L, 0);
               active = false;
             }
           } else {
@@ -622,6 +673,10 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       }
     }
   }
+  tally.flush(a.stats);
+  // unused slots of the wave's last reserved block become empty slots
+  for (unsigned long long i = o_next + lane; i < o_end; i += 64)
+    if (i < a.capacity) a.out.sg[i] = kNoTree;
 }
 
 // ---------------------------------------------------------------------------

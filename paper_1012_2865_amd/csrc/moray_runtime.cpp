@@ -387,7 +387,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   if (!cap) {
     const size_t room = c->budget > c->allocated + fixed ? c->budget - fixed : 0;
     const double fit = (double)room / (double)per_ray;
-    cap = (size_t)std::max(4096.0, std::min({need, fit, 2.0e9}));
+    const double slack = (double)std::max(1, c->num_cu * c->blocks_per_cu) * (kTraceBlock / kWave) * kReserveMax;
+    cap = (size_t)std::max(4096.0, std::min({need + slack, fit, 2.0e9}));
   }
   cap = std::max<size_t>(cap, 256);
 
@@ -469,7 +470,12 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const int n_grids_tot = (int)grids.size();
   Counters* ctr = (Counters*)c->ctr.p;
   SgStats* stats = (SgStats*)c->stats.p;
-  double chunk_limit = (double)cap;
+  // each wave may leave up to one reserved block unused per level: keep that
+  // under an eighth of the queue and plan the trees against the rest
+  const double waves = (double)blocks * (kTraceBlock / kWave);
+  unsigned long long reserve = (unsigned long long)std::min<double>((double)kReserveMax, (double)cap / (8.0 * waves));
+  reserve = std::max<unsigned long long>(4, reserve & ~3ull);
+  double chunk_limit = std::max(1.0, (double)cap - waves * (double)reserve);
   const int max_launches = (max_reach - min_l0 + 1);
 
   for (int attempt = 0;; ++attempt) {
@@ -518,7 +524,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
-          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
+          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<float>(c->stream, blocks, A);
         } else {
           TraceArgs<double> A{};
@@ -526,7 +532,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
-          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps;
+          A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<double>(c->stream, blocks, A);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
