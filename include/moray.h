@@ -73,6 +73,8 @@ typedef struct {
   int chunk_rays;             /* rays a wave claims from the level queue per atomic; 0 = default */
   void* hip_stream;           /* hipStream_t for every launch; NULL = the null stream */
   int profile;                /* nonzero: time every trace-kernel launch with HIP events */
+  int deposit_cache;          /* >= 0: combine deposits in a per-wave LDS table (default);
+                                 < 0: one float64 atomic per segment */
 } moray_init_params;
 
 typedef struct {

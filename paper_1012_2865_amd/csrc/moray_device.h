@@ -15,6 +15,9 @@ constexpr int kFinalCellsPerThread = 4;
 constexpr unsigned long long kReserveMax = 256;   // next-level queue slots a wave reserves per atomic
 constexpr uint32_t kNoTree = 0xffffffffu;      // tree index of an empty queue slot
 constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
+constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries
+constexpr int kCacheEntries = 1 << kCacheLog2;
+constexpr uint32_t kNoSlot = 0xffffffffu;      // empty cache entry
 
 // One uniform grid patch of one problem, in the batch-wide cell numbering.
 struct GridDev {

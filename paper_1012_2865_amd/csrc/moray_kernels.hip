@@ -271,6 +271,7 @@ struct Ray {
   int lin;                // batch-wide cell index
   double P, pmin;
   double* acc;            // acc[lin] is this ray's (problem, group) slot of cell lin
+  uint32_t slot0;         // the same as an index: acc[slot0 + lin]
   R sigma;
   R kap;                  // absorber column per root-cell length of the current cell
   R split_t;              // float path: split when u^2 > split_t; float64 path: 12*4^l (inf: never)
@@ -390,6 +391,7 @@ struct Tracer {
     const SgDev& S = a.sgs[L.sg];
     L.pmin = ldexp(S.pmin0, -2 * (level - S.level_init));
     L.acc = a.acc + S.acc_slot;
+    L.slot0 = (uint32_t)S.acc_slot;
     L.segs = 0;
     const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
@@ -519,7 +521,85 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
   return ((unsigned long long)hi << 32) | lo;
 }
 
-template <typename R>
+__device__ __forceinline__ uint32_t cache_index(uint32_t key) {
+  return (key * 0x9E3779B1u) >> (32 - kCacheLog2);
+}
+
+// Deposit combining: each wave keeps a direct-mapped table of (accumulator
+// slot, float64 sum) in LDS. The rays of a wave come from one small patch of
+// HEALPix pixels, so each cell of their cone receives several of their
+// deposits a few steps apart; those add up in LDS and reach the float64
+// accumulator in HBM as one atomic when the entry is evicted or the launch
+// ends. Within an iteration every lane first compares its key, matching lanes
+// add, and only then may a lane claim the entry for a new key (one winner per
+// entry via compare-and-swap), so every deposit lands in its own cell's sum.
+template <bool CACHE>
+struct DepositCache;
+
+template <>
+struct DepositCache<false> {
+  __device__ void init(int) {}
+  __device__ void add(double* acc, uint32_t key, double v, bool has) { if (has) unsafeAtomicAdd(&acc[key], v); }
+  __device__ void flush(double*, int) {}
+};
+
+template <>
+struct DepositCache<true> {
+  uint32_t* key;
+  double* val;
+  __device__ void init(int lane) {
+    __shared__ uint32_t skey[kTraceBlock / kWave][kCacheEntries];
+    __shared__ double sval[kTraceBlock / kWave][kCacheEntries];
+    const int wv = threadIdx.x / kWave;
+    key = skey[wv];
+    val = sval[wv];
+    for (int e = lane; e < kCacheEntries; e += kWave) key[e] = kNoSlot;
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  }
+  // Every lane of the wave calls this (uniform control flow). The phases are
+  // separated by wave barriers: per thread the "add" and "claim" branches are
+  // exclusive, and without a convergent barrier between them the compiler may
+  // merge them into one if/else and run the claims first.
+  __device__ void add(double* acc, uint32_t k_new, double v, bool has) {
+    bool pending = has;
+    while (__ballot(pending)) {
+      uint32_t h = 0, k = kNoSlot;
+      bool match = false;
+      if (pending) {
+        h = cache_index(k_new);
+        k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        match = k == k_new;
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (match) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __builtin_amdgcn_wave_barrier();
+      const bool claim = pending && !match;
+      bool won = false;
+      if (claim) {
+        uint32_t expected = k;
+        won = __hip_atomic_compare_exchange_strong(&key[h], &expected, k_new, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+      }
+      __builtin_amdgcn_wave_barrier();
+      if (won) {
+        const double old = __hip_atomic_load(&val[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        __hip_atomic_store(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        if (k != kNoSlot) unsafeAtomicAdd(&acc[k], old);
+      }
+      __builtin_amdgcn_wave_barrier();
+      pending = claim && !won;
+    }
+  }
+  __device__ void flush(double* acc, int lane) {
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    for (int e = lane; e < kCacheEntries; e += kWave) {
+      const uint32_t k = key[e];
+      if (k != kNoSlot) unsafeAtomicAdd(&acc[k], val[e]);
+    }
+  }
+};
+
+template <typename R, bool CACHE>
 __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a) {
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
@@ -534,6 +614,8 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   Ray<R> L;
   Tally tally;
   tally.clear(kNoTree);
+  DepositCache<CACHE> cache;
+  cache.init(lane);
   bool active = false;
   unsigned steps = 0;
   unsigned long long w_next = 0, w_end = 0;     // the wave's claimed input slots
@@ -622,13 +704,17 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         active = false;
       }
     }
+    bool dep = false;
+    uint32_t dkey = 0;
+    double dval = 0.0;
     if (active) {
       {
         const R dr = L.g.chord(ax);
         if (L.g.positive(dr, ax)) {
           const R tau = L.kap * L.sigma * dr;
-          const double dP = absorb(L.P, tau);
-          unsafeAtomicAdd(&L.acc[L.lin], dP);
+          dval = absorb(L.P, tau);
+          dkey = L.slot0 + (uint32_t)L.lin;
+          dep = true;
           L.segs++;
           L.g.advance(ax);
         }
@@ -672,7 +758,9 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         }
       }
     }
+    cache.add(a.acc, dkey, dval, dep);
   }
+  cache.flush(a.acc, lane);
   tally.flush(a.stats);
   // unused slots of the wave's last reserved block become empty slots
   for (unsigned long long i = o_next + lane; i < o_end; i += 64)
@@ -803,8 +891,9 @@ hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_gr
 }
 
 template <typename R>
-hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args) {
-  hipLaunchKernelGGL(trace_level_kernel<R>, dim3(blocks), dim3(kTraceBlock), 0, s, args);
+hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache) {
+  if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+  else hipLaunchKernelGGL((trace_level_kernel<R, false>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
   return hipGetLastError();
 }
 
@@ -821,13 +910,15 @@ template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, co
                                        double*, Counters*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, double*,
                                         double*, Counters*);
-template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&);
-template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&);
+template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool);
+template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool);
 
-hipError_t trace_occupancy(int precision, int* blocks_per_cu) {
+hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu) {
   if (precision == 0)
-    return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double>, kTraceBlock, 0);
-  return hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float>, kTraceBlock, 0);
+    return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, true>, kTraceBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, false>, kTraceBlock, 0);
+  return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, true>, kTraceBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, false>, kTraceBlock, 0);
 }
 
 }  // namespace moray

@@ -26,10 +26,10 @@ hipError_t launch_reset_levels(hipStream_t, Counters*);
 template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, R*, double*, Counters*);
 template <typename R>
-hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&);
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
-hipError_t trace_occupancy(int precision, int* blocks_per_cu);
+hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
 }  // namespace moray
 
 using namespace moray;
@@ -57,6 +57,7 @@ struct moray_ctx {
   size_t budget = 0;
   size_t queue_cap_user = 0;
   int waves_per_cu = 0, refill = 0, chunk = 0, profile = 0;
+  bool cache = true;
   int num_cu = 0;
   int blocks_per_cu = 1;
   std::string err = "no error";
@@ -231,8 +232,9 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
     delete c;
     return MORAY_EDEVICE;
   }
+  c->cache = p->deposit_cache >= 0;
   int bpc = 1;
-  if (trace_occupancy(c->precision, &bpc) != hipSuccess || bpc < 1) bpc = 1;
+  if (trace_occupancy(c->precision, c->cache, &bpc) != hipSuccess || bpc < 1) bpc = 1;
   c->blocks_per_cu = bpc;
   if (p->waves_per_cu) {
     const int want = std::max(1, p->waves_per_cu / (kTraceBlock / kWave));
@@ -326,6 +328,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     min_l0 = std::min(min_l0, P.params.level_init);
   }
   if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
+  const bool cache_ok = n_acc < (long long)kNoSlot;   // cache keys are 32-bit accumulator indices
 
   // finalize blocks: each covers up to kFinalBlock*kFinalCellsPerThread cells of one grid
   std::vector<FinalBlock> fblocks;
@@ -525,7 +528,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(c->stream, blocks, A);
+          e = launch_trace_level<float>(c->stream, blocks, A, c->cache && cache_ok);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -533,7 +536,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(c->stream, blocks, A);
+          e = launch_trace_level<double>(c->stream, blocks, A, c->cache && cache_ok);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], c->stream);

@@ -208,3 +208,25 @@ def test_queue_too_small_for_one_tree_reports_equeue():
         _check(_run(c, [q])[0], ref, 1e-4, name="fp32 no-split")
     finally:
         M.moray_free(c)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP32_ACC64, M.MORAY_FP64])
+def test_direct_atomics_and_lds_cache_agree(precision):
+    # deposits combined in the per-wave LDS table and deposits sent one atomic
+    # per segment give the same fields (to summation order)
+    probs = [W.lognormal_problem(98, 0, 24, 4), _nested(9)]
+    outs = {}
+    for cache in (0, -1):
+        c = _ctx(precision, deposit_cache=cache)
+        try:
+            outs[cache] = _run(c, probs)
+        finally:
+            M.moray_free(c)
+    for p, a, b in zip(probs, outs[0], outs[-1]):
+        ref = O.trace(p)
+        for res in (a, b):
+            _check(res, ref, 1e-4 if precision == M.MORAY_FP32_ACC64 else 1e-9, name=f"cache p{precision}",
+                   fp64=precision == M.MORAY_FP64)
+        for q in range(len(p.grids)):
+            x, y = _np(a["k_ph"][q]), _np(b["k_ph"][q])
+            assert np.allclose(x, y, rtol=1e-12, atol=1e-15 * y.max())
