@@ -18,6 +18,9 @@ constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries
 constexpr int kCacheEntries = 1 << kCacheLog2;
 constexpr uint32_t kNoSlot = 0xffffffffu;      // empty cache entry
+constexpr int kEvictCap = 256;                 // per-wave buffer of evicted sums (drained at >= 192)
+constexpr int kStageFlush = 16;                // split parents staged before their children are written
+constexpr int kStageCap = kStageFlush + kWave; // one iteration adds at most 64 parents
 
 // One uniform grid patch of one problem, in the batch-wide cell numbering.
 struct GridDev {
@@ -65,12 +68,18 @@ struct SgStats {
   unsigned long long segs, splits, n_esc, n_trunc;
 };
 
+// A level queue is split into up to kSegMax segments of seg_cap slots, each
+// with its own write and claim counters, so the same-address atomics that
+// reserve and claim rays spread over many addresses (a float64 or integer
+// atomic on one address serialises at the memory side).
+constexpr int kSegMax = 64;
+
 struct Counters {
-  unsigned long long count[kLevels];   // rays written to each level queue
-  unsigned long long head[kLevels];    // rays claimed from each level queue
-  unsigned long long lost_rays;        // children dropped on overflow
+  unsigned long long count[kLevels][kSegMax];   // slots written to each segment of each level queue
+  unsigned long long head[kLevels][kSegMax];    // slots claimed from each segment
+  unsigned long long lost_rays;                 // children dropped on overflow
   double lost_P;
-  unsigned int err;                    // bit flags, see kErr*
+  unsigned int err;                             // bit flags, see kErr*
   unsigned int pad;
 };
 
@@ -94,8 +103,9 @@ struct TraceArgs {
   const SgDev* sgs;
   const R* kappa;          // n_H x_HI dx_root per leaf cell; -(child+1) on covered root cells
   double* acc;             // absorbed photons/s per (problem, group, leaf cell)
-  RayQueue in, out;
-  unsigned long long capacity;
+  RayQueue in, out;                    // nseg segments of seg_cap slots each
+  unsigned long long seg_cap;
+  int nseg;
   Counters* ctr;
   SgStats* stats;
   int level;

@@ -368,20 +368,20 @@ struct Tracer {
     return true;
   }
 
-  // Start ray `idx` of this level: from the queue or synthesised as a seed.
+  // Start a ray of this level: queue slot `idx` (child) or seed number `idx`.
   // Returns kSkip for an unused queue slot, kEscaped when the ray starts
   // outside the root grid, kStarted otherwise.
-  __device__ int start(Ray<R>& L, unsigned long long idx, unsigned long long n_children) const {
+  __device__ int start(Ray<R>& L, bool child, unsigned long long idx) const {
     const int level = a.level;
     double r64;
-    if (idx < n_children) {
+    if (child) {
       L.sg = a.in.sg[idx];
       if (L.sg == kNoTree) return kSkip;
       L.pix = a.in.pix[idx];
       r64 = a.in.r[idx];
       L.P = a.in.P[idx];
     } else {
-      const unsigned long long j = idx - n_children;
+      const unsigned long long j = idx;
       const unsigned long long npix = 12ull << (2 * level);
       L.sg = (uint32_t)(a.seed_sg_begin + j / npix);
       L.pix = j % npix;
@@ -525,13 +525,21 @@ __device__ __forceinline__ uint32_t cache_index(uint32_t key) {
   return (key * 0x9E3779B1u) >> (32 - kCacheLog2);
 }
 
+// Every global store or atomic a wave issues stays outstanding in the same
+// in-order counter as its loads, so the next gather of an absorber column
+// may wait for it, and float64 atomics are performed at the memory side. The
+// trace therefore stages its writes in LDS and issues them in bulk: deposits
+// combine in a per-wave cache, evicted sums collect in a per-wave buffer
+// drained 64 atomics per instruction, and split parents collect in a per-wave
+// stage whose children are written together.
+
 // Deposit combining: each wave keeps a direct-mapped table of (accumulator
 // slot, float64 sum) in LDS. The rays of a wave come from one small patch of
 // HEALPix pixels, so each cell of their cone receives several of their
 // deposits a few steps apart; those add up in LDS and reach the float64
-// accumulator in HBM as one atomic when the entry is evicted or the launch
-// ends. Within an iteration every lane first compares its key, matching lanes
-// add, and only then may a lane claim the entry for a new key (one winner per
+// accumulator in HBM only when the entry is evicted or the launch ends.
+// Within an iteration every lane first compares its key, matching lanes add,
+// and only then may a lane claim the entry for a new key (one winner per
 // entry via compare-and-swap), so every deposit lands in its own cell's sum.
 template <bool CACHE>
 struct DepositCache;
@@ -539,7 +547,9 @@ struct DepositCache;
 template <>
 struct DepositCache<false> {
   __device__ void init(int) {}
-  __device__ void add(double* acc, uint32_t key, double v, bool has) { if (has) unsafeAtomicAdd(&acc[key], v); }
+  __device__ void add(double* acc, uint32_t key, double v, bool has, int) { if (has) unsafeAtomicAdd(&acc[key], v); }
+  __device__ bool want_drain() const { return false; }
+  __device__ void drain(double*, int) {}
   __device__ void flush(double*, int) {}
 };
 
@@ -547,22 +557,41 @@ template <>
 struct DepositCache<true> {
   uint32_t* key;
   double* val;
+  uint32_t* ekey;         // evicted sums waiting for their global atomic
+  double* eval;
+  int ecount;             // wave-uniform
+
   __device__ void init(int lane) {
     __shared__ uint32_t skey[kTraceBlock / kWave][kCacheEntries];
     __shared__ double sval[kTraceBlock / kWave][kCacheEntries];
+    __shared__ uint32_t sekey[kTraceBlock / kWave][kEvictCap];
+    __shared__ double seval[kTraceBlock / kWave][kEvictCap];
     const int wv = threadIdx.x / kWave;
     key = skey[wv];
     val = sval[wv];
+    ekey = sekey[wv];
+    eval = seval[wv];
+    ecount = 0;
     for (int e = lane; e < kCacheEntries; e += kWave) key[e] = kNoSlot;
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ bool want_drain() const { return ecount >= kEvictCap - kWave; }
+  // one global atomic instruction per 64 buffered sums
+  __device__ void drain(double* acc, int lane) {
+    __builtin_amdgcn_wave_barrier();
+    for (int i = lane; i < ecount; i += kWave) unsafeAtomicAdd(&acc[ekey[i]], eval[i]);
+    ecount = 0;
+    __builtin_amdgcn_wave_barrier();
   }
   // Every lane of the wave calls this (uniform control flow). The phases are
   // separated by wave barriers: per thread the "add" and "claim" branches are
   // exclusive, and without a convergent barrier between them the compiler may
   // merge them into one if/else and run the claims first.
-  __device__ void add(double* acc, uint32_t k_new, double v, bool has) {
+  __device__ void add(double* acc, uint32_t k_new, double v, bool has, int lane) {
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
     bool pending = has;
     while (__ballot(pending)) {
+      if (ecount > kEvictCap - kWave) drain(acc, lane);     // room for this round's evictions
       uint32_t h = 0, k = kNoSlot;
       bool match = false;
       if (pending) {
@@ -581,21 +610,88 @@ struct DepositCache<true> {
                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
       }
       __builtin_amdgcn_wave_barrier();
+      const bool evict = won && k != kNoSlot;
+      const unsigned long long emask = __ballot(evict);
       if (won) {
         const double old = __hip_atomic_load(&val[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
         __hip_atomic_store(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (k != kNoSlot) unsafeAtomicAdd(&acc[k], old);
+        if (evict) {
+          const int e = ecount + __popcll(emask & below);
+          ekey[e] = k;
+          eval[e] = old;
+        }
       }
+      ecount += __popcll(emask);
       __builtin_amdgcn_wave_barrier();
       pending = claim && !won;
     }
   }
   __device__ void flush(double* acc, int lane) {
-    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    drain(acc, lane);
     for (int e = lane; e < kCacheEntries; e += kWave) {
       const uint32_t k = key[e];
       if (k != kNoSlot) unsafeAtomicAdd(&acc[k], val[e]);
     }
+  }
+};
+
+// Split parents waiting for their children to be written: the children of a
+// stage go to the wave's home segment of the next level's queue in one
+// reservation and coalesced stores (lane c writes child c), four consecutive
+// records per parent.
+struct SplitStage {
+  uint64_t* pix;
+  uint32_t* sg;
+  double* r;
+  double* P;
+  int count;                                    // wave-uniform
+  unsigned long long o_next, o_end;             // the wave's reserved slots of its home segment
+
+  __device__ void init() {
+    __shared__ uint64_t spix[kTraceBlock / kWave][kStageCap];
+    __shared__ uint32_t ssg[kTraceBlock / kWave][kStageCap];
+    __shared__ double sr[kTraceBlock / kWave][kStageCap];
+    __shared__ double sP[kTraceBlock / kWave][kStageCap];
+    const int wv = threadIdx.x / kWave;
+    pix = spix[wv]; sg = ssg[wv]; r = sr[wv]; P = sP[wv];
+    count = 0;
+    o_next = o_end = 0;
+  }
+  template <typename R>
+  __device__ void write(const TraceArgs<R>& a, int home, int lane) {
+    __builtin_amdgcn_wave_barrier();
+    const unsigned long long need = 4ull * (unsigned long long)count;
+    const unsigned long long rem = o_end - o_next;
+    const unsigned long long grab = need > a.reserve ? need : a.reserve;
+    unsigned long long fresh = 0;
+    if (need > rem) {
+      if (lane == 0) fresh = atomicAdd(&a.ctr->count[a.level + 1][home], grab);
+      fresh = bcast64(fresh, 0);
+    }
+    const unsigned long long base = (unsigned long long)home * a.seg_cap;
+    for (unsigned long long c = lane; c < need; c += kWave) {
+      const int p = (int)(c >> 2);
+      const unsigned long long d = c < rem ? o_next + c : fresh + (c - rem);
+      const double Pc = 0.25 * P[p];
+      if (d < a.seg_cap) {
+        a.out.pix[base + d] = 4ull * pix[p] + (c & 3);
+        a.out.sg[base + d] = sg[p];
+        a.out.r[base + d] = r[p];
+        a.out.P[base + d] = Pc;
+      } else {
+        atomicOr(&a.ctr->err, kErrOverflow);
+        atomicAdd(&a.ctr->lost_rays, 1ull);
+        unsafeAtomicAdd(&a.ctr->lost_P, Pc);
+      }
+    }
+    if (need > rem) {
+      o_next = fresh + (need - rem);
+      o_end = fresh + grab;
+    } else {
+      o_next += need;
+    }
+    count = 0;
+    __builtin_amdgcn_wave_barrier();
   }
 };
 
@@ -605,43 +701,71 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if (a.ctr->err & kErrBadInput) return;
   const int level = a.level;
-  const unsigned long long n_children = min(a.ctr->count[level], a.capacity);
-  const unsigned long long n_seeds =
-      (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * (12ull << (2 * level));
-  const unsigned long long total = n_children + n_seeds;
-  if (total == 0) return;
+  const int K = a.nseg;
+  const unsigned long long npix = 12ull << (2 * level);
+  const unsigned long long n_seeds = (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * npix;
+  const unsigned long long* cnt_in = a.ctr->count[level];
+  unsigned long long* head_in = a.ctr->head[level];
+  // the wave's home segment: it claims there first and writes children there
+  const int home = (int)((blockIdx.x * (kTraceBlock / kWave) + threadIdx.x / kWave) % (unsigned)K);
   const Tracer<R> T(a);
   Ray<R> L;
   Tally tally;
   tally.clear(kNoTree);
   DepositCache<CACHE> cache;
   cache.init(lane);
+  SplitStage stage;
+  stage.init();
   bool active = false;
   unsigned steps = 0;
-  unsigned long long w_next = 0, w_end = 0;     // the wave's claimed input slots
-  unsigned long long o_next = 0, o_end = 0;     // the wave's reserved output slots
+  // the wave's current claim: [w_next, w_end) of segment w_seg, whose first
+  // w_nch indices are queue slots and the rest seed numbers from w_slo on
+  unsigned long long w_next = 0, w_end = 0, w_nch = 0, w_slo = 0;
+  int w_seg = home, visited = 0;
   bool drained = false;
 
   for (;;) {
-    // ---- refill idle lanes from the wave's chunk of the level queue ----
+    // ---- refill idle lanes from the wave's claim on the level queue ----
     unsigned long long idle = __ballot(!active);
     if (!drained && idle && (__popcll(idle) >= a.refill || idle == ~0ull)) {
       for (;;) {
         idle = __ballot(!active);
         if (!idle) break;
         if (w_next >= w_end) {
-          unsigned long long b = 0;
-          if (lane == 0) b = atomicAdd(&a.ctr->head[level], (unsigned long long)a.chunk);
-          b = bcast64(b, 0);
-          if (b >= total) { drained = true; break; }
-          w_next = b;
-          w_end = min(b + (unsigned long long)a.chunk, total);
+          // claim from the current segment; move on once it is exhausted
+          bool got = false;
+          while (visited < K) {
+            const int s = w_seg;
+            const unsigned long long nch = min(cnt_in[s], a.seg_cap);
+            const unsigned long long slo = ((unsigned long long)s * n_seeds) / (unsigned long long)K;
+            const unsigned long long shi = ((unsigned long long)(s + 1) * n_seeds) / (unsigned long long)K;
+            const unsigned long long size = nch + (shi - slo);
+            const unsigned long long seen = __hip_atomic_load(&head_in[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (seen < size) {
+              unsigned long long b = 0;
+              if (lane == 0) b = atomicAdd(&head_in[s], (unsigned long long)a.chunk);
+              b = bcast64(b, 0);
+              if (b < size) {
+                w_nch = nch;
+                w_slo = slo;
+                w_next = b;
+                w_end = min(b + (unsigned long long)a.chunk, size);
+                got = true;
+                break;
+              }
+            }
+            w_seg = (s + 1 == K) ? 0 : s + 1;
+            ++visited;
+          }
+          if (!got) { drained = true; break; }
         }
         const unsigned long long idx = w_next + __popcll(idle & below);
         const bool take = !active && idx < w_end;
         w_next += __popcll(__ballot(take));
         if (take) {
-          const int st = T.start(L, idx, n_children);
+          const bool child = idx < w_nch;
+          const unsigned long long q = child ? (unsigned long long)w_seg * a.seg_cap + idx : w_slo + (idx - w_nch);
+          const int st = T.start(L, child, q);
           if (st == kStarted) {
             active = true;
             steps = 0;
@@ -662,109 +786,82 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       ax = L.g.exit_axis();
       split = T.split_test(L, ax);
     }
-    // split children go to the wave's reserved block of the next level's queue;
-    // a fresh block of `reserve` slots costs one atomic per reserve/4 splits (blocks and
-    // requests are multiples of 4, so no parent's children straddle two blocks).
-    // Every lane runs this part so the reservation stays uniform across the wave.
     const unsigned long long smask = __ballot(split);
     if (smask) {
-      const unsigned long long need = 4ull * (unsigned long long)__popcll(smask);
-      const unsigned long long rem = o_end - o_next;
-      const unsigned long long grab = need > a.reserve ? need : a.reserve;   // covers need - rem
-      unsigned long long fresh = 0;
-      if (need > rem) {
-        if (lane == 0) fresh = atomicAdd(&a.ctr->count[level + 1], grab);
-        fresh = bcast64(fresh, 0);
-      }
-      const unsigned long long k4 = 4ull * (unsigned long long)__popcll(smask & below);
-      const unsigned long long dst = k4 < rem ? o_next + k4 : fresh + (k4 - rem);
-      if (need > rem) {
-        o_next = fresh + (need - rem);
-        o_end = fresh + grab;
-      } else {
-        o_next += need;
-      }
       if (split) {
-        if (dst + 4 <= a.capacity) {
-          const double Pc = 0.25 * L.P;
-          const double r64 = L.g.radius64();
-#pragma unroll
-          for (int k = 0; k < 4; ++k) {
-            a.out.pix[dst + k] = 4ull * L.pix + (uint64_t)k;
-            a.out.sg[dst + k] = L.sg;
-            a.out.r[dst + k] = r64;
-            a.out.P[dst + k] = Pc;
-          }
-        } else {
-          atomicOr(&a.ctr->err, kErrOverflow);
-          atomicAdd(&a.ctr->lost_rays, 4ull);
-          unsafeAtomicAdd(&a.ctr->lost_P, L.P);
-        }
+        const int e = stage.count + __popcll(smask & below);
+        stage.pix[e] = L.pix;
+        stage.sg[e] = L.sg;
+        stage.r[e] = L.g.radius64();
+        stage.P[e] = L.P;
         tally.end(a.stats, L, 2);
         active = false;
       }
+      stage.count += __popcll(smask);
     }
     bool dep = false;
     uint32_t dkey = 0;
     double dval = 0.0;
     if (active) {
-      {
-        const R dr = L.g.chord(ax);
-        if (L.g.positive(dr, ax)) {
-          const R tau = L.kap * L.sigma * dr;
-          dval = absorb(L.P, tau);
-          dkey = L.slot0 + (uint32_t)L.lin;
-          dep = true;
-          L.segs++;
-          L.g.advance(ax);
-        }
-        // step across the exit face
-        int dir, cnew, nax;
-        if (ax == 0) {
-          dir = L.g.dirf(0) > 0.0f ? 1 : -1;
-          cnew = (L.c0 += dir);
-          nax = L.n0;
-          L.lin += dir;
-        } else if (ax == 1) {
-          dir = L.g.dirf(1) > 0.0f ? 1 : -1;
-          cnew = (L.c1 += dir);
-          nax = L.n1;
-          L.lin += dir * L.n0;
-        } else {
-          dir = L.g.dirf(2) > 0.0f ? 1 : -1;
-          cnew = (L.c2 += dir);
-          nax = L.n2;
-          L.lin += dir * L.n0 * L.n1;
-        }
-        L.g.step(ax, cnew);
-        if (L.P < L.pmin) {
-          tally.end(a.stats, L, 1);
-          active = false;
-        } else if (++steps > a.max_steps) {
-          // cell indices move monotonically, so this bound is never reached by a correct trace
-          atomicOr(&a.ctr->err, kErrInternal);
-          tally.end(a.stats, L, 0);
-          active = false;
-        } else {
-          const R k = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
-          if (k < (R)0) {
-            if (!T.settle(L, ax, dir)) {
-              tally.end(a.stats, L, 0);
-              active = false;
-            }
-          } else {
-            L.kap = k;
+      const R dr = L.g.chord(ax);
+      if (L.g.positive(dr, ax)) {
+        const R tau = L.kap * L.sigma * dr;
+        dval = absorb(L.P, tau);
+        dkey = L.slot0 + (uint32_t)L.lin;
+        dep = true;
+        L.segs++;
+        L.g.advance(ax);
+      }
+      // step across the exit face
+      int dir, cnew, nax;
+      if (ax == 0) {
+        dir = L.g.dirf(0) > 0.0f ? 1 : -1;
+        cnew = (L.c0 += dir);
+        nax = L.n0;
+        L.lin += dir;
+      } else if (ax == 1) {
+        dir = L.g.dirf(1) > 0.0f ? 1 : -1;
+        cnew = (L.c1 += dir);
+        nax = L.n1;
+        L.lin += dir * L.n0;
+      } else {
+        dir = L.g.dirf(2) > 0.0f ? 1 : -1;
+        cnew = (L.c2 += dir);
+        nax = L.n2;
+        L.lin += dir * L.n0 * L.n1;
+      }
+      L.g.step(ax, cnew);
+      if (L.P < L.pmin) {
+        tally.end(a.stats, L, 1);
+        active = false;
+      } else if (++steps > a.max_steps) {
+        // cell indices move monotonically, so this bound is never reached by a correct trace
+        atomicOr(&a.ctr->err, kErrInternal);
+        tally.end(a.stats, L, 0);
+        active = false;
+      } else {
+        const R k = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
+        if (k < (R)0) {
+          if (!T.settle(L, ax, dir)) {
+            tally.end(a.stats, L, 0);
+            active = false;
           }
+        } else {
+          L.kap = k;
         }
       }
     }
-    cache.add(a.acc, dkey, dval, dep);
+    cache.add(a.acc, dkey, dval, dep, lane);
+    // bulk writes, only when a buffer is nearly full
+    if (stage.count >= kStageFlush) stage.write(a, home, lane);
+    if (cache.want_drain()) cache.drain(a.acc, lane);
   }
+  if (stage.count) stage.write(a, home, lane);
   cache.flush(a.acc, lane);
   tally.flush(a.stats);
   // unused slots of the wave's last reserved block become empty slots
-  for (unsigned long long i = o_next + lane; i < o_end; i += 64)
-    if (i < a.capacity) a.out.sg[i] = kNoTree;
+  for (unsigned long long i = stage.o_next + lane; i < stage.o_end; i += 64)
+    if (i < a.seg_cap) a.out.sg[(unsigned long long)home * a.seg_cap + i] = kNoTree;
 }
 
 // ---------------------------------------------------------------------------
@@ -781,16 +878,21 @@ __device__ __forceinline__ int grid_of(const GridDev* grids, int n_grids, long l
 
 __global__ void reset_kernel(Counters* ctr, SgStats* stats, int n_sg) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < kLevels * kSegMax) {
+    (&ctr->count[0][0])[i] = 0;
+    (&ctr->head[0][0])[i] = 0;
+  }
   if (i == 0) {
-    for (int l = 0; l < kLevels; ++l) { ctr->count[l] = 0; ctr->head[l] = 0; }
     ctr->lost_rays = 0; ctr->lost_P = 0.0; ctr->err = 0;
   }
   if (i < n_sg) stats[i] = SgStats{0.0, 0.0, 0ull, 0ull, 0ull, 0ull};
 }
 
 __global__ void reset_levels_kernel(Counters* ctr) {
-  const int l = threadIdx.x;
-  if (l < kLevels) { ctr->count[l] = 0; ctr->head[l] = 0; }
+  for (int i = threadIdx.x; i < kLevels * kSegMax; i += blockDim.x) {
+    (&ctr->count[0][0])[i] = 0;
+    (&ctr->head[0][0])[i] = 0;
+  }
 }
 
 // Absorber column per root-cell length, input checks, zeroed accumulators.
@@ -869,13 +971,14 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
 // Host-side launchers (called by the runtime on its stream).
 // ---------------------------------------------------------------------------
 hipError_t launch_reset(hipStream_t s, Counters* ctr, SgStats* stats, int n_sg) {
-  const int blocks = (n_sg > 0 ? n_sg : 1) / 256 + 1;
+  const int n = n_sg > kLevels * kSegMax ? n_sg : kLevels * kSegMax;
+  const int blocks = n / 256 + 1;
   hipLaunchKernelGGL(reset_kernel, dim3(blocks), dim3(256), 0, s, ctr, stats, n_sg);
   return hipGetLastError();
 }
 
 hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
-  hipLaunchKernelGGL(reset_levels_kernel, dim3(1), dim3(64), 0, s, ctr);
+  hipLaunchKernelGGL(reset_levels_kernel, dim3(1), dim3(256), 0, s, ctr);
   return hipGetLastError();
 }
 

@@ -476,6 +476,10 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   // each wave may leave up to one reserved block unused per level: keep that
   // under an eighth of the queue and plan the trees against the rest
   const double waves = (double)blocks * (kTraceBlock / kWave);
+  // level queues in nseg segments (one claim and one write counter each); a
+  // segment serves about waves/nseg waves, so the reserve fraction holds per segment
+  const int nseg = (int)std::min<size_t>(kSegMax, std::max<size_t>(1, cap / 65536));
+  const unsigned long long seg_cap = cap / (size_t)nseg;
   unsigned long long reserve = (unsigned long long)std::min<double>((double)kReserveMax, (double)cap / (8.0 * waves));
   reserve = std::max<unsigned long long>(4, reserve & ~3ull);
   double chunk_limit = std::max(1.0, (double)cap - waves * (double)reserve);
@@ -525,7 +529,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           TraceArgs<float> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
           A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
-          A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<float>(c->stream, blocks, A, c->cache && cache_ok);
@@ -533,7 +537,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
           A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
-          A.capacity = cap; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<double>(c->stream, blocks, A, c->cache && cache_ok);
@@ -588,7 +592,11 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       }
     }
     unsigned long long peak = 0;
-    for (int l = 0; l < kLevels; ++l) peak = std::max(peak, hctr->count[l]);
+    for (int l = 0; l < kLevels; ++l) {
+      unsigned long long n = 0;
+      for (int s = 0; s < nseg; ++s) n += std::min<unsigned long long>(hctr->count[l][s], seg_cap);
+      peak = std::max(peak, n);
+    }
     for (int i = 0; i < n_probs; ++i) {
       moray_result& R = outs[i];
       R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
