@@ -10,6 +10,8 @@ result read-back of each call). The plain float64 path on the same input is
 reported beside it.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
+  python bench.py --counter-pass            (under rocprofv3 --pmc)
+  python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
 
 Prints one JSON line.
 """
@@ -30,6 +32,7 @@ HBM_PEAK_GBS = 8000.0
 BYTES_PER_SEGMENT = {"fp32": 36, "fp64": 40}     # absorber read + two float64 read-modify-writes
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_level.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1012_2865_amd", "csrc", "moray_kernels.hip")
+COPY_BYTES = 1 << 30                              # calibration copy of the counter pass
 
 
 def _workload(name):
@@ -91,6 +94,72 @@ def _traffic(workload, precision):
     return rec["per_launch_bytes"][key]
 
 
+def _counter_pass(workload):
+    """One warm-up and one measured fp32 trace of the workload, then a 1 GiB
+    device-to-device copy whose counter readings calibrate FETCH_SIZE and
+    WRITE_SIZE. Meant to run under `rocprofv3 --pmc`."""
+    import torch
+    from paper_1012_2865_amd import moray as M
+    problems, config = _workload(workload)
+    dev = [M.problem_to_device(p) for p in problems]
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        M.moray_trace(ctx, dev)
+        res = M.moray_trace(ctx, dev)
+    finally:
+        M.moray_free(ctx)
+    a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
+    a.fill_(1.0)
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"counter_pass": config["workload"], "segments": sum(r["segments"] for r in res),
+                      "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES}), flush=True)
+
+
+def _read_counter_csv(folder, counter):
+    """Per-dispatch values of one counter from a rocprofv3 --pmc output folder,
+    in dispatch order: list of (kernel name, value in KiB)."""
+    import csv
+    import glob
+    rows = []
+    for f in sorted(glob.glob(os.path.join(folder, "**", "*counter_collection.csv"), recursive=True)):
+        for r in csv.DictReader(open(f)):
+            if r["Counter_Name"] == counter:
+                rows.append((int(r["Dispatch_Id"]), r["Kernel_Name"], float(r["Counter_Value"])))
+    rows.sort()
+    return [(k, v) for _, k, v in rows]
+
+
+def _write_traffic(fetch_dir, write_dir, workload, launches):
+    """Turn two counter passes into HBM bytes per trace-kernel launch. The
+    trace kernel's dispatches of the second (measured) trace are averaged; the
+    1 GiB copy's reading calibrates KiB per byte moved."""
+    rec = {"kernel_sha256": hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest(), "per_launch_bytes": {}}
+    if os.path.exists(TRAFFIC_FILE):
+        old = json.load(open(TRAFFIC_FILE))
+        if old.get("kernel_sha256") == rec["kernel_sha256"]:
+            rec = old
+    out = {}
+    for name, folder, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        rows = _read_counter_csv(folder, counter)
+        trace = [v for k, v in rows if "trace_level_kernel" in k]
+        if len(trace) < 2 * launches:
+            raise SystemExit(f"{folder}: {len(trace)} trace dispatches, expected {2 * launches}")
+        measured = trace[len(trace) - launches:]
+        other = [v for k, v in rows if "moray" not in k]
+        copy_kib = max(other)
+        factor = COPY_BYTES / (copy_kib * 1024.0)
+        out[name] = {"kib_per_launch": sum(measured) / launches, "copy_kib": copy_kib, "bytes_per_byte": factor,
+                     "bytes_per_launch": sum(measured) / launches * 1024.0 * factor}
+    key = f"{workload}/fp32"
+    rec["per_launch_bytes"][key] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
+    rec.setdefault("detail", {})[key] = out
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps(out, indent=1))
+
+
 def _cpu_baseline(problems, threads):
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -110,12 +179,22 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("MORAY_CPU_THREADS", "16")))
+    ap.add_argument("--counter-pass", action="store_true",
+                    help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
+    ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
+                    help="host only: turn FETCH_SIZE / WRITE_SIZE pass folders into the traffic record")
     args = ap.parse_args()
+    if args.write_traffic:
+        _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this tracer shards by request or by source; "
               f"--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
+    if args.counter_pass:
+        _counter_pass(args.workload)
+        return
     import torch
     from paper_1012_2865_amd import moray as M
 

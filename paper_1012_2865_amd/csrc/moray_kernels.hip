@@ -583,48 +583,57 @@ struct DepositCache<true> {
     ecount = 0;
     __builtin_amdgcn_wave_barrier();
   }
-  // Every lane of the wave calls this (uniform control flow). The phases are
-  // separated by wave barriers: per thread the "add" and "claim" branches are
-  // exclusive, and without a convergent barrier between them the compiler may
-  // merge them into one if/else and run the claims first.
+  // Every lane of the wave calls this (uniform control flow); one pass per
+  // call. Lanes whose key is in the table add to its sum; the others claim
+  // their entry by compare-and-swap. A winner swaps its deposit in and passes
+  // the entry's old sum to the eviction buffer. A lane that loses the claim
+  // sees the winner's key in the failed swap: if it is its own key (two rays
+  // of one tree entering the same cell) it adds to the new sum once the
+  // winner has swapped, otherwise it passes its deposit to the eviction
+  // buffer. The phases are separated by wave barriers: per thread the
+  // branches are exclusive, and without a convergent barrier between them
+  // the compiler may merge them into one if/else and reorder the LDS ops.
   __device__ void add(double* acc, uint32_t k_new, double v, bool has, int lane) {
     const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-    bool pending = has;
-    while (__ballot(pending)) {
-      if (ecount > kEvictCap - kWave) drain(acc, lane);     // room for this round's evictions
-      uint32_t h = 0, k = kNoSlot;
-      bool match = false;
-      if (pending) {
-        h = cache_index(k_new);
-        k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        match = k == k_new;
-      }
-      __builtin_amdgcn_wave_barrier();
-      if (match) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __builtin_amdgcn_wave_barrier();
-      const bool claim = pending && !match;
-      bool won = false;
-      if (claim) {
-        uint32_t expected = k;
-        won = __hip_atomic_compare_exchange_strong(&key[h], &expected, k_new, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-      }
-      __builtin_amdgcn_wave_barrier();
-      const bool evict = won && k != kNoSlot;
-      const unsigned long long emask = __ballot(evict);
-      if (won) {
-        const double old = __hip_atomic_load(&val[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        __hip_atomic_store(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (evict) {
-          const int e = ecount + __popcll(emask & below);
-          ekey[e] = k;
-          eval[e] = old;
-        }
-      }
-      ecount += __popcll(emask);
-      __builtin_amdgcn_wave_barrier();
-      pending = claim && !won;
+    if (!__ballot(has)) return;
+    if (ecount > kEvictCap - kWave) drain(acc, lane);     // room for this call's evictions
+    uint32_t h = 0, k = kNoSlot;
+    bool match = false;
+    if (has) {
+      h = cache_index(k_new);
+      k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      match = k == k_new;
     }
+    __builtin_amdgcn_wave_barrier();
+    if (match) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    __builtin_amdgcn_wave_barrier();
+    const bool claim = has && !match;
+    bool won = false, join = false;
+    if (claim) {
+      uint32_t seen = k;
+      won = __hip_atomic_compare_exchange_strong(&key[h], &seen, k_new, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      join = !won && seen == k_new;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool out = claim && !join && (!won || k != kNoSlot);
+    const unsigned long long omask = __ballot(out);
+    uint32_t ok = k_new;
+    double ov = v;
+    if (won) {
+      // the adds of this call precede the exchange, so the old sum is complete
+      ov = __hip_atomic_exchange(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      ok = k;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (join) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (out) {
+      const int e = ecount + __popcll(omask & below);
+      ekey[e] = ok;
+      eval[e] = ov;
+    }
+    ecount += __popcll(omask);
+    __builtin_amdgcn_wave_barrier();
   }
   __device__ void flush(double* acc, int lane) {
     drain(acc, lane);
@@ -799,9 +808,11 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       }
       stage.count += __popcll(smask);
     }
-    bool dep = false;
+    bool dep = false, moved = false;
     uint32_t dkey = 0;
     double dval = 0.0;
+    R knext = (R)0;
+    int s_ax = 0, s_dir = 0;
     if (active) {
       const R dr = L.g.chord(ax);
       if (L.g.positive(dr, ax)) {
@@ -840,18 +851,24 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         tally.end(a.stats, L, 0);
         active = false;
       } else {
-        const R k = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
-        if (k < (R)0) {
-          if (!T.settle(L, ax, dir)) {
-            tally.end(a.stats, L, 0);
-            active = false;
-          }
-        } else {
-          L.kap = k;
-        }
+        // the next cell's absorber column is gathered while the deposit is combined
+        knext = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
+        s_ax = ax;
+        s_dir = dir;
+        moved = true;
       }
     }
     cache.add(a.acc, dkey, dval, dep, lane);
+    if (moved) {
+      if (knext < (R)0) {
+        if (!T.settle(L, s_ax, s_dir)) {
+          tally.end(a.stats, L, 0);
+          active = false;
+        }
+      } else {
+        L.kap = knext;
+      }
+    }
     // bulk writes, only when a buffer is nearly full
     if (stage.count >= kStageFlush) stage.write(a, home, lane);
     if (cache.want_drain()) cache.drain(a.acc, lane);
