@@ -46,19 +46,23 @@ struct ProblemDev {
   int pad;
 };
 
-// One (source, group) ray tree.
+// One (source, group) ray tree, with the shape of its problem's root grid so
+// a ray can start without another table lookup.
 struct SgDev {
   double sx, sy, sz;       // source position, root cells
   double P0;               // photon rate of one seed ray
   double pmin0;            // p_min_frac * P0 (quartered per level below the seeds)
-  double sigma64;          // cross-section, cm^2
-  double four_pi_phi_c;    // 4 pi phi_c of its problem
   long long acc_slot;      // accumulator of cell c (batch numbering) is acc[acc_slot + c]
   float sigma32;
   float split_t2_base;     // 12 / (4 pi phi_c), float; FLT_MAX when the problem never splits
-  int problem;
   int level_init;
   int level_max;
+  int root_grid;           // grid-table index of the problem's root grid
+  int rnx, rny, rnz;       // its shape
+  long long rcell_off;     // its first cell
+  double sigma64;          // cross-section, cm^2
+  double four_pi_phi_c;    // 4 pi phi_c of its problem
+  int problem;
   int pad;
 };
 

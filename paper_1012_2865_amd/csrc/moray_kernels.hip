@@ -45,16 +45,19 @@ __device__ __forceinline__ uint64_t compact_even_bits(uint64_t x) {
   return x;
 }
 
-__device__ void healpix_dir(int level, uint64_t pix, double& vx, double& vy, double& vz) {
-  const int64_t ns = (int64_t)1 << level;
+// I is the integer type of the ring arithmetic: every intermediate is below
+// 16 Ns^2, so 32 bits hold it up to level 13.
+template <typename I>
+__device__ __forceinline__ void healpix_dir_t(int level, uint64_t pix, double& vx, double& vy, double& vz) {
+  const I ns = (I)1 << level;
   const int face = (int)(pix >> (2 * level));
   const uint64_t ipf = pix & ((1ull << (2 * level)) - 1ull);
-  const int64_t ix = (int64_t)compact_even_bits(ipf);
-  const int64_t iy = (int64_t)compact_even_bits(ipf >> 1);
+  const I ix = (I)compact_even_bits(ipf);
+  const I iy = (I)compact_even_bits(ipf >> 1);
   const int row = face >> 2;                              // 0 north, 1 equator, 2 south
-  const int64_t jr = (int64_t)(row + 2) * ns - ix - iy - 1;
-  const int64_t jpf = 2 * (face & 3) + (row == 1 ? 0 : 1);
-  int64_t nr;
+  const I jr = (I)(row + 2) * ns - ix - iy - 1;
+  const I jpf = 2 * (face & 3) + (row == 1 ? 0 : 1);
+  I nr;
   int kshift;
   double z, sth;
   if (jr < ns || jr > 3 * ns) {
@@ -66,22 +69,22 @@ __device__ void healpix_dir(int level, uint64_t pix, double& vx, double& vy, dou
     kshift = 0;
   } else {
     nr = ns;
-    const int64_t m = 2 * (2 * ns - jr);
+    const I m = 2 * (2 * ns - jr);
     z = (double)m / (3.0 * (double)ns);
     sth = sqrt((double)(9 * ns * ns - m * m)) / (3.0 * (double)ns);
     kshift = (int)((jr - ns) & 1);
   }
-  int64_t jp = (jpf * nr + ix - iy + 1 + kshift) >> 1;   // the numerator is always even
+  I jp = (jpf * nr + ix - iy + 1 + kshift) >> 1;          // the numerator is always even
   if (jp > 4 * nr) jp -= 4 * nr;
   if (jp < 1) jp += 4 * nr;
-  const int64_t num = 2 * jp - kshift - 1, den = 2 * nr;
-  const int64_t q = num / den, rem = num - q * den;
+  const I num = 2 * jp - kshift - 1, den = 2 * nr;
+  const I q = num / den, rem = num - q * den;
   double c, s;
   if (2 * rem == den) {
     c = s = sqrt(0.5);
   } else {
     const bool low = 2 * rem < den;
-    const int64_t m = low ? rem : den - rem;
+    const I m = low ? rem : den - rem;
     const double beta = ((double)m / (double)den) * (M_PI / 2.0);
     double sb, cb;
     sincos(beta, &sb, &cb);
@@ -98,6 +101,11 @@ __device__ void healpix_dir(int level, uint64_t pix, double& vx, double& vy, dou
   vx = sth * cx;
   vy = sth * cy;
   vz = z;
+}
+
+__device__ void healpix_dir(int level, uint64_t pix, double& vx, double& vy, double& vz) {
+  if (level <= 13) healpix_dir_t<int32_t>(level, pix, vx, vy, vz);
+  else healpix_dir_t<int64_t>(level, pix, vx, vy, vz);
 }
 
 // A point on a cell plane belongs to the upper cell when the direction
@@ -259,7 +267,9 @@ __device__ __forceinline__ double absorb(double& P, float tau) {
   return dP;
 }
 
-// Per-lane ray state.
+// Per-lane ray state. The tree fields (source, photon rates, absorber
+// accumulator, cross-section, root grid) belong to the lane's current tree
+// and are reloaded only when the lane starts a ray of another tree.
 template <typename R>
 struct Ray {
   typename GeomOf<R>::type g;
@@ -270,13 +280,16 @@ struct Ray {
   int n0, n1, n2;         // grid dims
   int lin;                // batch-wide cell index
   double P, pmin;
-  double* acc;            // acc[lin] is this ray's (problem, group) slot of cell lin
-  uint32_t slot0;         // the same as an index: acc[slot0 + lin]
+  uint32_t slot0;         // the ray's (problem, group) accumulator of cell lin is acc[slot0 + lin]
   R sigma;
   R kap;                  // absorber column per root-cell length of the current cell
   R split_t;              // float path: split when u^2 > split_t; float64 path: 12*4^l (inf: never)
   double fpp;             // 4 pi phi_c (float64 path)
   unsigned segs;
+  // the lane's tree
+  uint32_t tree;
+  double sx, sy, sz, P0;
+  int root, rn0, rn1, rn2, rcell;
 };
 
 template <typename R>
@@ -284,20 +297,20 @@ struct Tracer {
   const TraceArgs<R>& a;
   __device__ explicit Tracer(const TraceArgs<R>& args) : a(args) {}
 
-  __device__ void set_frame(Ray<R>& L, int q) const {
+  __device__ void root_frame(Ray<R>& L) const {
+    L.q = L.root;
+    L.n0 = L.rn0; L.n1 = L.rn1; L.n2 = L.rn2;
+    const double sl[3] = {L.sx, L.sy, L.sz};
+    L.g.set_frame(sl, L.c0, L.c1, L.c2, false);
+    L.lin = L.rcell + L.c0 + L.n0 * (L.c1 + L.n1 * L.c2);
+  }
+
+  __device__ void child_frame(Ray<R>& L, int q) const {
     const GridDev& G = a.grids[q];
-    const SgDev& S = a.sgs[L.sg];
     L.q = q;
     L.n0 = G.nx; L.n1 = G.ny; L.n2 = G.nz;
-    double sl[3];
-    if (G.is_child) {
-      sl[0] = 2.0 * (S.sx - (double)G.ox);
-      sl[1] = 2.0 * (S.sy - (double)G.oy);
-      sl[2] = 2.0 * (S.sz - (double)G.oz);
-    } else {
-      sl[0] = S.sx; sl[1] = S.sy; sl[2] = S.sz;
-    }
-    L.g.set_frame(sl, L.c0, L.c1, L.c2, G.is_child != 0);
+    const double sl[3] = {2.0 * (L.sx - (double)G.ox), 2.0 * (L.sy - (double)G.oy), 2.0 * (L.sz - (double)G.oz)};
+    L.g.set_frame(sl, L.c0, L.c1, L.c2, true);
     L.lin = (int)G.cell_off + L.c0 + G.nx * (L.c1 + G.ny * L.c2);
   }
 
@@ -307,10 +320,9 @@ struct Tracer {
   // kept among the two fine cells under the root cell.
   __device__ void enter_child(Ray<R>& L, int ch, int rc0, int rc1, int rc2, int ax, int dir) const {
     const GridDev& G = a.grids[ch];
-    const SgDev& S = a.sgs[L.sg];
     const int rc[3] = {rc0, rc1, rc2};
     const int o[3] = {G.ox, G.oy, G.oz};
-    const double sr[3] = {S.sx, S.sy, S.sz};
+    const double sr[3] = {L.sx, L.sy, L.sz};
     const double r = L.g.radius64();
     int c[3];
 #pragma unroll
@@ -326,15 +338,14 @@ struct Tracer {
       }
     }
     L.c0 = c[0]; L.c1 = c[1]; L.c2 = c[2];
-    set_frame(L, ch);
+    child_frame(L, ch);
   }
 
   // After a step along `ax` by `dir` out of the current grid, or into a root
   // cell covered by a child: find the new leaf cell. Returns false when the
   // ray left the root grid.
   __device__ bool settle(Ray<R>& L, int ax, int dir) const {
-    const GridDev& G = a.grids[L.q];
-    if (!G.is_child) {
+    if (L.q == L.root) {
       if ((unsigned)L.c0 >= (unsigned)L.n0 || (unsigned)L.c1 >= (unsigned)L.n1 || (unsigned)L.c2 >= (unsigned)L.n2)
         return false;
       const R k = a.kappa[L.lin];
@@ -350,49 +361,53 @@ struct Tracer {
       L.kap = a.kappa[L.lin];
       return true;
     }
+    const GridDev& G = a.grids[L.q];
     const int rc0 = G.ox + floor_half(L.c0), rc1 = G.oy + floor_half(L.c1), rc2 = G.oz + floor_half(L.c2);
-    const int root = a.probs[G.problem].root_grid;
-    const GridDev& Rg = a.grids[root];
-    if ((unsigned)rc0 >= (unsigned)Rg.nx || (unsigned)rc1 >= (unsigned)Rg.ny || (unsigned)rc2 >= (unsigned)Rg.nz)
+    if ((unsigned)rc0 >= (unsigned)L.rn0 || (unsigned)rc1 >= (unsigned)L.rn1 || (unsigned)rc2 >= (unsigned)L.rn2)
       return false;
-    const int rlin = (int)Rg.cell_off + rc0 + Rg.nx * (rc1 + Rg.ny * rc2);
+    const int rlin = L.rcell + rc0 + L.rn0 * (rc1 + L.rn1 * rc2);
     const R k = a.kappa[rlin];
     if (k < (R)0) {
       enter_child(L, (int)(-k) - 1, rc0, rc1, rc2, ax, dir);
       L.kap = a.kappa[L.lin];
     } else {
       L.c0 = rc0; L.c1 = rc1; L.c2 = rc2;
-      set_frame(L, root);
+      root_frame(L);
       L.kap = k;
     }
     return true;
   }
 
-  // Start a ray of this level: queue slot `idx` (child) or seed number `idx`.
-  // Returns kSkip for an unused queue slot, kEscaped when the ray starts
-  // outside the root grid, kStarted otherwise.
-  __device__ int start(Ray<R>& L, bool child, unsigned long long idx) const {
-    const int level = a.level;
-    double r64;
+  // A ray starts in three steps:
+  //   fetch  - its queue record (a child) or its tree and pixel (a seed);
+  //   tree   - the tree's constants, unless the lane already holds them;
+  //   locate - direction, start cell and frame, and that cell's absorber column.
+  __device__ void fetch(Ray<R>& L, bool child, unsigned long long idx, double& r64) const {
     if (child) {
       L.sg = a.in.sg[idx];
-      if (L.sg == kNoTree) return kSkip;
       L.pix = a.in.pix[idx];
       r64 = a.in.r[idx];
       L.P = a.in.P[idx];
     } else {
-      const unsigned long long j = idx;
-      const unsigned long long npix = 12ull << (2 * level);
-      L.sg = (uint32_t)(a.seed_sg_begin + j / npix);
-      L.pix = j % npix;
+      const unsigned long long npix = 12ull << (2 * a.level);
+      L.sg = (uint32_t)(a.seed_sg_begin + idx / npix);
+      L.pix = idx % npix;
       r64 = 0.0;
-      L.P = a.sgs[L.sg].P0;
+      L.P = -1.0;                          // the tree's seed rate, set in locate
     }
+  }
+
+  __device__ void load_tree(Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
+    const int level = a.level;
+    L.tree = L.sg;
+    L.sx = S.sx; L.sy = S.sy; L.sz = S.sz;
+    L.P0 = S.P0;
     L.pmin = ldexp(S.pmin0, -2 * (level - S.level_init));
-    L.acc = a.acc + S.acc_slot;
     L.slot0 = (uint32_t)S.acc_slot;
-    L.segs = 0;
+    L.root = S.root_grid;
+    L.rn0 = S.rnx; L.rn1 = S.rny; L.rn2 = S.rnz;
+    L.rcell = (int)S.rcell_off;
     const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.sigma = S.sigma32;
@@ -403,55 +418,73 @@ struct Tracer {
       L.split_t = can_split ? ldexp(12.0, 2 * level) : __builtin_huge_val();
       L.fpp = S.four_pi_phi_c;
     }
+  }
+
+  // Start cell of a fetched ray whose tree constants are loaded. Returns false
+  // when the ray starts outside the root grid; otherwise the ray is framed in
+  // the root cell holding s + r d and `k` receives that cell's column.
+  __device__ bool locate(Ray<R>& L, double r64, R& k) const {
+    if (L.P < 0.0) L.P = L.P0;
+    L.segs = 0;
     double v[3];
-    healpix_dir(level, L.pix, v[0], v[1], v[2]);
+    healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
     L.g.set_dir(v);
     L.g.set_radius(r64);
-    // locate the leaf cell holding s + r d
-    const int root = a.probs[S.problem].root_grid;
-    const GridDev& Rg = a.grids[root];
-    const double x0 = __dadd_rn(S.sx, __dmul_rn(r64, v[0]));
-    const double x1 = __dadd_rn(S.sy, __dmul_rn(r64, v[1]));
-    const double x2 = __dadd_rn(S.sz, __dmul_rn(r64, v[2]));
-    const int rc0 = cell_rule(x0, v[0]), rc1 = cell_rule(x1, v[1]), rc2 = cell_rule(x2, v[2]);
-    if ((unsigned)rc0 >= (unsigned)Rg.nx || (unsigned)rc1 >= (unsigned)Rg.ny || (unsigned)rc2 >= (unsigned)Rg.nz)
-      return kEscaped;
-    const int rlin = (int)Rg.cell_off + rc0 + Rg.nx * (rc1 + Rg.ny * rc2);
-    const R k = a.kappa[rlin];
-    if (k < (R)0) {
-      const int ch = (int)(-k) - 1;
-      const GridDev& G = a.grids[ch];
-      // the fine cell lies under root cell rc (exact in floating point; kept in range regardless)
-      const int f0 = 2 * (rc0 - G.ox), f1 = 2 * (rc1 - G.oy), f2 = 2 * (rc2 - G.oz);
-      L.c0 = min(max(cell_rule(2.0 * (x0 - (double)G.ox), v[0]), f0), f0 + 1);
-      L.c1 = min(max(cell_rule(2.0 * (x1 - (double)G.oy), v[1]), f1), f1 + 1);
-      L.c2 = min(max(cell_rule(2.0 * (x2 - (double)G.oz), v[2]), f2), f2 + 1);
-      set_frame(L, ch);
-      L.kap = a.kappa[L.lin];
-    } else {
-      L.c0 = rc0; L.c1 = rc1; L.c2 = rc2;
-      set_frame(L, root);
+    const double x0 = __dadd_rn(L.sx, __dmul_rn(r64, v[0]));
+    const double x1 = __dadd_rn(L.sy, __dmul_rn(r64, v[1]));
+    const double x2 = __dadd_rn(L.sz, __dmul_rn(r64, v[2]));
+    L.c0 = cell_rule(x0, v[0]); L.c1 = cell_rule(x1, v[1]); L.c2 = cell_rule(x2, v[2]);
+    if ((unsigned)L.c0 >= (unsigned)L.rn0 || (unsigned)L.c1 >= (unsigned)L.rn1 || (unsigned)L.c2 >= (unsigned)L.rn2)
+      return false;
+    root_frame(L);
+    k = a.kappa[L.lin];
+    return true;
+  }
+
+  // The located ray becomes active: in the root cell, or when that cell is
+  // covered by a child grid, in the fine cell under it that holds s + r d
+  // (exact in floating point; kept in range regardless).
+  __device__ void begin(Ray<R>& L, R k) const {
+    if (k >= (R)0) {
       L.kap = k;
+      return;
     }
-    return kStarted;
+    const int ch = (int)(-k) - 1;
+    const GridDev& G = a.grids[ch];
+    const double r64 = L.g.radius64();
+    double v[3];
+    healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
+    const double x0 = __dadd_rn(L.sx, __dmul_rn(r64, v[0]));
+    const double x1 = __dadd_rn(L.sy, __dmul_rn(r64, v[1]));
+    const double x2 = __dadd_rn(L.sz, __dmul_rn(r64, v[2]));
+    const int f0 = 2 * (L.c0 - G.ox), f1 = 2 * (L.c1 - G.oy), f2 = 2 * (L.c2 - G.oz);
+    L.c0 = min(max(cell_rule(2.0 * (x0 - (double)G.ox), v[0]), f0), f0 + 1);
+    L.c1 = min(max(cell_rule(2.0 * (x1 - (double)G.oy), v[1]), f1), f1 + 1);
+    L.c2 = min(max(cell_rule(2.0 * (x2 - (double)G.oz), v[2]), f2), f2 + 1);
+    child_frame(L, ch);
+    L.kap = a.kappa[L.lin];
   }
 
   // Float64 re-evaluation of the split test for the current cell, in the
   // canonical form 12 * 4^l < (4 pi phi_c) * u^2, u = t_exit in local cells.
   __device__ bool split_exact(const Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
-    const GridDev& G = a.grids[L.q];
+    const bool child = L.q != L.root;
+    int o[3] = {0, 0, 0};
+    if (child) {
+      const GridDev& G = a.grids[L.q];
+      o[0] = G.ox; o[1] = G.oy; o[2] = G.oz;
+    }
     double v[3];
     healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
-    const double h = G.is_child ? 2.0 : 1.0;
-    const double s[3] = {S.sx, S.sy, S.sz};
-    const int o[3] = {G.ox, G.oy, G.oz};
+    const double h = child ? 2.0 : 1.0;
+    const double s[3] = {L.sx, L.sy, L.sz};
     const int c[3] = {L.c0, L.c1, L.c2};
     double te = __builtin_huge_val();
 #pragma unroll
     for (int k = 0; k < 3; ++k) {
       if (v[k] == 0.0) continue;
-      const double sl = G.is_child ? h * (s[k] - (double)o[k]) : s[k];
+      const double sl = child ? h * (s[k] - (double)o[k]) : s[k];
       const double b = (double)(c[k] + (v[k] > 0.0 ? 1 : 0));
       const double t = ((b - sl) / v[k]) / h;
       te = t < te ? t : te;
@@ -727,6 +760,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   stage.init();
   bool active = false;
   unsigned steps = 0;
+  L.tree = kNoTree;
   // the wave's current claim: [w_next, w_end) of segment w_seg, whose first
   // w_nch indices are queue slots and the rest seed numbers from w_slo on
   unsigned long long w_next = 0, w_end = 0, w_nch = 0, w_slo = 0;
@@ -735,11 +769,15 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
 
   for (;;) {
     // ---- refill idle lanes from the wave's claim on the level queue ----
-    unsigned long long idle = __ballot(!active);
+    // Every idle lane first gets its queue slot or seed number (claiming as
+    // many chunks as that takes), then all of them start in one pass; lanes
+    // whose slot turns out empty wait for the next refill.
+    const unsigned long long idle = __ballot(!active);
     if (!drained && idle && (__popcll(idle) >= a.refill || idle == ~0ull)) {
-      for (;;) {
-        idle = __ballot(!active);
-        if (!idle) break;
+      unsigned long long left = idle;
+      bool take = false, child = false;
+      unsigned long long q = 0;
+      while (left) {
         if (w_next >= w_end) {
           // claim from the current segment; move on once it is exhausted
           bool got = false;
@@ -768,18 +806,29 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
           }
           if (!got) { drained = true; break; }
         }
-        const unsigned long long idx = w_next + __popcll(idle & below);
-        const bool take = !active && idx < w_end;
-        w_next += __popcll(__ballot(take));
-        if (take) {
-          const bool child = idx < w_nch;
-          const unsigned long long q = child ? (unsigned long long)w_seg * a.seg_cap + idx : w_slo + (idx - w_nch);
-          const int st = T.start(L, child, q);
-          if (st == kStarted) {
+        const unsigned long long idx = w_next + __popcll(left & below);
+        const bool mine = ((left >> lane) & 1ull) && idx < w_end;
+        if (mine) {
+          take = true;
+          child = idx < w_nch;
+          q = child ? (unsigned long long)w_seg * a.seg_cap + idx : w_slo + (idx - w_nch);
+        }
+        const unsigned long long got_mask = __ballot(mine);
+        w_next += __popcll(got_mask);
+        left &= ~got_mask;
+      }
+      if (take) {
+        double r64;
+        T.fetch(L, child, q, r64);
+        if (L.sg != kNoTree) {
+          if (L.sg != L.tree) T.load_tree(L);
+          R k;
+          if (T.locate(L, r64, k)) {
+            T.begin(L, k);
             active = true;
             steps = 0;
-          } else if (st == kEscaped) {
-            tally.end(a.stats, L, 0);
+          } else {
+            tally.end(a.stats, L, 0);     // starts outside the root grid: escaped at once
           }
         }
       }

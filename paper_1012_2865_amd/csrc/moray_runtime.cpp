@@ -374,6 +374,9 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPi * P.params.phi_c)) : FLT_MAX;
     d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
     d.problem = K.prob;
+    d.root_grid = pd.root_grid;
+    d.rnx = grids[pd.root_grid].nx; d.rny = grids[pd.root_grid].ny; d.rnz = grids[pd.root_grid].nz;
+    d.rcell_off = grids[pd.root_grid].cell_off;
     d.level_init = P.params.level_init;
     d.level_max = P.params.phi_c > 0.0 ? P.params.level_max : P.params.level_init;
     sg_bound[k] = level_rays_bound(P);
