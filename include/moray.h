@@ -129,8 +129,12 @@ typedef struct {
   unsigned long long rays_seeded, splits, rays_escaped, rays_truncated;
   unsigned long long peak_level_rays; /* largest level population of this solve's ray queue */
   double trace_ms;            /* summed trace-kernel device time of the call (profile only) */
-  int trace_launches;         /* trace-kernel launches of the call */
+  int trace_launches;         /* trace-kernel launches the problem took part in */
+  double t_admit, t_done;     /* asynchronous solves: CLOCK_MONOTONIC seconds when the problem
+                                 was admitted to the device and when its results were complete */
 } moray_result;
+
+typedef unsigned long long moray_ticket;
 
 /* Create a context on params->device. Returns MORAY_EDEVICE when no GPU is
  * visible or the device cannot be used, MORAY_EINVAL for bad parameters.
@@ -145,7 +149,35 @@ moray_status moray_init(moray_ctx** ctx, const moray_init_params* params);
 moray_status moray_trace(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
                          moray_result* outs);
 
-/* Release every device and host resource of the context (NULL is allowed). */
+/* Serving: queue n_probs problems (n_probs >= 1) for asynchronous tracing and
+ * return at once with a ticket. Not part of the paper's method: this is the
+ * request loop around it. A host thread of the context runs launch
+ * generations of the trace kernel; each generation advances every admitted
+ * problem's rays by one HEALPix level, and problems queued meanwhile are
+ * admitted between generations, in arrival order, as their cells, absorber
+ * columns, accumulators, table slots and ray-queue share fit the context's HBM
+ * budget. Their rays then share the launches with the problems already
+ * running, and a problem leaves as soon as it has no rays left (its k_ph,
+ * heating and totals are written then). A problem's results are the same as
+ * from moray_trace up to the order of floating-point additions into each cell.
+ * Inputs (field arrays, descriptors) and outputs (the moray_result structs and
+ * their buffers) must stay valid until moray_query reports the ticket done.
+ * Returns MORAY_EINVAL for invalid problems (nothing is queued), MORAY_ENOMEM
+ * when the serving pools cannot be created inside the budget; a problem that
+ * cannot fit even alone, or whose fields hold invalid values, completes with
+ * that error on its ticket. While a context has queued or running solves,
+ * moray_trace on it returns MORAY_EBUSY. */
+moray_status moray_trace_async(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
+                               moray_result* outs, moray_ticket* ticket);
+
+/* Wait up to wait_ms milliseconds (0: do not wait, < 0: until done) for a
+ * ticket. Returns MORAY_EBUSY if it is not done yet, otherwise the ticket's
+ * status (MORAY_OK when every problem's results are written), after which the
+ * ticket is forgotten; MORAY_EINVAL for an unknown ticket. */
+moray_status moray_query(moray_ctx* ctx, moray_ticket ticket, int wait_ms);
+
+/* Release every device and host resource of the context (NULL is allowed).
+ * Queued and running asynchronous solves are finished first. */
 void moray_free(moray_ctx* ctx);
 
 /* Description of the last error on this context (never NULL). */

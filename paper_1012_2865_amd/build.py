@@ -25,7 +25,7 @@ COMMON = [
     "-munsafe-fp-atomics",
     # keep the compiler from forming packed-fp32 instructions
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-    "-Wall", "-Wno-unused-result",
+    "-Wall", "-Wno-unused-result", "-pthread",
 ]
 
 
@@ -43,13 +43,13 @@ def build_library(out: str = LIB) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src in ("moray_kernels.hip", "moray_runtime.cpp"):
+    for src in ("moray_kernels.hip", "moray_runtime.cpp", "moray_serve.cpp"):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])
         objs.append(obj)
     tmp = out + ".tmp"
-    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp] + objs)
+    _run([HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-pthread", "-o", tmp] + objs)
     os.replace(tmp, out)
     return out
 

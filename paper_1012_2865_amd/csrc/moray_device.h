@@ -57,13 +57,14 @@ struct SgDev {
   float split_t2_base;     // 12 / (4 pi phi_c), float; FLT_MAX when the problem never splits
   int level_init;
   int level_max;
+  int gen0;                // launch generation of the tree's seed rays: a ray of generation g is at
+                           // HEALPix level level_init + (g - gen0)
   int root_grid;           // grid-table index of the problem's root grid
   int rnx, rny, rnz;       // its shape
   long long rcell_off;     // its first cell
   double sigma64;          // cross-section, cm^2
   double four_pi_phi_c;    // 4 pi phi_c of its problem
   int problem;
-  int pad;
 };
 
 struct SgStats {
@@ -112,8 +113,10 @@ struct TraceArgs {
   int nseg;
   Counters* ctr;
   SgStats* stats;
-  int level;
-  int seed_sg_begin, seed_sg_end;      // trees seeded at this level
+  int gen;                             // launch generation (the HEALPix level in a one-shot solve)
+  int cin, cout;                       // counter rows of the input and output queues
+  int seed_level;                      // HEALPix level of the seed rays of this launch
+  int seed_sg_begin, seed_sg_end;      // trees seeded in this launch
   int chunk;                           // rays claimed per atomic
   int refill;                          // idle lanes that trigger a refill
   unsigned max_steps;                  // hard cap on cells per ray (never reached)

@@ -1,0 +1,75 @@
+// Host-side internals shared by the one-shot runtime (moray_runtime.cpp) and
+// the serving engine (moray_serve.cpp). Not part of the public ABI.
+#pragma once
+#include "moray.h"
+#include "moray_device.h"
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+namespace moray {
+
+// ---- kernel launchers (moray_kernels.hip) ----
+hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
+hipError_t launch_reset_levels(hipStream_t, Counters*);
+hipError_t launch_reset_generation(hipStream_t, Counters*, int cin, int cout);
+hipError_t launch_reset_stats(hipStream_t, SgStats*, int first, int count);
+template <typename R>
+hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
+                       Counters*);
+template <typename R>
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
+hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
+                           const double*, double*, const Counters*);
+hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+};
+
+struct Engine;   // serving engine of a context (moray_serve.cpp)
+
+}  // namespace moray
+
+struct moray_ctx {
+  int device = 0;
+  int precision = MORAY_FP32_ACC64;
+  hipStream_t stream = nullptr;
+  size_t budget = 0;
+  size_t queue_cap_user = 0;
+  int waves_per_cu = 0, refill = 0, chunk = 0, profile = 0;
+  bool cache = true;
+  int num_cu = 0;
+  int blocks_per_cu = 1;
+  std::string err = "no error";
+  size_t allocated = 0;
+  moray::DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial, fields, outs;
+  moray::DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
+  size_t q_cap = 0;
+  void* h_stage = nullptr;
+  size_t h_stage_bytes = 0;
+  std::vector<hipEvent_t> evs;
+  moray::Engine* engine = nullptr;
+};
+
+namespace moray {
+
+moray_status fail(moray_ctx* c, moray_status s, const std::string& msg);
+bool hip_ok(moray_ctx* c, hipError_t e, const char* what);
+void release(moray_ctx* c, DevBuf& b);
+moray_status ensure(moray_ctx* c, DevBuf& b, size_t bytes, const char* what);
+moray_status validate(moray_ctx* c, const moray_problem& P, int pi);
+int reach_level(const moray_problem& P);
+double level_rays_bound(const moray_problem& P);
+
+// serving engine (moray_serve.cpp)
+bool engine_busy(moray_ctx* c);
+void engine_stop(moray_ctx* c);
+
+constexpr double kEvErgConst = 1.602176634e-12;
+constexpr double kPiConst = 3.14159265358979323846;
+
+}  // namespace moray

@@ -288,6 +288,7 @@ struct Ray {
   unsigned segs;
   // the lane's tree
   uint32_t tree;
+  int level;              // HEALPix level of the tree's rays in this launch
   double sx, sy, sz, P0;
   int root, rn0, rn1, rn2, rcell;
 };
@@ -389,7 +390,7 @@ struct Tracer {
       r64 = a.in.r[idx];
       L.P = a.in.P[idx];
     } else {
-      const unsigned long long npix = 12ull << (2 * a.level);
+      const unsigned long long npix = 12ull << (2 * a.seed_level);
       L.sg = (uint32_t)(a.seed_sg_begin + idx / npix);
       L.pix = idx % npix;
       r64 = 0.0;
@@ -399,8 +400,9 @@ struct Tracer {
 
   __device__ void load_tree(Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
-    const int level = a.level;
+    const int level = S.level_init + (a.gen - S.gen0);
     L.tree = L.sg;
+    L.level = level;
     L.sx = S.sx; L.sy = S.sy; L.sz = S.sz;
     L.P0 = S.P0;
     L.pmin = ldexp(S.pmin0, -2 * (level - S.level_init));
@@ -427,7 +429,7 @@ struct Tracer {
     if (L.P < 0.0) L.P = L.P0;
     L.segs = 0;
     double v[3];
-    healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
+    healpix_dir(L.level, L.pix, v[0], v[1], v[2]);
     L.g.set_dir(v);
     L.g.set_radius(r64);
     const double x0 = __dadd_rn(L.sx, __dmul_rn(r64, v[0]));
@@ -453,7 +455,7 @@ struct Tracer {
     const GridDev& G = a.grids[ch];
     const double r64 = L.g.radius64();
     double v[3];
-    healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
+    healpix_dir(L.level, L.pix, v[0], v[1], v[2]);
     const double x0 = __dadd_rn(L.sx, __dmul_rn(r64, v[0]));
     const double x1 = __dadd_rn(L.sy, __dmul_rn(r64, v[1]));
     const double x2 = __dadd_rn(L.sz, __dmul_rn(r64, v[2]));
@@ -476,7 +478,7 @@ struct Tracer {
       o[0] = G.ox; o[1] = G.oy; o[2] = G.oz;
     }
     double v[3];
-    healpix_dir(a.level, L.pix, v[0], v[1], v[2]);
+    healpix_dir(L.level, L.pix, v[0], v[1], v[2]);
     const double h = child ? 2.0 : 1.0;
     const double s[3] = {L.sx, L.sy, L.sz};
     const int c[3] = {L.c0, L.c1, L.c2};
@@ -490,7 +492,7 @@ struct Tracer {
       te = t < te ? t : te;
     }
     const double u = te * h;
-    return ldexp(12.0, 2 * a.level) < S.four_pi_phi_c * (u * u);
+    return ldexp(12.0, 2 * L.level) < S.four_pi_phi_c * (u * u);
   }
 
   __device__ bool split_test(const Ray<R>& L, int ax) const {
@@ -707,7 +709,7 @@ struct SplitStage {
     const unsigned long long grab = need > a.reserve ? need : a.reserve;
     unsigned long long fresh = 0;
     if (need > rem) {
-      if (lane == 0) fresh = atomicAdd(&a.ctr->count[a.level + 1][home], grab);
+      if (lane == 0) fresh = atomicAdd(&a.ctr->count[a.cout][home], grab);
       fresh = bcast64(fresh, 0);
     }
     const unsigned long long base = (unsigned long long)home * a.seg_cap;
@@ -742,12 +744,11 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   if (a.ctr->err & kErrBadInput) return;
-  const int level = a.level;
   const int K = a.nseg;
-  const unsigned long long npix = 12ull << (2 * level);
+  const unsigned long long npix = 12ull << (2 * a.seed_level);
   const unsigned long long n_seeds = (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * npix;
-  const unsigned long long* cnt_in = a.ctr->count[level];
-  unsigned long long* head_in = a.ctr->head[level];
+  const unsigned long long* cnt_in = a.ctr->count[a.cin];
+  unsigned long long* head_in = a.ctr->head[a.cin];
   // the wave's home segment: it claims there first and writes children there
   const int home = (int)((blockIdx.x * (kTraceBlock / kWave) + threadIdx.x / kWave) % (unsigned)K);
   const Tracer<R> T(a);
@@ -961,11 +962,33 @@ __global__ void reset_levels_kernel(Counters* ctr) {
   }
 }
 
+// Before a launch of the serving engine: the input queue's claim counters and
+// the output queue's write counters start at zero; earlier overflow flags are
+// cleared (the host has read them).
+__global__ void reset_generation_kernel(Counters* ctr, int cin, int cout) {
+  for (int s = threadIdx.x; s < kSegMax; s += blockDim.x) {
+    ctr->head[cin][s] = 0;
+    ctr->count[cout][s] = 0;
+  }
+  if (threadIdx.x == 0) {
+    ctr->err &= ~kErrOverflow;
+    ctr->lost_rays = 0;
+    ctr->lost_P = 0.0;
+  }
+}
+
+__global__ void reset_stats_kernel(SgStats* stats, int first, int count) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) stats[first + i] = SgStats{0.0, 0.0, 0ull, 0ull, 0ull, 0ull};
+}
+
 // Absorber column per root-cell length, input checks, zeroed accumulators.
+// `grids` holds the n_grids grids (grid-table indices grid_base...) whose
+// cells fill [cell_begin, cell_end) of the batch-wide numbering.
 template <typename R>
-__global__ void prep_kernel(const GridDev* grids, int n_grids, const ProblemDev* probs, long long n_cells, R* kappa,
-                            double* acc, Counters* ctr) {
-  for (long long c = blockIdx.x * (long long)blockDim.x + threadIdx.x; c < n_cells;
+__global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, const ProblemDev* probs,
+                            long long cell_begin, long long cell_end, R* kappa, double* acc, Counters* ctr) {
+  for (long long c = cell_begin + blockIdx.x * (long long)blockDim.x + threadIdx.x; c < cell_end;
        c += (long long)gridDim.x * blockDim.x) {
     const int g = grid_of(grids, n_grids, c);
     const GridDev& G = grids[g];
@@ -981,7 +1004,7 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, const ProblemDev*
       for (int q = g + 1; q < n_grids && grids[q].is_child && grids[q].problem == G.problem; ++q) {
         const GridDev& C = grids[q];
         if (i >= C.ox && i < C.ox + C.nx / 2 && j >= C.oy && j < C.oy + C.ny / 2 && kk >= C.oz && kk < C.oz + C.nz / 2)
-          k = (R)(-(q + 1));
+          k = (R)(-(grid_base + q + 1));
       }
     }
     kappa[c] = k;
@@ -1043,19 +1066,31 @@ hipError_t launch_reset(hipStream_t s, Counters* ctr, SgStats* stats, int n_sg) 
   return hipGetLastError();
 }
 
+hipError_t launch_reset_generation(hipStream_t s, Counters* ctr, int cin, int cout) {
+  hipLaunchKernelGGL(reset_generation_kernel, dim3(1), dim3(kSegMax), 0, s, ctr, cin, cout);
+  return hipGetLastError();
+}
+
+hipError_t launch_reset_stats(hipStream_t s, SgStats* stats, int first, int count) {
+  if (count < 1) return hipSuccess;
+  hipLaunchKernelGGL(reset_stats_kernel, dim3((count + 255) / 256), dim3(256), 0, s, stats, first, count);
+  return hipGetLastError();
+}
+
 hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
   hipLaunchKernelGGL(reset_levels_kernel, dim3(1), dim3(256), 0, s, ctr);
   return hipGetLastError();
 }
 
 template <typename R>
-hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, const ProblemDev* probs,
-                       long long n_cells, R* kappa, double* acc, Counters* ctr) {
-  long long blocks = (n_cells + 255) / 256;
+hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, int grid_base,
+                       const ProblemDev* probs, long long cell_begin, long long cell_end, R* kappa, double* acc,
+                       Counters* ctr) {
+  long long blocks = (cell_end - cell_begin + 255) / 256;
   if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
   if (blocks < 1) blocks = 1;
-  hipLaunchKernelGGL(prep_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, probs, n_cells, kappa,
-                     acc, ctr);
+  hipLaunchKernelGGL(prep_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, grid_base, probs,
+                     cell_begin, cell_end, kappa, acc, ctr);
   return hipGetLastError();
 }
 
@@ -1075,10 +1110,10 @@ hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, co
   return hipGetLastError();
 }
 
-template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, float*,
-                                       double*, Counters*);
-template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, double*,
-                                        double*, Counters*);
+template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
+                                       long long, float*, double*, Counters*);
+template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
+                                        long long, double*, double*, Counters*);
 template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool);
 template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool);
 

@@ -7,10 +7,7 @@
 // on the context's stream. Trees whose queue estimate exceeds the capacity
 // are traced in chunks sharing the same accumulators; a device overflow flag
 // triggers a retry with smaller chunks.
-#include "moray.h"
-#include "moray_device.h"
-
-#include <hip/hip_runtime.h>
+#include "moray_internal.h"
 
 #include <algorithm>
 #include <cfloat>
@@ -20,29 +17,9 @@
 #include <string>
 #include <vector>
 
-namespace moray {
-hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
-hipError_t launch_reset_levels(hipStream_t, Counters*);
-template <typename R>
-hipError_t launch_prep(hipStream_t, int, const GridDev*, int, const ProblemDev*, long long, R*, double*, Counters*);
-template <typename R>
-hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
-hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
-                           const double*, double*, const Counters*);
-hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
-}  // namespace moray
-
 using namespace moray;
 
 namespace {
-
-constexpr double kEvErg = 1.602176634e-12;
-constexpr double kPi = 3.14159265358979323846;
-
-struct DevBuf {
-  void* p = nullptr;
-  size_t bytes = 0;
-};
 
 struct ChunkPlan {
   int sg_begin, sg_end;
@@ -50,27 +27,7 @@ struct ChunkPlan {
 
 }  // namespace
 
-struct moray_ctx {
-  int device = 0;
-  int precision = MORAY_FP32_ACC64;
-  hipStream_t stream = nullptr;
-  size_t budget = 0;
-  size_t queue_cap_user = 0;
-  int waves_per_cu = 0, refill = 0, chunk = 0, profile = 0;
-  bool cache = true;
-  int num_cu = 0;
-  int blocks_per_cu = 1;
-  std::string err = "no error";
-  size_t allocated = 0;
-  DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial, fields, outs;
-  DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
-  size_t q_cap = 0;
-  void* h_stage = nullptr;
-  size_t h_stage_bytes = 0;
-  std::vector<hipEvent_t> evs;
-};
-
-namespace {
+namespace moray {
 
 moray_status fail(moray_ctx* c, moray_status s, const std::string& msg) {
   if (c) c->err = msg;
@@ -108,7 +65,7 @@ moray_status ensure(moray_ctx* c, DevBuf& b, size_t bytes, const char* what) {
   return MORAY_OK;
 }
 
-bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
+static bool finite_nonneg(double x) { return std::isfinite(x) && x >= 0.0; }
 
 // Host-side checks of everything except field values (checked on the device).
 moray_status validate(moray_ctx* c, const moray_problem& P, int pi) {
@@ -181,7 +138,7 @@ int reach_level(const moray_problem& P) {
   const moray_grid& R = P.grids[0];
   double umax = std::sqrt((double)R.nx * R.nx + (double)R.ny * R.ny + (double)R.nz * R.nz) + 2.0;
   if (P.n_grids > 1) umax *= 2.0;
-  const double k = 4.0 * kPi * T.phi_c * umax * umax;
+  const double k = 4.0 * kPiConst * T.phi_c * umax * umax;
   int l = T.level_init;
   while (l < T.level_max && std::ldexp(12.0, 2 * l) < k) ++l;
   return l;
@@ -201,7 +158,7 @@ double level_rays_bound(const moray_problem& P) {
   return std::min(std::ldexp(12.0, 2 * lr), geo);
 }
 
-}  // namespace
+}  // namespace moray
 
 extern "C" {
 
@@ -257,6 +214,7 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
 
 void moray_free(moray_ctx* c) {
   if (!c) return;
+  engine_stop(c);
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
@@ -283,6 +241,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     if (s != MORAY_OK) return s;
     if (!outs[i].k_ph || !outs[i].heating) return fail(c, MORAY_EINVAL, "result buffers are NULL");
   }
+  if (engine_busy(c)) return fail(c, MORAY_EBUSY, "asynchronous solves are still running on this context");
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
   const bool fdev = flags & MORAY_FIELDS_ON_DEVICE, odev = flags & MORAY_OUT_ON_DEVICE;
   const bool fp32 = c->precision == MORAY_FP32_ACC64;
@@ -303,7 +262,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     pd.cell_off = n_cells;
     pd.eexc_off = (int)eexc.size();
     for (int g = 0; g < P.spectrum->n_groups; ++g)
-      eexc.push_back((P.spectrum->energy_ev[g] - P.spectrum->e_ion_ev) * kEvErg);
+      eexc.push_back((P.spectrum->energy_ev[g] - P.spectrum->e_ion_ev) * kEvErgConst);
     long long steps = 16;
     for (int q = 0; q < P.n_grids; ++q) {
       const moray_grid& G = P.grids[q];
@@ -370,14 +329,15 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     d.pmin0 = P.params.p_min_frac * d.P0;
     d.sigma64 = Sp.sigma_cm2[K.grp];
     d.sigma32 = (float)Sp.sigma_cm2[K.grp];
-    d.four_pi_phi_c = 4.0 * kPi * P.params.phi_c;
-    d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPi * P.params.phi_c)) : FLT_MAX;
+    d.four_pi_phi_c = 4.0 * kPiConst * P.params.phi_c;
+    d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPiConst * P.params.phi_c)) : FLT_MAX;
     d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
     d.problem = K.prob;
     d.root_grid = pd.root_grid;
     d.rnx = grids[pd.root_grid].nx; d.rny = grids[pd.root_grid].ny; d.rnz = grids[pd.root_grid].nz;
     d.rcell_off = grids[pd.root_grid].cell_off;
     d.level_init = P.params.level_init;
+    d.gen0 = P.params.level_init;     // one-shot solve: the launch generation is the HEALPix level
     d.level_max = P.params.phi_c > 0.0 ? P.params.level_max : P.params.level_init;
     sg_bound[k] = level_rays_bound(P);
   }
@@ -513,10 +473,11 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       }
     }
     if (!hip_ok(c, launch_reset(c->stream, ctr, stats, n_sg), "reset")) return MORAY_EDEVICE;
-    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot,
-                                             (ProblemDev*)c->probs.p, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
-                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot,
-                                              (ProblemDev*)c->probs.p, n_cells, (double*)c->kappa.p, (double*)c->acc.p, ctr);
+    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
+                                             (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
+                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
+                                              (ProblemDev*)c->probs.p, 0, n_cells, (double*)c->kappa.p,
+                                              (double*)c->acc.p, ctr);
     if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
     int launches = 0;
     for (const ChunkPlan& ch : chunks) {
@@ -532,7 +493,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           TraceArgs<float> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
           A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
-          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.gen = l; A.cin = l; A.cout = l + 1;
+          A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<float>(c->stream, blocks, A, c->cache && cache_ok);
@@ -540,7 +502,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
           A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
-          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.level = l;
+          A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.gen = l; A.cin = l; A.cout = l + 1;
+          A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<double>(c->stream, blocks, A, c->cache && cache_ok);
@@ -607,6 +570,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       R.peak_level_rays = peak;
       R.trace_ms = trace_ms;
       R.trace_launches = launches;
+      R.t_admit = R.t_done = 0.0;
       for (int b = fblock_first[i]; b < fblock_first[i + 1]; ++b) R.absorbed += hpart[b];
     }
     for (int k = 0; k < n_sg; ++k) {

@@ -70,10 +70,12 @@ class Result(ctypes.Structure):
                 ("truncated", ctypes.c_double), ("segments", ctypes.c_ulonglong), ("rays_seeded", ctypes.c_ulonglong),
                 ("splits", ctypes.c_ulonglong), ("rays_escaped", ctypes.c_ulonglong),
                 ("rays_truncated", ctypes.c_ulonglong), ("peak_level_rays", ctypes.c_ulonglong),
-                ("trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int)]
+                ("trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double)]
 
 
-ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_free", "moray_last_error", "moray_version")
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_trace_async", "moray_query", "moray_free", "moray_last_error",
+                 "moray_version")
 
 _lib = None
 
@@ -89,6 +91,11 @@ def load_library(path: str = LIB_PATH):
         lib.moray_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                     ctypes.POINTER(Result)]
         lib.moray_trace.restype = ctypes.c_int
+        lib.moray_trace_async.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
+                                          ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_ulonglong)]
+        lib.moray_trace_async.restype = ctypes.c_int
+        lib.moray_query.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_int]
+        lib.moray_query.restype = ctypes.c_int
         lib.moray_free.argtypes = [ctypes.c_void_p]
         lib.moray_free.restype = None
         lib.moray_last_error.argtypes = [ctypes.c_void_p]
@@ -148,16 +155,8 @@ def _ptr(a, dtype_np, keep: list):
     return arr.ctypes.data
 
 
-def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False) -> List[dict]:
-    """Trace a batch of problems in one call.
-
-    Each problem is duck-typed: ``grids`` (``n_h``, ``x_hi`` as torch CUDA
-    tensors or numpy arrays of shape (nz, ny, nx); ``dx_cm``, ``parent``,
-    ``offset``), ``sources`` (S x 4), ``spectrum`` (``energy_ev``, ``sigma_cm2``,
-    ``frac``, ``e_ion_ev``), ``params`` (``phi_c``, ``level_init``,
-    ``level_max``, ``p_min_frac``). Returns one dict per problem with ``k_ph``
-    and ``heating`` (lists per grid) and the totals."""
-    lib = load_library()
+def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool):
+    """C structs for a list of problems, plus everything they point into."""
     keep: list = []
     n = len(problems)
     cprobs = (Problem * n)()
@@ -215,11 +214,12 @@ def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escape
             results[i].escaped_sg = esc.ctypes.data_as(dp)
         outs.append((kph, heat, shapes, esc, len(S), len(e)))
     flags = (MORAY_FIELDS_ON_DEVICE if on_dev else 0) | (MORAY_OUT_ON_DEVICE if out_on_device else 0)
-    rc = lib.moray_trace(ctx, cprobs, n, flags, results)
-    if rc != MORAY_OK:
-        raise MorayError(rc, moray_last_error(ctx))
+    return cprobs, results, keep, outs, flags
+
+
+def _unpack(results, outs, want_escaped_sg: bool) -> List[dict]:
     out = []
-    for i in range(n):
+    for i in range(len(outs)):
         kph, heat, shapes, esc, ns, ng = outs[i]
         kl, hl, o = [], [], 0
         for shp in shapes:
@@ -234,6 +234,59 @@ def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escape
             d["escaped_sg"] = esc[:ns * ng].reshape(ns, ng)
         out.append(d)
     return out
+
+
+def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False) -> List[dict]:
+    """Trace a batch of problems in one call.
+
+    Each problem is duck-typed: ``grids`` (``n_h``, ``x_hi`` as torch CUDA
+    tensors or numpy arrays of shape (nz, ny, nx); ``dx_cm``, ``parent``,
+    ``offset``), ``sources`` (S x 4), ``spectrum`` (``energy_ev``, ``sigma_cm2``,
+    ``frac``, ``e_ion_ev``), ``params`` (``phi_c``, ``level_init``,
+    ``level_max``, ``p_min_frac``). Returns one dict per problem with ``k_ph``
+    and ``heating`` (lists per grid) and the totals."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg)
+    rc = lib.moray_trace(ctx, cprobs, len(problems), flags, results)
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return _unpack(results, outs, want_escaped_sg)
+
+
+class Ticket:
+    """A pending asynchronous solve: owns the C structs and buffers the
+    library writes into until the ticket is done."""
+
+    def __init__(self, handle: int, cprobs, results, keep, outs, want_escaped_sg: bool):
+        self.handle = handle
+        self._c = (cprobs, results, keep)
+        self._results, self._outs, self._want = results, outs, want_escaped_sg
+        self.results = None
+
+
+def moray_trace_async(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False) -> Ticket:
+    """Queue problems on the context's serving engine; returns at once."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg)
+    t = ctypes.c_ulonglong()
+    rc = lib.moray_trace_async(ctx, cprobs, len(problems), flags, results, ctypes.byref(t))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return Ticket(t.value, cprobs, results, keep, outs, want_escaped_sg)
+
+
+def moray_query(ctx, ticket: Ticket, wait_ms: int = -1):
+    """Results of a ticket (a list of dicts like moray_trace's), or None while
+    it is still running after wait_ms milliseconds (-1: wait until done)."""
+    if ticket.results is not None:
+        return ticket.results
+    rc = load_library().moray_query(ctx, ticket.handle, int(wait_ms))
+    if rc == MORAY_EBUSY:
+        return None
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    ticket.results = _unpack(ticket._results, ticket._outs, ticket._want)
+    return ticket.results
 
 
 def problem_to_device(problem, device: str = "cuda"):

@@ -73,7 +73,7 @@ int main(void) {
   S(moray_trace_params) O(moray_trace_params, p_min_frac)
   S(moray_problem) O(moray_problem, params)
   S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
-  O(moray_result, trace_ms) O(moray_result, trace_launches)
+  O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done)
   return 0;
 }
 """
@@ -94,3 +94,10 @@ def test_binding_struct_layout_matches_header():
             assert getattr(py[t], f).offset == int(val), key
         else:
             assert ctypes.sizeof(py[key]) == int(val), key
+
+
+def test_async_entry_points_reject_null_context():
+    lib = M.load_library()
+    t = ctypes.c_ulonglong(0)
+    assert lib.moray_trace_async(None, None, 1, 0, None, ctypes.byref(t)) == M.MORAY_EINVAL
+    assert lib.moray_query(None, ctypes.c_ulonglong(1), 0) == M.MORAY_EINVAL
