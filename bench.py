@@ -10,6 +10,7 @@ result read-back of each call). The plain float64 path on the same input is
 reported beside it.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
+  python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
 
@@ -160,6 +161,80 @@ def _write_traffic(fetch_dir, write_dir, workload, launches):
     print(json.dumps(out, indent=1))
 
 
+def _batched_c2(M, steps):
+    """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
+    form traces all of them in one call (one launch sequence) in mixed
+    precision; the plain form calls the float64 path once per problem."""
+    import torch
+    problems, config = _workload("c2")
+    dev = [M.problem_to_device(p) for p in problems]
+    torch.cuda.synchronize()
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        s32, seg32, _ = _time_steps(M, ctx, dev, steps, 1)
+    finally:
+        M.moray_free(ctx)
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
+    try:
+        for p in dev[:4]:
+            M.moray_trace(ctx, [p])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        reps = max(1, steps // 2)
+        seg64 = 0
+        for _ in range(reps):
+            seg64 = 0
+            for p in dev:
+                seg64 += M.moray_trace(ctx, [p])[0]["segments"]
+        torch.cuda.synchronize()
+        s64 = (time.perf_counter() - t0) / reps
+    finally:
+        M.moray_free(ctx)
+    return {"workload": config["workload"], "batched_fp32": {"value": seg32 / s32, "unit": "segments/s",
+                                                             "ms_per_step": s32 * 1e3, "segments": seg32},
+            "plain_fp64": {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3,
+                           "segments": seg64, "form": "one problem per call"},
+            "batched_over_plain": (seg32 / s32) / (seg64 / s64)}
+
+
+def _serving_c3(M, rate_hz, n_requests, horizon_s):
+    """Config 3: Poisson arrivals of requests (edges 32-256, 1-32 sources,
+    Ndot log-U[1e47, 1e51]) on device-resident pooled fields, submitted in
+    real time to the serving engine. Latency = completion - arrival."""
+    import numpy as np
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    pool, reqs = W.config3_pool(rate_hz, n_requests, horizon_s)
+    dev_pool = {e: [M.problem_to_device(W.Problem([g], np.zeros((0, 4)), None, None)).grids[0] for g in gs]
+                for e, gs in pool.items()}
+    torch.cuda.synchronize()
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        # the engine's pools are created by the first request
+        M.moray_query(ctx, M.moray_trace_async(ctx, [W.pooled_problem(dev_pool, reqs[0])]), -1)
+        t0 = time.monotonic()
+        tickets = []
+        for r in reqs:
+            delay = t0 + r.arrival_s - time.monotonic()
+            if delay > 0:
+                time.sleep(delay)
+            tickets.append((r, M.moray_trace_async(ctx, [W.pooled_problem(dev_pool, r)])))
+        lat, segs, done = [], 0, []
+        for r, t in tickets:
+            res = M.moray_query(ctx, t, -1)[0]
+            lat.append(res["t_done"] - (t0 + r.arrival_s))
+            done.append(res["t_done"])
+            segs += res["segments"]
+        span = max(done) - t0
+    finally:
+        M.moray_free(ctx)
+    lat = np.sort(np.asarray(lat)) * 1e3
+    return {"rate_hz": rate_hz, "requests": len(reqs), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "mean_ms": float(lat.mean()),
+            "segments_per_s": segs / span, "makespan_s": span, "dtype": "f32+f64acc",
+            "fields": "device-resident pool, 2 per edge"}
+
+
 def _cpu_baseline(problems, threads):
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -179,6 +254,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("MORAY_CPU_THREADS", "16")))
+    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving measurements")
+    ap.add_argument("--serve-rate", type=float, default=10.0, help="serving measurement: arrivals per second")
+    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--serve-only", action="store_true",
+                    help="print one serving JSON line per --serve-rates value and exit")
+    ap.add_argument("--serve-rates", type=str, default="10,20,50,100,200,500")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
@@ -197,6 +278,10 @@ def main():
         return
     import torch
     from paper_1012_2865_amd import moray as M
+    if args.serve_only:
+        for rate in (float(x) for x in args.serve_rates.split(",")):
+            print(json.dumps(_serving_c3(M, rate, args.serve_requests, 60.0)), flush=True)
+        return
 
     problems, config = _workload(args.workload)
     dev = [M.problem_to_device(p) for p in problems]
@@ -239,10 +324,18 @@ def main():
                "sample": f"{'full workload' if args.workload == 'c1' else 'first 8 of 64 problems'}: "
                          f"{segs} segments in {dt:.1f} s"}
 
+    extras = {}
+    if not args.no_extras:
+        extras["batched_c2"] = _batched_c2(M, max(2, args.steps // 2))
+        print(f"# batched c2: {extras['batched_c2']['batched_over_plain']:.2f}x plain fp64", file=sys.stderr, flush=True)
+        extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
+        print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
+              file=sys.stderr, flush=True)
+
     out = {"metric": METRIC, "value": seg32 / s32, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": s32 * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64acc", "data": "synthetic", "config": config,
-           "segments_per_step": seg32, "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain}
+           "segments_per_step": seg32, "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, **extras}
     print(json.dumps(out), flush=True)
 
 

@@ -112,7 +112,23 @@ struct ServeProblem {
   std::vector<unsigned long long> splits_seen;
   unsigned long long peak = 0;
   double t_admit = 0.0;
+  int restarts = 0;
 };
+
+// Ray-queue share of a problem for admission: the largest level population
+// of one tree measured on lognormal grids of 64^3..256^3 is 6-14 rays per
+// unit of face area (N^2); 4 phi_c per unit, capped by the pixel count,
+// covers it. An underestimate only costs a restart.
+double serve_rays_estimate(const moray_problem& P) {
+  const int lr = reach_level(P);
+  double face = 0.0;
+  for (int q = 0; q < P.n_grids; ++q) {
+    const moray_grid& G = P.grids[q];
+    face += ((double)G.nx * G.ny + (double)G.ny * G.nz + (double)G.nz * G.nx) / 3.0;
+  }
+  const double per_tree = std::min(std::ldexp(12.0, 2 * lr), 4.0 * std::max(P.params.phi_c, 1.0) * face + 256.0);
+  return per_tree * (double)P.n_sources * (double)P.spectrum->n_groups;
+}
 
 }  // namespace
 
@@ -216,7 +232,7 @@ moray_status engine_setup(moray_ctx* c, Engine* E) {
   const double avail = c->budget > c->allocated ? (double)(c->budget - c->allocated) : 0.0;
   const double per_ray = 2.0 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
   E->qcap = c->queue_cap_user ? c->queue_cap_user
-                              : (size_t)std::min(std::max(avail * 0.3 / per_ray, 65536.0), (double)(1u << 27));
+                              : (size_t)std::min(std::max(avail * 0.3 / per_ray, 65536.0), (double)(1u << 28));
   E->qcap = std::max<size_t>(E->qcap, 256);
   E->cells_cap = (long long)std::min(std::max(avail * 0.15 / (double)E->rsz, 65536.0), (double)(1 << 28));
   E->acc_cap = (long long)std::min(std::max(avail * 0.3 / 8.0, 262144.0), (double)(1u << 31));
@@ -699,8 +715,20 @@ bool trip(Engine* E) {
     return false;
   }
   if (E->hctr->err & kErrOverflow) {
-    // children were lost: every running problem starts again, with a smaller queue share
-    std::vector<ServeProblem*> again = E->running;
+    // children were lost: every running problem starts again, with a smaller
+    // queue share; one that overflowed alone, or again and again, cannot be served
+    std::vector<ServeProblem*> again;
+    const bool alone = E->running.size() == 1;
+    for (ServeProblem* p : E->running) {
+      if (alone || ++p->restarts > 4) {
+        E->load -= p->bound;
+        unplace(E, p);
+        finish_ticket(E, p, MORAY_EQUEUE, "ray queue overflowed; raise queue_capacity or the HBM budget");
+        delete p;
+      } else {
+        again.push_back(p);
+      }
+    }
     E->running.clear();
     E->load_frac = std::max(0.02, E->load_frac * 0.5);
     if (!eok(E, launch_reset_generation(s, (Counters*)E->ctr.p, cout, cout), "reset")) {
@@ -771,7 +799,7 @@ ServeProblem* make_problem(const moray_problem& P, unsigned flags, moray_result*
   }
   p->max_steps = (unsigned)std::min<long long>(steps * 2, 1u << 30);
   p->nacc = p->ncells * p->ngroups;
-  p->bound = level_rays_bound(p->prob) * p->ntrees;
+  p->bound = serve_rays_estimate(p->prob);
   return p;
 }
 

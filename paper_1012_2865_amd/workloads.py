@@ -229,6 +229,48 @@ def config3(rate_hz: float, n_requests: int = 2000, horizon_s: float = 60.0, see
     return out
 
 
+@dataclass
+class PooledRequest:
+    """A serving request whose fields come from a shared pool (one of
+    `pool[edge]`), with its own sources."""
+    arrival_s: float
+    edge: int
+    pool_index: int
+    sources: np.ndarray              # float64 (S, 4)
+
+
+def config3_pool(rate_hz: float, n_requests: int = 2000, horizon_s: float = 60.0, pool_per_edge: int = 2,
+                 seed_item: int = 0, edges: Sequence[int] = C3_EDGES):
+    """The serving stream with device-resident fields: `pool_per_edge`
+    lognormal field sets per grid edge (as config 1 otherwise), and Poisson
+    arrivals each naming an edge, a pool entry, 1-32 sources and Ndot
+    log-U[1e47, 1e51]. Returns (pool, requests): pool maps an edge to a list
+    of Grid, requests is a list of PooledRequest."""
+    pool = {}
+    for e in edges:
+        pool[int(e)] = [Grid(lognormal_density(int(e), 1.0, 1e-2, rng_for(3, 900_000 + 10 * int(e) + k, 0)),
+                             rng_for(3, 900_000 + 10 * int(e) + k, 1).uniform(0.5, 1.0, (int(e),) * 3).astype(np.float32),
+                             DX_C1)
+                        for k in range(pool_per_edge)]
+    rng = rng_for(3, seed_item, int(rate_hz * 1000))
+    out: List[PooledRequest] = []
+    t = 0.0
+    for i in range(n_requests):
+        t += rng.exponential(1.0 / rate_hz)
+        if t > horizon_s:
+            break
+        e = int(rng.choice(edges))
+        k = int(rng.integers(0, pool_per_edge))
+        s = int(rng.integers(1, 33))
+        out.append(PooledRequest(t, e, k, random_sources(rng, s, (e, e, e), (47.0, 51.0))))
+    return pool, out
+
+
+def pooled_problem(pool, req: PooledRequest, energies=FOUR_GROUPS_EV) -> Problem:
+    return Problem([pool[req.edge][req.pool_index]], req.sources, hydrogen_spectrum(energies), Params(),
+                   name=f"serve{req.edge}_s{len(req.sources)}")
+
+
 def config4(n_clusters: int = 10, per_cluster: int = 100, root_n: int = 256, sub_root_cells: int = 64,
             sigma_root_cells: float = 8.0) -> Problem:
     """Two-level nested grid: root_n^3 root plus a 2x-refined child of
