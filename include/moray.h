@@ -132,6 +132,8 @@ typedef struct {
   int trace_launches;         /* trace-kernel launches the problem took part in */
   double t_admit, t_done;     /* asynchronous solves: CLOCK_MONOTONIC seconds when the problem
                                  was admitted to the device and when its results were complete */
+  int from_graph;             /* 1 when the call replayed the launch sequence captured for the
+                                 same descriptors (device fields and results, see moray_trace) */
 } moray_result;
 
 typedef unsigned long long moray_ticket;
@@ -145,9 +147,36 @@ moray_status moray_init(moray_ctx** ctx, const moray_init_params* params);
  * of them through the same launch sequence. Inputs are read-only and must stay
  * valid until the call returns; outputs are written only on success (on
  * MORAY_EINVAL they are untouched, on device-side errors their content is
- * undefined). Blocks until the results are complete. */
+ * undefined). Blocks until the results are complete.
+ * With both MORAY_FIELDS_ON_DEVICE and MORAY_OUT_ON_DEVICE (and profiling
+ * off), a call whose descriptors, field and result pointers and settings
+ * equal the previous call's captures its launch sequence in a HIP graph, and
+ * later such calls replay it; field values may change in place between
+ * calls. Any other call drops the captured sequence. */
 moray_status moray_trace(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
                          moray_result* outs);
+
+/* Launch settings chosen by moray_autotune. */
+typedef struct {
+  int chunk_rays;             /* rays a wave claims from a level queue per atomic */
+  int refill_lanes;           /* idle lanes of 64 that make a wave refetch rays */
+  int reserve_rays;           /* next-level queue slots a wave reserves per atomic (split-queue depth) */
+  int waves_per_cu;           /* persistent trace waves per compute unit */
+  double first_ms;            /* fastest solve of the batch with the settings the context had */
+  double best_ms;             /* fastest solve with the chosen settings */
+  int trials;                 /* settings timed */
+} moray_tune_result;
+
+/* Autotuner (not part of the paper's method): time the batch under candidate
+ * launch settings, one coordinate-descent pass over chunk size, refill
+ * threshold, reservation block and waves per compute unit (each setting the
+ * fastest of three solves), and keep the fastest in the context for later
+ * moray_trace calls. Fields as in moray_trace (flags); results go to scratch
+ * device memory. max_trials bounds the settings timed (0 = all candidates).
+ * out may be NULL. Errors as in moray_trace; on error the context keeps the
+ * settings it had. */
+moray_status moray_autotune(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
+                            int max_trials, moray_tune_result* out);
 
 /* Serving: queue n_probs problems (n_probs >= 1) for asynchronous tracing and
  * return at once with a ticket. Not part of the paper's method: this is the

@@ -30,7 +30,8 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
-struct Engine;   // serving engine of a context (moray_serve.cpp)
+struct Engine;     // serving engine of a context (moray_serve.cpp)
+struct PlanHost;   // last one-shot solve and its captured launch sequence (moray_runtime.cpp)
 
 }  // namespace moray
 
@@ -41,6 +42,7 @@ struct moray_ctx {
   size_t budget = 0;
   size_t queue_cap_user = 0;
   int waves_per_cu = 0, refill = 0, chunk = 0, profile = 0;
+  int reserve_user = 0;          // next-level slots a wave reserves at once; 0 = from the queue size
   bool cache = true;
   int num_cu = 0;
   int blocks_per_cu = 1;
@@ -53,6 +55,9 @@ struct moray_ctx {
   size_t h_stage_bytes = 0;
   std::vector<hipEvent_t> evs;
   moray::Engine* engine = nullptr;
+  moray::PlanHost* plan = nullptr;
+  hipStream_t gstream = nullptr;   // stream of captured launch sequences
+  hipEvent_t gev = nullptr;
 };
 
 namespace moray {

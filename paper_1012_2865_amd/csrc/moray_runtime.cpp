@@ -11,6 +11,7 @@
 
 #include <algorithm>
 #include <cfloat>
+#include <chrono>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -24,6 +25,132 @@ namespace {
 struct ChunkPlan {
   int sg_begin, sg_end;
 };
+
+// (source, group) tree of a one-shot solve: its seed level, problem, source and group.
+struct SgKey {
+  int l0, prob, src, grp;
+};
+
+}  // namespace
+
+// What a one-shot solve needs to turn the staged counters into results, kept
+// with the launch sequence captured for the same descriptors.
+struct moray::PlanHost {
+  std::string key;                  // descriptors, settings and buffer pointers of the solve
+  std::vector<SgKey> keys;
+  std::vector<int> fblock_first;
+  int n_sg = 0;
+  size_t nfb = 0;
+  int nseg = 1;
+  unsigned long long seg_cap = 0;
+  int launches = 0;
+  bool valid = false;               // the device tables hold this solve
+  bool no_graph = false;            // capture failed once: run it directly
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+};
+
+namespace {
+
+void drop_graph(PlanHost* ph) {
+  if (ph->exec) (void)hipGraphExecDestroy(ph->exec);
+  if (ph->graph) (void)hipGraphDestroy(ph->graph);
+  ph->exec = nullptr;
+  ph->graph = nullptr;
+}
+
+template <typename T>
+void put(std::string& k, const T& v) {
+  k.append(reinterpret_cast<const char*>(&v), sizeof v);
+}
+
+// Everything a captured launch sequence depends on: problem descriptors,
+// field and output pointers, flags and the context's launch settings.
+std::string plan_key(const moray_ctx* c, const moray_problem* probs, int n, unsigned flags, const moray_result* outs) {
+  std::string k;
+  put(k, n); put(k, flags); put(k, c->precision); put(k, c->chunk); put(k, c->refill); put(k, c->blocks_per_cu);
+  put(k, c->cache); put(k, c->reserve_user); put(k, c->queue_cap_user);
+  for (int i = 0; i < n; ++i) {
+    const moray_problem& P = probs[i];
+    put(k, P.n_grids); put(k, P.n_sources); put(k, P.params);
+    for (int q = 0; q < P.n_grids; ++q) {
+      const moray_grid& G = P.grids[q];
+      put(k, G.nx); put(k, G.ny); put(k, G.nz); put(k, G.dx_cm); put(k, G.parent); put(k, G.offset);
+      put(k, G.n_h); put(k, G.x_hi);
+    }
+    for (int j = 0; j < P.n_sources; ++j) put(k, P.sources[j]);
+    const moray_spectrum& S = *P.spectrum;
+    put(k, S.n_groups); put(k, S.e_ion_ev);
+    for (int g = 0; g < S.n_groups; ++g) {
+      put(k, S.energy_ev[g]); put(k, S.sigma_cm2[g]); put(k, S.photon_frac[g]);
+    }
+    put(k, outs[i].k_ph); put(k, outs[i].heating);
+  }
+  return k;
+}
+
+// Results of a finished solve from the pinned staging area.
+void collect(moray_ctx* c, const PlanHost& ph, const moray_problem* probs, int n_probs, moray_result* outs,
+             double trace_ms) {
+  char* hs = (char*)c->h_stage;
+  const Counters* hctr = (const Counters*)hs;
+  const SgStats* hst = (const SgStats*)(hs + sizeof(Counters));
+  const double* hpart = (const double*)(hs + sizeof(Counters) + ph.n_sg * sizeof(SgStats));
+  unsigned long long peak = 0;
+  for (int l = 0; l < kLevels; ++l) {
+    unsigned long long n = 0;
+    for (int s = 0; s < ph.nseg; ++s) n += std::min<unsigned long long>(hctr->count[l][s], ph.seg_cap);
+    peak = std::max(peak, n);
+  }
+  for (int i = 0; i < n_probs; ++i) {
+    moray_result& R = outs[i];
+    R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
+    R.segments = R.rays_seeded = R.splits = R.rays_escaped = R.rays_truncated = 0;
+    R.peak_level_rays = peak;
+    R.trace_ms = trace_ms;
+    R.trace_launches = ph.launches;
+    R.t_admit = R.t_done = 0.0;
+    R.from_graph = 0;
+    for (int b = ph.fblock_first[i]; b < ph.fblock_first[i + 1]; ++b) R.absorbed += hpart[b];
+  }
+  for (int k = 0; k < ph.n_sg; ++k) {
+    const SgKey& K = ph.keys[k];
+    moray_result& R = outs[K.prob];
+    const moray_problem& P = probs[K.prob];
+    const SgStats& S = hst[k];
+    R.emitted += P.spectrum->photon_frac[K.grp] * P.sources[K.src].ndot;
+    R.escaped += S.esc_P;
+    R.truncated += S.trunc_P;
+    R.segments += S.segs;
+    R.splits += S.splits;
+    R.rays_escaped += S.n_esc;
+    R.rays_truncated += S.n_trunc;
+    R.rays_seeded += (unsigned long long)std::ldexp(12.0, 2 * P.params.level_init);
+    if (R.escaped_sg) R.escaped_sg[K.src * P.spectrum->n_groups + K.grp] = S.esc_P;
+  }
+}
+
+// Replay of the captured launch sequence. Returns MORAY_EQUEUE (and drops the
+// plan) when the replay overflowed, so the caller traces afresh.
+moray_status replay(moray_ctx* c, PlanHost& ph, const moray_problem* probs, int n_probs, moray_result* outs) {
+  if (!hip_ok(c, hipEventRecord(c->gev, c->stream), "event") ||
+      !hip_ok(c, hipStreamWaitEvent(c->gstream, c->gev, 0), "event") ||
+      !hip_ok(c, hipGraphLaunch(ph.exec, c->gstream), "graph launch") ||
+      !hip_ok(c, hipStreamSynchronize(c->gstream), "synchronize"))
+    return MORAY_EDEVICE;
+  const Counters* hctr = (const Counters*)c->h_stage;
+  if (hctr->err & kErrBadInput) return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
+  if (hctr->err & kErrInternal) return fail(c, MORAY_EINTERNAL, "a ray exceeded its step bound");
+  if (hctr->err & kErrOverflow) {
+    drop_graph(&ph);
+    ph.valid = false;
+    return MORAY_EQUEUE;
+  }
+  collect(c, ph, probs, n_probs, outs, 0.0);
+  for (int i = 0; i < n_probs; ++i) outs[i].from_graph = 1;
+  c->err = "no error";
+  return MORAY_OK;
+}
 
 }  // namespace
 
@@ -228,6 +355,12 @@ void moray_free(moray_ctx* c) {
     release(c, c->q_P[i]);
   }
   for (hipEvent_t e : c->evs) (void)hipEventDestroy(e);
+  if (c->plan) {
+    drop_graph(c->plan);
+    delete c->plan;
+  }
+  if (c->gstream) (void)hipStreamSynchronize(c->gstream), (void)hipStreamDestroy(c->gstream);
+  if (c->gev) (void)hipEventDestroy(c->gev);
   if (c->h_stage) (void)hipHostFree(c->h_stage);
   delete c;
 }
@@ -243,6 +376,31 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   }
   if (engine_busy(c)) return fail(c, MORAY_EBUSY, "asynchronous solves are still running on this context");
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
+
+  // Repeated solves of the same descriptors with device-resident fields and
+  // results: the second call captures its launch sequence in a graph, later
+  // calls replay it (fields may change in place between calls).
+  const bool graphable = (flags & MORAY_FIELDS_ON_DEVICE) && (flags & MORAY_OUT_ON_DEVICE) && !c->profile;
+  std::string key;
+  bool capture = false;
+  if (graphable) {
+    key = plan_key(c, probs, n_probs, flags, outs);
+    if (!c->plan) c->plan = new PlanHost();
+    PlanHost& ph = *c->plan;
+    if (ph.valid && ph.key == key) {
+      if (ph.exec) {
+        const moray_status st = replay(c, ph, probs, n_probs, outs);
+        if (st != MORAY_EQUEUE) return st;
+      } else if (!ph.no_graph) {
+        capture = true;
+      }
+    }
+  }
+  if (c->plan && !(capture && c->plan->key == key)) {
+    drop_graph(c->plan);
+    c->plan->valid = false;
+    c->plan->no_graph = false;
+  }
   const bool fdev = flags & MORAY_FIELDS_ON_DEVICE, odev = flags & MORAY_OUT_ON_DEVICE;
   const bool fp32 = c->precision == MORAY_FP32_ACC64;
   const size_t rsz = fp32 ? sizeof(float) : sizeof(double);
@@ -305,9 +463,6 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   }
 
   // (source, group) trees ordered by seed level, then problem, source, group
-  struct SgKey {
-    int l0, prob, src, grp;
-  };
   std::vector<SgKey> keys;
   for (int i = 0; i < n_probs; ++i)
     for (int s = 0; s < probs[i].n_sources; ++s)
@@ -444,11 +599,39 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const int nseg = (int)std::min<size_t>(kSegMax, std::max<size_t>(1, cap / 65536));
   const unsigned long long seg_cap = cap / (size_t)nseg;
   unsigned long long reserve = (unsigned long long)std::min<double>((double)kReserveMax, (double)cap / (8.0 * waves));
+  if (c->reserve_user > 0) reserve = std::min<unsigned long long>((unsigned long long)c->reserve_user, kReserveMax);
   reserve = std::max<unsigned long long>(4, reserve & ~3ull);
   double chunk_limit = std::max(1.0, (double)cap - waves * (double)reserve);
   const int max_launches = (max_reach - min_l0 + 1);
 
+  // pinned staging for the counters, the tree statistics and the partial sums
+  const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + fblocks.size() * 8;
+  if (need_stage > c->h_stage_bytes) {
+    (void)hipHostFree(c->h_stage);
+    c->h_stage = nullptr;
+    if (hipHostMalloc(&c->h_stage, need_stage, hipHostMallocDefault) != hipSuccess) {
+      c->h_stage_bytes = 0;
+      return fail(c, MORAY_ENOMEM, "pinned staging allocation failed");
+    }
+    c->h_stage_bytes = need_stage;
+  }
+  char* hs = (char*)c->h_stage;
+  Counters* hctr = (Counters*)hs;
+  SgStats* hst = (SgStats*)(hs + sizeof(Counters));
+  double* hpart = (double*)(hs + sizeof(Counters) + n_sg * sizeof(SgStats));
+  if (capture) {
+    if (!c->gstream && (!hip_ok(c, hipStreamCreateWithFlags(&c->gstream, hipStreamNonBlocking), "stream") ||
+                        !hip_ok(c, hipEventCreateWithFlags(&c->gev, hipEventDisableTiming), "event")))
+      return MORAY_EDEVICE;
+    // the tables above were uploaded on the context's stream
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")) return MORAY_EDEVICE;
+  }
+
   for (int attempt = 0;; ++attempt) {
+    const bool capturing = capture && attempt == 0;
+    hipStream_t strm = capturing ? c->gstream : c->stream;
+    if (capturing && !hip_ok(c, hipStreamBeginCapture(strm, hipStreamCaptureModeThreadLocal), "capture"))
+      return MORAY_EDEVICE;
     // chunks: consecutive trees whose bounds fit the capacity
     std::vector<ChunkPlan> chunks;
     {
@@ -472,23 +655,23 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         c->evs.push_back(e);
       }
     }
-    if (!hip_ok(c, launch_reset(c->stream, ctr, stats, n_sg), "reset")) return MORAY_EDEVICE;
-    hipError_t e = fp32 ? launch_prep<float>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
+    if (!hip_ok(c, launch_reset(strm, ctr, stats, n_sg), "reset")) return MORAY_EDEVICE;
+    hipError_t e = fp32 ? launch_prep<float>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                              (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
-                        : launch_prep<double>(c->stream, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
+                        : launch_prep<double>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                               (ProblemDev*)c->probs.p, 0, n_cells, (double*)c->kappa.p,
                                               (double*)c->acc.p, ctr);
     if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
     int launches = 0;
     for (const ChunkPlan& ch : chunks) {
-      if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(c->stream, ctr), "reset levels")) return MORAY_EDEVICE;
+      if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(strm, ctr), "reset levels")) return MORAY_EDEVICE;
       for (int l = min_l0; l <= max_reach; ++l) {
         const int lo = std::max(seed_lo[l], ch.sg_begin), hi = std::min(seed_hi[l], ch.sg_end);
         const RayQueue qin{(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (double*)c->q_r[l & 1].p,
                            (double*)c->q_P[l & 1].p};
         const RayQueue qout{(uint64_t*)c->q_pix[(l + 1) & 1].p, (uint32_t*)c->q_sg[(l + 1) & 1].p,
                             (double*)c->q_r[(l + 1) & 1].p, (double*)c->q_P[(l + 1) & 1].p};
-        if (c->profile) (void)hipEventRecord(c->evs[2 * launches], c->stream);
+        if (c->profile) (void)hipEventRecord(c->evs[2 * launches], strm);
         if (fp32) {
           TraceArgs<float> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -497,7 +680,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(c->stream, blocks, A, c->cache && cache_ok);
+          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -506,45 +689,45 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(c->stream, blocks, A, c->cache && cache_ok);
+          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
-        if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], c->stream);
+        if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], strm);
         ++launches;
       }
     }
-    if (!hip_ok(c, launch_finalize(c->stream, (int)fblocks.size(), (GridDev*)c->grids.p, (ProblemDev*)c->probs.p,
+    if (!hip_ok(c, launch_finalize(strm, (int)fblocks.size(), (GridDev*)c->grids.p, (ProblemDev*)c->probs.p,
                                    (FinalBlock*)c->fblocks.p, (double*)c->acc.p, (double*)c->eexc.p,
                                    (double*)c->partial.p, ctr),
                 "finalize"))
       return MORAY_EDEVICE;
 
     // ---- results ----
-    const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + fblocks.size() * 8;
-    if (need_stage > c->h_stage_bytes) {
-      (void)hipHostFree(c->h_stage);
-      c->h_stage = nullptr;
-      if (hipHostMalloc(&c->h_stage, need_stage, hipHostMallocDefault) != hipSuccess) {
-        c->h_stage_bytes = 0;
-        return fail(c, MORAY_ENOMEM, "pinned staging allocation failed");
-      }
-      c->h_stage_bytes = need_stage;
-    }
-    char* hs = (char*)c->h_stage;
-    Counters* hctr = (Counters*)hs;
-    SgStats* hst = (SgStats*)(hs + sizeof(Counters));
-    double* hpart = (double*)(hs + sizeof(Counters) + n_sg * sizeof(SgStats));
-    if (!hip_ok(c, hipMemcpyAsync(hctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, c->stream), "copy") ||
-        (n_sg && !hip_ok(c, hipMemcpyAsync(hst, stats, n_sg * sizeof(SgStats), hipMemcpyDeviceToHost, c->stream), "copy")) ||
+    if (!hip_ok(c, hipMemcpyAsync(hctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, strm), "copy") ||
+        (n_sg && !hip_ok(c, hipMemcpyAsync(hst, stats, n_sg * sizeof(SgStats), hipMemcpyDeviceToHost, strm), "copy")) ||
         (!fblocks.empty() &&
-         !hip_ok(c, hipMemcpyAsync(hpart, c->partial.p, fblocks.size() * 8, hipMemcpyDeviceToHost, c->stream), "copy")) ||
-        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
+         !hip_ok(c, hipMemcpyAsync(hpart, c->partial.p, fblocks.size() * 8, hipMemcpyDeviceToHost, strm), "copy")))
       return MORAY_EDEVICE;
+    if (capturing) {
+      PlanHost& ph = *c->plan;
+      if (!hip_ok(c, hipStreamEndCapture(strm, &ph.graph), "capture") ||
+          !hip_ok(c, hipGraphInstantiate(&ph.exec, ph.graph, nullptr, nullptr, 0), "graph instantiate") ||
+          !hip_ok(c, hipGraphLaunch(ph.exec, strm), "graph launch")) {
+        drop_graph(&ph);
+        ph.no_graph = true;
+        return MORAY_EDEVICE;
+      }
+    }
+    if (!hip_ok(c, hipStreamSynchronize(strm), "synchronize")) return MORAY_EDEVICE;
     if (hctr->err & kErrBadInput) return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
     if (hctr->err & kErrInternal) return fail(c, MORAY_EINTERNAL, "a ray exceeded its step bound");
     if (hctr->err & kErrOverflow) {
       bool single = true;
       for (const ChunkPlan& ch : chunks) single = single && ch.sg_end - ch.sg_begin <= 1;
+      if (c->plan) {
+        drop_graph(c->plan);
+        c->plan->no_graph = true;
+      }
       if (single || attempt >= 6)
         return fail(c, MORAY_EQUEUE, "ray queue overflowed; raise queue_capacity or the HBM budget");
       chunk_limit *= 0.25;   // retry with smaller chunks of trees
@@ -557,37 +740,20 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         if (hipEventElapsedTime(&ms, c->evs[2 * k], c->evs[2 * k + 1]) == hipSuccess) trace_ms += ms;
       }
     }
-    unsigned long long peak = 0;
-    for (int l = 0; l < kLevels; ++l) {
-      unsigned long long n = 0;
-      for (int s = 0; s < nseg; ++s) n += std::min<unsigned long long>(hctr->count[l][s], seg_cap);
-      peak = std::max(peak, n);
+    PlanHost local;
+    PlanHost& ph = graphable ? *c->plan : local;
+    ph.keys = keys;
+    ph.fblock_first = fblock_first;
+    ph.n_sg = n_sg;
+    ph.nfb = fblocks.size();
+    ph.nseg = nseg;
+    ph.seg_cap = seg_cap;
+    ph.launches = launches;
+    if (graphable) {
+      ph.key = key;
+      ph.valid = true;
     }
-    for (int i = 0; i < n_probs; ++i) {
-      moray_result& R = outs[i];
-      R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
-      R.segments = R.rays_seeded = R.splits = R.rays_escaped = R.rays_truncated = 0;
-      R.peak_level_rays = peak;
-      R.trace_ms = trace_ms;
-      R.trace_launches = launches;
-      R.t_admit = R.t_done = 0.0;
-      for (int b = fblock_first[i]; b < fblock_first[i + 1]; ++b) R.absorbed += hpart[b];
-    }
-    for (int k = 0; k < n_sg; ++k) {
-      const SgKey& K = keys[k];
-      moray_result& R = outs[K.prob];
-      const moray_problem& P = probs[K.prob];
-      const SgStats& S = hst[k];
-      R.emitted += P.spectrum->photon_frac[K.grp] * P.sources[K.src].ndot;
-      R.escaped += S.esc_P;
-      R.truncated += S.trunc_P;
-      R.segments += S.segs;
-      R.splits += S.splits;
-      R.rays_escaped += S.n_esc;
-      R.rays_truncated += S.n_trunc;
-      R.rays_seeded += (unsigned long long)std::ldexp(12.0, 2 * P.params.level_init);
-      if (R.escaped_sg) R.escaped_sg[K.src * P.spectrum->n_groups + K.grp] = S.esc_P;
-    }
+    collect(c, ph, probs, n_probs, outs, trace_ms);
     if (!odev) {
       for (int i = 0; i < n_probs; ++i) {
         const long long off = pdev[i].cell_off, nc = pdev[i].n_cells;
@@ -599,6 +765,107 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     c->err = "no error";
     return MORAY_OK;
   }
+}
+
+moray_status moray_autotune(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, int max_trials,
+                            moray_tune_result* out) {
+  if (!c) return MORAY_EINVAL;
+  if (!probs || n_probs < 1) return fail(c, MORAY_EINVAL, "need n_probs >= 1 problems");
+  if (flags & ~(MORAY_FIELDS_ON_DEVICE | MORAY_OUT_ON_DEVICE)) return fail(c, MORAY_EINVAL, "unknown flags");
+  for (int i = 0; i < n_probs; ++i) {
+    const moray_status s = validate(c, probs[i], i);
+    if (s != MORAY_OK) return s;
+  }
+  if (engine_busy(c)) return fail(c, MORAY_EBUSY, "asynchronous solves are still running on this context");
+  if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
+  // scratch results on the device
+  long long cells = 0;
+  for (int i = 0; i < n_probs; ++i)
+    for (int q = 0; q < probs[i].n_grids; ++q)
+      cells += (long long)probs[i].grids[q].nx * probs[i].grids[q].ny * probs[i].grids[q].nz;
+  DevBuf scratch;
+  moray_status st = ensure(c, scratch, (size_t)cells * 16, "autotune results");
+  if (st != MORAY_OK) return st;
+  std::vector<moray_result> res(n_probs);
+  {
+    long long off = 0;
+    for (int i = 0; i < n_probs; ++i) {
+      long long nc = 0;
+      for (int q = 0; q < probs[i].n_grids; ++q)
+        nc += (long long)probs[i].grids[q].nx * probs[i].grids[q].ny * probs[i].grids[q].nz;
+      res[i] = moray_result{};
+      res[i].k_ph = (double*)scratch.p + off;
+      res[i].heating = (double*)scratch.p + cells + off;
+      off += nc;
+    }
+  }
+  const unsigned fl = flags | MORAY_OUT_ON_DEVICE;
+  const int keep_chunk = c->chunk, keep_refill = c->refill, keep_reserve = c->reserve_user, keep_bpc = c->blocks_per_cu;
+  int trials = 0;
+  // fastest of three solves (the second captures a graph, the third replays it)
+  auto timed = [&](double& ms) -> moray_status {
+    ms = 1e300;
+    for (int r = 0; r < 3; ++r) {
+      const auto t0 = std::chrono::steady_clock::now();
+      const moray_status s = moray_trace(c, probs, n_probs, fl, res.data());
+      if (s != MORAY_OK) return s;
+      ms = std::min(ms, std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count());
+    }
+    ++trials;
+    return MORAY_OK;
+  };
+  double first = 0.0;
+  st = timed(first);
+  double best = first;
+  int bpc_max = 1;
+  if (st == MORAY_OK && (trace_occupancy(c->precision, c->cache, &bpc_max) != hipSuccess || bpc_max < 1)) bpc_max = 1;
+  struct Knob {
+    int* field;
+    std::vector<int> values;
+  };
+  std::vector<int> bpcs;
+  for (int b = 1; b <= bpc_max; ++b) bpcs.push_back(b);
+  std::vector<Knob> knobs = {{&c->chunk, {128, 256, 512}},
+                             {&c->refill, {8, 12, 16, 24}},
+                             {&c->reserve_user, {64, 128, 256}},
+                             {&c->blocks_per_cu, bpcs}};
+  for (Knob& k : knobs) {
+    if (st != MORAY_OK) break;
+    const int start = *k.field;
+    int pick = start;
+    for (int v : k.values) {
+      if (v == start) continue;
+      if (max_trials > 0 && trials >= max_trials) break;
+      *k.field = v;
+      double ms = 0.0;
+      st = timed(ms);
+      if (st != MORAY_OK) break;
+      if (ms < best) {
+        best = ms;
+        pick = v;
+      }
+    }
+    *k.field = pick;
+  }
+  release(c, scratch);
+  if (st != MORAY_OK) {
+    c->chunk = keep_chunk;
+    c->refill = keep_refill;
+    c->reserve_user = keep_reserve;
+    c->blocks_per_cu = keep_bpc;
+    return st;
+  }
+  if (out) {
+    out->chunk_rays = c->chunk;
+    out->refill_lanes = c->refill;
+    out->reserve_rays = c->reserve_user;
+    out->waves_per_cu = c->blocks_per_cu * (kTraceBlock / kWave);
+    out->first_ms = first;
+    out->best_ms = best;
+    out->trials = trials;
+  }
+  c->err = "no error";
+  return MORAY_OK;
 }
 
 }  // extern "C"

@@ -501,6 +501,7 @@ moray_status retire(Engine* E, std::vector<ServeProblem*>& done) {
     R.trace_launches = p->launches;
     R.t_admit = p->t_admit;
     R.t_done = t;
+    R.from_graph = 0;
   }
   for (ServeProblem* p : done) {
     E->load -= p->bound;

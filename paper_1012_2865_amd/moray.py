@@ -71,11 +71,17 @@ class Result(ctypes.Structure):
                 ("splits", ctypes.c_ulonglong), ("rays_escaped", ctypes.c_ulonglong),
                 ("rays_truncated", ctypes.c_ulonglong), ("peak_level_rays", ctypes.c_ulonglong),
                 ("trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double)]
+                ("t_done", ctypes.c_double), ("from_graph", ctypes.c_int)]
 
 
-ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_trace_async", "moray_query", "moray_free", "moray_last_error",
-                 "moray_version")
+class TuneResult(ctypes.Structure):
+    _fields_ = [("chunk_rays", ctypes.c_int), ("refill_lanes", ctypes.c_int), ("reserve_rays", ctypes.c_int),
+                ("waves_per_cu", ctypes.c_int), ("first_ms", ctypes.c_double), ("best_ms", ctypes.c_double),
+                ("trials", ctypes.c_int)]
+
+
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_trace_async", "moray_query", "moray_free",
+                 "moray_last_error", "moray_version")
 
 _lib = None
 
@@ -91,6 +97,9 @@ def load_library(path: str = LIB_PATH):
         lib.moray_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                     ctypes.POINTER(Result)]
         lib.moray_trace.restype = ctypes.c_int
+        lib.moray_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
+                                       ctypes.c_int, ctypes.POINTER(TuneResult)]
+        lib.moray_autotune.restype = ctypes.c_int
         lib.moray_trace_async.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                           ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_ulonglong)]
         lib.moray_trace_async.restype = ctypes.c_int
@@ -155,8 +164,10 @@ def _ptr(a, dtype_np, keep: list):
     return arr.ctypes.data
 
 
-def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool):
-    """C structs for a list of problems, plus everything they point into."""
+def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, outputs=None):
+    """C structs for a list of problems, plus everything they point into.
+    outputs: optional list of (k_ph, heating) flat float64 buffers per
+    problem (torch CUDA tensors when out_on_device, else numpy arrays)."""
     keep: list = []
     n = len(problems)
     cprobs = (Problem * n)()
@@ -201,7 +212,15 @@ def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool):
         pr = pb.params
         cprobs[i] = Problem(grids, len(pb.grids), srcs, len(S), ctypes.pointer(cspec),
                             TraceParams(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac)))
-        if out_on_device:
+        if outputs is not None:
+            kph, heat = outputs[i]
+            assert (kph.numel() if hasattr(kph, "numel") else kph.size) >= n_cells
+            if out_on_device:
+                assert _is_torch_cuda(kph) and _is_torch_cuda(heat) and kph.is_contiguous() and heat.is_contiguous()
+                results[i].k_ph, results[i].heating = kph.data_ptr(), heat.data_ptr()
+            else:
+                results[i].k_ph, results[i].heating = kph.ctypes.data, heat.ctypes.data
+        elif out_on_device:
             import torch
             kph = torch.empty(n_cells, dtype=torch.float64, device="cuda")
             heat = torch.empty(n_cells, dtype=torch.float64, device="cuda")
@@ -236,7 +255,8 @@ def _unpack(results, outs, want_escaped_sg: bool) -> List[dict]:
     return out
 
 
-def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False) -> List[dict]:
+def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False,
+                outputs=None) -> List[dict]:
     """Trace a batch of problems in one call.
 
     Each problem is duck-typed: ``grids`` (``n_h``, ``x_hi`` as torch CUDA
@@ -244,13 +264,26 @@ def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escape
     ``offset``), ``sources`` (S x 4), ``spectrum`` (``energy_ev``, ``sigma_cm2``,
     ``frac``, ``e_ion_ev``), ``params`` (``phi_c``, ``level_init``,
     ``level_max``, ``p_min_frac``). Returns one dict per problem with ``k_ph``
-    and ``heating`` (lists per grid) and the totals."""
+    and ``heating`` (lists per grid) and the totals. ``outputs`` optionally
+    names the result buffers (see _marshal); reusing them across calls lets
+    the library replay its captured launch sequence."""
     lib = load_library()
-    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg)
+    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg, outputs)
     rc = lib.moray_trace(ctx, cprobs, len(problems), flags, results)
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
     return _unpack(results, outs, want_escaped_sg)
+
+
+def moray_autotune(ctx, problems: Sequence, max_trials: int = 0) -> dict:
+    """Pick the fastest launch settings for this batch and keep them in the context."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal(problems, True, False)
+    r = TuneResult()
+    rc = lib.moray_autotune(ctx, cprobs, len(problems), flags, int(max_trials), ctypes.byref(r))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return {name: getattr(r, name) for name, _ in TuneResult._fields_}
 
 
 class Ticket:

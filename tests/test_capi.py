@@ -73,7 +73,7 @@ int main(void) {
   S(moray_trace_params) O(moray_trace_params, p_min_frac)
   S(moray_problem) O(moray_problem, params)
   S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
-  O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done)
+  O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)
   return 0;
 }
 """
