@@ -5,9 +5,11 @@ A step is one full single-pass trace (absorber columns, seeding, every
 HEALPix level's march/split/deposit, finalize) of one synthetic workload whose
 fields are already resident in HBM. `value` is ray-cell segments per second
 of the float32-geometry / float64-accumulate path over the timed steps
-(wall clock around the steps, including the host-side planning and the
-result read-back of each call). The plain float64 path on the same input is
-reported beside it.
+(wall clock around the steps, including the result read-back of each call),
+with the launch settings the autotuner chose (untimed, before the warm-up)
+and the launch sequence replayed from its HIP graph. The plain float64 path
+on the same input (planned and launched anew every call) is reported beside
+it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
@@ -51,25 +53,49 @@ def _workload(name):
     raise ValueError(name)
 
 
-def _time_steps(M, ctx, dev, steps, warmup):
+def _outputs(dev):
+    """Result buffers per problem (k_ph, heating), flat float64 on the device."""
     import torch
+    out = []
+    for p in dev:
+        n = sum(int(g.n_h.numel()) for g in p.grids)
+        out.append((torch.empty(n, dtype=torch.float64, device="cuda"),
+                    torch.empty(n, dtype=torch.float64, device="cuda")))
+    return out
+
+
+def _time_steps(M, ctx, dev, steps, warmup, graph=True):
+    """Seconds per step. graph=True reuses one set of result buffers, so from
+    the third call on the library replays its captured launch sequence;
+    graph=False alternates two sets, so every call plans and launches anew."""
+    import torch
+    sets = [_outputs(dev), _outputs(dev)] if not graph else [_outputs(dev)]
     res = None
-    for _ in range(warmup):
-        res = M.moray_trace(ctx, dev)
+    for i in range(warmup):
+        res = M.moray_trace(ctx, dev, outputs=sets[i % len(sets)])
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(steps):
-        res = M.moray_trace(ctx, dev)
+    for i in range(steps):
+        res = M.moray_trace(ctx, dev, outputs=sets[(warmup + i) % len(sets)])
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     segs = sum(r["segments"] for r in res)
     return dt / steps, segs, res
 
 
-def _kernel_time(M, precision, dev, reps=3):
+def _tuned(M, precision, dev):
+    """A context whose launch settings the autotuner chose for this batch."""
+    ctx = M.moray_init(device=0, precision=precision)
+    tune = M.moray_autotune(ctx, dev)
+    return ctx, tune
+
+
+def _kernel_time(M, precision, dev, tune, reps=3):
     """Summed trace-kernel device time per step, measured with HIP events on
-    the library's stream."""
-    ctx = M.moray_init(device=0, precision=precision, profile=True)
+    the library's stream, with the tuned launch settings."""
+    ctx = M.moray_init(device=0, precision=precision, profile=True, chunk_rays=tune["chunk_rays"],
+                       refill_lanes=tune["refill_lanes"], waves_per_cu=tune["waves_per_cu"],
+                       reserve_rays=tune["reserve_rays"])
     try:
         M.moray_trace(ctx, dev)
         ms, launches, segs = 0.0, 0, 0
@@ -169,9 +195,9 @@ def _batched_c2(M, steps):
     problems, config = _workload("c2")
     dev = [M.problem_to_device(p) for p in problems]
     torch.cuda.synchronize()
-    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    ctx, tune = _tuned(M, M.MORAY_FP32_ACC64, dev)
     try:
-        s32, seg32, _ = _time_steps(M, ctx, dev, steps, 1)
+        s32, seg32, res = _time_steps(M, ctx, dev, steps, 2)
     finally:
         M.moray_free(ctx)
     ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
@@ -191,7 +217,9 @@ def _batched_c2(M, steps):
     finally:
         M.moray_free(ctx)
     return {"workload": config["workload"], "batched_fp32": {"value": seg32 / s32, "unit": "segments/s",
-                                                             "ms_per_step": s32 * 1e3, "segments": seg32},
+                                                             "ms_per_step": s32 * 1e3, "segments": seg32,
+                                                             "graph_replay": bool(res[0]["from_graph"]),
+                                                             "tuned": tune},
             "plain_fp64": {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3,
                            "segments": seg64, "form": "one problem per call"},
             "batched_over_plain": (seg32 / s32) / (seg64 / s64)}
@@ -288,24 +316,26 @@ def main():
     torch.cuda.synchronize()
     print(f"# workload {config['workload']} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
 
-    ctx32 = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    ctx32, tune = _tuned(M, M.MORAY_FP32_ACC64, dev)
+    print(f"# autotuned: {tune}", file=sys.stderr, flush=True)
     try:
-        s32, seg32, res32 = _time_steps(M, ctx32, dev, args.steps, args.warmup)
+        s32, seg32, res32 = _time_steps(M, ctx32, dev, args.steps, max(2, args.warmup))
     finally:
         M.moray_free(ctx32)
-    print(f"# fp32: {s32 * 1e3:.2f} ms/step, {seg32} segments", file=sys.stderr, flush=True)
+    print(f"# fp32: {s32 * 1e3:.2f} ms/step, {seg32} segments, graph replay {bool(res32[0]['from_graph'])}",
+          file=sys.stderr, flush=True)
     plain = None
     if not args.no_fp64:
         ctx64 = M.moray_init(device=0, precision=M.MORAY_FP64)
         try:
-            s64, seg64, _ = _time_steps(M, ctx64, dev, max(1, args.steps // 2), 1)
+            s64, seg64, _ = _time_steps(M, ctx64, dev, max(1, args.steps // 2), 1, graph=False)
         finally:
             M.moray_free(ctx64)
         plain = {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3, "segments": seg64,
                  "dtype": "f64", "form": "one solve per call, no graph"}
         print(f"# fp64: {s64 * 1e3:.2f} ms/step, {seg64} segments", file=sys.stderr, flush=True)
 
-    kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, dev)
+    kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, dev, tune)
     algo_bytes = BYTES_PER_SEGMENT["fp32"] * ksegs
     achieved = algo_bytes / (kms * 1e-3) / 1e9
     traffic = _traffic(args.workload, "fp32")
@@ -335,7 +365,8 @@ def main():
     out = {"metric": METRIC, "value": seg32 / s32, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": s32 * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64acc", "data": "synthetic", "config": config,
-           "segments_per_step": seg32, "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, **extras}
+           "segments_per_step": seg32, "graph_replay": bool(res32[0]["from_graph"]), "tuned": tune,
+           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, **extras}
     print(json.dumps(out), flush=True)
 
 

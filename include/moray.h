@@ -75,6 +75,7 @@ typedef struct {
   int profile;                /* nonzero: time every trace-kernel launch with HIP events */
   int deposit_cache;          /* >= 0: combine deposits in a per-wave LDS table (default);
                                  < 0: one float64 atomic per segment */
+  int reserve_rays;           /* next-level queue slots a wave reserves per atomic; 0 = from the queue size */
 } moray_init_params;
 
 typedef struct {

@@ -298,7 +298,8 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   *out = nullptr;
   if (!p) return MORAY_EINVAL;
   if (p->precision != MORAY_FP64 && p->precision != MORAY_FP32_ACC64) return MORAY_EINVAL;
-  if (p->waves_per_cu < 0 || p->refill_lanes < 0 || p->refill_lanes > kWave || p->chunk_rays < 0) return MORAY_EINVAL;
+  if (p->waves_per_cu < 0 || p->refill_lanes < 0 || p->refill_lanes > kWave || p->chunk_rays < 0 || p->reserve_rays < 0)
+    return MORAY_EINVAL;
   int n = 0;
   if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return MORAY_EDEVICE;
   if (p->device < 0 || p->device >= n) return MORAY_EINVAL;
@@ -311,6 +312,7 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   c->profile = p->profile;
   c->refill = p->refill_lanes ? p->refill_lanes : 16;
   c->chunk = p->chunk_rays ? p->chunk_rays : 256;
+  c->reserve_user = p->reserve_rays;
   if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
       c->num_cu < 1) {
     delete c;

@@ -35,7 +35,7 @@ class InitParams(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int), ("precision", ctypes.c_int), ("hbm_budget_bytes", ctypes.c_size_t),
                 ("queue_capacity", ctypes.c_size_t), ("waves_per_cu", ctypes.c_int), ("refill_lanes", ctypes.c_int),
                 ("chunk_rays", ctypes.c_int), ("hip_stream", ctypes.c_void_p), ("profile", ctypes.c_int),
-                ("deposit_cache", ctypes.c_int)]
+                ("deposit_cache", ctypes.c_int), ("reserve_rays", ctypes.c_int)]
 
 
 class Source(ctypes.Structure):
@@ -125,7 +125,7 @@ def moray_last_error(ctx) -> str:
 
 def moray_init(device: int = 0, precision: int = MORAY_FP32_ACC64, hbm_budget_bytes: int = 0,
                queue_capacity: int = 0, waves_per_cu: int = 0, refill_lanes: int = 0, chunk_rays: int = 0,
-               hip_stream=None, profile: bool = False, deposit_cache: int = 0):
+               hip_stream=None, profile: bool = False, deposit_cache: int = 0, reserve_rays: int = 0):
     """Create a context; returns an opaque handle. hip_stream: an int handle
     (torch.cuda.Stream.cuda_stream) or None for torch's current stream."""
     lib = load_library()
@@ -137,7 +137,7 @@ def moray_init(device: int = 0, precision: int = MORAY_FP32_ACC64, hbm_budget_by
         except Exception:
             hip_stream = None
     p = InitParams(device, precision, hbm_budget_bytes, queue_capacity, waves_per_cu, refill_lanes, chunk_rays,
-                   ctypes.c_void_p(hip_stream or 0), int(bool(profile)), int(deposit_cache))
+                   ctypes.c_void_p(hip_stream or 0), int(bool(profile)), int(deposit_cache), int(reserve_rays))
     h = ctypes.c_void_p()
     rc = lib.moray_init(ctypes.byref(h), ctypes.byref(p))
     if rc != MORAY_OK:

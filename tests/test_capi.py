@@ -50,9 +50,9 @@ def test_init_without_gpu_reports_edevice():
 def test_init_rejects_bad_parameters_before_touching_the_device():
     lib = M.load_library()
     h = ctypes.c_void_p()
-    p = M.InitParams(0, 7, 0, 0, 0, 0, 0, None, 0, 0)           # unknown precision
+    p = M.InitParams(0, 7, 0, 0, 0, 0, 0, None, 0, 0, 0)        # unknown precision
     assert lib.moray_init(ctypes.byref(h), ctypes.byref(p)) == M.MORAY_EINVAL
-    p = M.InitParams(0, 1, 0, 0, 0, 65, 0, None, 0, 0)          # more idle lanes than a wave has
+    p = M.InitParams(0, 1, 0, 0, 0, 65, 0, None, 0, 0, 0)       # more idle lanes than a wave has
     assert lib.moray_init(ctypes.byref(h), ctypes.byref(p)) == M.MORAY_EINVAL
     assert lib.moray_init(None, ctypes.byref(p)) == M.MORAY_EINVAL
     assert not h.value
@@ -67,7 +67,7 @@ _LAYOUT_C = r"""
 #define S(T) printf(#T " %zu\n", sizeof(T));
 #define O(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
 int main(void) {
-  S(moray_init_params) O(moray_init_params, hip_stream) O(moray_init_params, profile) O(moray_init_params, deposit_cache)
+  S(moray_init_params) O(moray_init_params, hip_stream) O(moray_init_params, profile) O(moray_init_params, deposit_cache) O(moray_init_params, reserve_rays)
   S(moray_source) S(moray_spectrum) O(moray_spectrum, e_ion_ev)
   S(moray_grid) O(moray_grid, offset) O(moray_grid, n_h) O(moray_grid, x_hi)
   S(moray_trace_params) O(moray_trace_params, p_min_frac)
