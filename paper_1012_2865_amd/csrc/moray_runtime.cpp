@@ -291,19 +291,32 @@ extern "C" {
 
 const char* moray_version(void) { return "0.1.0"; }
 
-const char* moray_last_error(const moray_ctx* ctx) { return ctx ? ctx->err.c_str() : "context is NULL"; }
+namespace {
+// why the last moray_init on this thread returned no context
+thread_local std::string g_init_err = "context is NULL";
+
+moray_status init_fail(moray_status s, const std::string& msg) {
+  g_init_err = msg;
+  return s;
+}
+}  // namespace
+
+const char* moray_last_error(const moray_ctx* ctx) { return ctx ? ctx->err.c_str() : g_init_err.c_str(); }
 
 moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
-  if (!out) return MORAY_EINVAL;
+  if (!out) return init_fail(MORAY_EINVAL, "context pointer is NULL");
   *out = nullptr;
-  if (!p) return MORAY_EINVAL;
-  if (p->precision != MORAY_FP64 && p->precision != MORAY_FP32_ACC64) return MORAY_EINVAL;
+  if (!p) return init_fail(MORAY_EINVAL, "parameters are NULL");
+  if (p->precision != MORAY_FP64 && p->precision != MORAY_FP32_ACC64) return init_fail(MORAY_EINVAL, "unknown precision");
   if (p->waves_per_cu < 0 || p->refill_lanes < 0 || p->refill_lanes > kWave || p->chunk_rays < 0 || p->reserve_rays < 0)
-    return MORAY_EINVAL;
+    return init_fail(MORAY_EINVAL, "negative or out-of-range launch setting");
   int n = 0;
-  if (hipGetDeviceCount(&n) != hipSuccess || n < 1) return MORAY_EDEVICE;
-  if (p->device < 0 || p->device >= n) return MORAY_EINVAL;
-  if (hipSetDevice(p->device) != hipSuccess) return MORAY_EDEVICE;
+  hipError_t he = hipGetDeviceCount(&n);
+  if (he != hipSuccess || n < 1)
+    return init_fail(MORAY_EDEVICE, std::string("no usable GPU: hipGetDeviceCount: ") + hipGetErrorString(he));
+  if (p->device < 0 || p->device >= n) return init_fail(MORAY_EINVAL, "device ordinal out of range");
+  if ((he = hipSetDevice(p->device)) != hipSuccess)
+    return init_fail(MORAY_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he));
   moray_ctx* c = new moray_ctx();
   c->device = p->device;
   c->precision = p->precision;
@@ -313,10 +326,10 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   c->refill = p->refill_lanes ? p->refill_lanes : 16;
   c->chunk = p->chunk_rays ? p->chunk_rays : 256;
   c->reserve_user = p->reserve_rays;
-  if (hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device) != hipSuccess ||
+  if ((he = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess ||
       c->num_cu < 1) {
     delete c;
-    return MORAY_EDEVICE;
+    return init_fail(MORAY_EDEVICE, std::string("hipDeviceGetAttribute: ") + hipGetErrorString(he));
   }
   c->cache = p->deposit_cache >= 0;
   int bpc = 1;
@@ -327,14 +340,14 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
     c->blocks_per_cu = std::min(want, bpc);
   }
   size_t free_b = 0, total_b = 0;
-  if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) {
+  if ((he = hipMemGetInfo(&free_b, &total_b)) != hipSuccess) {
     delete c;
-    return MORAY_EDEVICE;
+    return init_fail(MORAY_EDEVICE, std::string("hipMemGetInfo: ") + hipGetErrorString(he));
   }
   c->budget = p->hbm_budget_bytes ? p->hbm_budget_bytes : free_b / 2;
-  if (hipHostMalloc(&c->h_stage, 1 << 20, hipHostMallocDefault) != hipSuccess) {
+  if ((he = hipHostMalloc(&c->h_stage, 1 << 20, hipHostMallocDefault)) != hipSuccess) {
     delete c;
-    return MORAY_EDEVICE;
+    return init_fail(MORAY_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(he));
   }
   c->h_stage_bytes = 1 << 20;
   *out = c;

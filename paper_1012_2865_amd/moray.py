@@ -141,7 +141,7 @@ def moray_init(device: int = 0, precision: int = MORAY_FP32_ACC64, hbm_budget_by
     h = ctypes.c_void_p()
     rc = lib.moray_init(ctypes.byref(h), ctypes.byref(p))
     if rc != MORAY_OK:
-        raise MorayError(rc, "moray_init failed")
+        raise MorayError(rc, "moray_init: " + moray_last_error(None))
     return h
 
 

@@ -18,3 +18,18 @@ def oracle_lib():
     from oracle import oracle as O
     O._load()
     return O
+
+
+@pytest.fixture(autouse=True, scope="session")
+def _hip_runtime_before_oracle():
+    """Initialise the library's HIP runtime before any test runs the oracle
+    with many OpenMP threads: on the MI355X machine a first HIP initialisation
+    after a 16-thread OpenMP region reported no device."""
+    try:
+        import torch
+        if torch.cuda.is_available():
+            from paper_1012_2865_amd import moray as M
+            M.moray_free(M.moray_init(device=0))
+    except Exception:
+        pass
+    yield

@@ -56,7 +56,7 @@ def test_init_rejects_bad_parameters_before_touching_the_device():
     assert lib.moray_init(ctypes.byref(h), ctypes.byref(p)) == M.MORAY_EINVAL
     assert lib.moray_init(None, ctypes.byref(p)) == M.MORAY_EINVAL
     assert not h.value
-    assert M.moray_last_error(None) == "context is NULL"
+    assert M.moray_last_error(None) == "context pointer is NULL"
     lib.moray_free(None)
 
 
