@@ -153,9 +153,11 @@ struct Geom64 {
   __device__ void advance(int ax) { r = te(ax); }
   __device__ double local_u(int ax) const { return te(ax) * hloc; }
   __device__ void step(int ax, int cnew) {
-    if (ax == 0) t0 = plane(d0, s0, cnew);
-    else if (ax == 1) t1 = plane(d1, s1, cnew);
-    else t2 = plane(d2, s2, cnew);
+    const double d = sel3(ax, d0, d1, d2), s = sel3(ax, s0, s1, s2);
+    const double t = (((double)(cnew + (d > 0.0 ? 1 : 0)) - s) / d) * hinv;   // d != 0 on the exit axis
+    t0 = ax == 0 ? t : t0;
+    t1 = ax == 1 ? t : t1;
+    t2 = ax == 2 ? t : t2;
   }
 };
 
@@ -233,10 +235,22 @@ struct Geom32 {
   __device__ bool positive(float dr, int ax) const { return dr > sel3(ax, h0, h1, h2) * 9.094947e-13f; }
   __device__ void advance(int ax) { rh = sel3(ax, h0, h1, h2); rl = sel3(ax, l0, l1, l2); }
   __device__ float local_u(int ax) const { return sel3(ax, h0, h1, h2) * hloc; }
+  // The exit axis always has a nonzero direction component (an axis with
+  // none is at infinity), so its next plane needs no special case; selects
+  // instead of a branch per axis keep the wave converged.
   __device__ void step(int ax, int cnew) {
-    if (ax == 0) plane(d0, i0, j0, q0, e0, cnew, h0, l0);
-    else if (ax == 1) plane(d1, i1, j1, q1, e1, cnew, h1, l1);
-    else plane(d2, i2, j2, q2, e2, cnew, h2, l2);
+    const bool a0 = ax == 0, a1 = ax == 1, a2 = ax == 2;
+    const float d = sel3(ax, d0, d1, d2), i = sel3(ax, i0, i1, i2), j = sel3(ax, j0, j1, j2);
+    const float q = sel3(ax, q0, q1, q2), e = sel3(ax, e0, e1, e2);
+    const float bs = (float)(cnew + (d > 0.0f ? 1 : 0)) - q;  // exact
+    const float th = bs * i;
+    float tl = fmaf(bs, i, -th);
+    tl = fmaf(bs, j, tl);
+    tl = fmaf(-e, i, tl);
+    const float h = th * hinv, l = tl * hinv;
+    h0 = a0 ? h : h0; l0 = a0 ? l : l0;
+    h1 = a1 ? h : h1; l1 = a1 ? l : l1;
+    h2 = a2 ? h : h2; l2 = a2 ? l : l2;
   }
 };
 
@@ -255,16 +269,30 @@ __device__ __forceinline__ double absorb(double& P, double tau) {
   P -= dP;
   return dP;
 }
+// One exponential core serves both: Cody-Waite reduction x = k ln2 + r with
+// |r| <= ln2/2 (ln 2 split so k ln2 is exact) and the Taylor series of
+// expm1(r) to r^7 (truncation below 2e-8 relative there). Then
+// e^x - 1 = 2^k expm1(r) + (2^k - 1) is accurate for thin segments (k is 0
+// or -1) and e^x = 2^k (1 + expm1(r)) for thick ones, without a branch.
 __device__ __forceinline__ double absorb(double& P, float tau) {
-  if (tau < 0.6931472f) {
-    const double dP = P * (double)(-expm1f(-tau));
-    P -= dP;
-    return dP;
-  }
-  const double Pt = P * (double)expf(-tau);
-  const double dP = P - Pt;
-  P = Pt;
-  return dP;
+  const float x = -tau;
+  const float k = rintf(x * 1.44269504f);
+  const float r = fmaf(-k, 1.42860677e-06f, fmaf(-k, 0.693145752f, x));
+  float q = fmaf(r, 1.0f / 5040.0f, 1.0f / 720.0f);
+  q = fmaf(r, q, 1.0f / 120.0f);
+  q = fmaf(r, q, 1.0f / 24.0f);
+  q = fmaf(r, q, 1.0f / 6.0f);
+  q = fmaf(r, q, 0.5f);
+  q = fmaf(r * r, q, r);                                   // expm1(r)
+  const int ki = (int)k;
+  const bool thin = tau < 0.6931472f;
+  const float p2 = ldexpf(1.0f, ki);
+  const float absorbed = -fmaf(p2, q, p2 - 1.0f);          // 1 - e^-tau (thin: k is 0 or -1)
+  const float transmitted = ldexpf(1.0f + q, ki);          // e^-tau
+  const double Pin = P;
+  const double a = Pin * (double)(thin ? absorbed : transmitted);
+  P = thin ? Pin - a : a;
+  return thin ? a : Pin - a;
 }
 
 // Per-lane ray state. The tree fields (source, photon rates, absorber
@@ -874,23 +902,13 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         L.g.advance(ax);
       }
       // step across the exit face
-      int dir, cnew, nax;
-      if (ax == 0) {
-        dir = L.g.dirf(0) > 0.0f ? 1 : -1;
-        cnew = (L.c0 += dir);
-        nax = L.n0;
-        L.lin += dir;
-      } else if (ax == 1) {
-        dir = L.g.dirf(1) > 0.0f ? 1 : -1;
-        cnew = (L.c1 += dir);
-        nax = L.n1;
-        L.lin += dir * L.n0;
-      } else {
-        dir = L.g.dirf(2) > 0.0f ? 1 : -1;
-        cnew = (L.c2 += dir);
-        nax = L.n2;
-        L.lin += dir * L.n0 * L.n1;
-      }
+      const int dir = L.g.dirf(ax) > 0.0f ? 1 : -1;
+      const int cnew = sel3(ax, L.c0, L.c1, L.c2) + dir;
+      const int nax = sel3(ax, L.n0, L.n1, L.n2);
+      L.c0 = ax == 0 ? cnew : L.c0;
+      L.c1 = ax == 1 ? cnew : L.c1;
+      L.c2 = ax == 2 ? cnew : L.c2;
+      L.lin += dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
       L.g.step(ax, cnew);
       if (L.P < L.pmin) {
         tally.end(a.stats, L, 1);
