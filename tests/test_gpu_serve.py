@@ -9,6 +9,8 @@
 * One asynchronous result is checked against the FP64 oracle directly.
 * Invalid field values fail only their own ticket; host fields and host
   outputs work; tickets report MORAY_EBUSY until done and are then forgotten.
+* A problem that overflows the ray queue while running alone fails with
+  MORAY_EQUEUE on its own ticket, and the engine goes on with the next one.
 """
 import ctypes
 import time
@@ -148,3 +150,24 @@ def test_ticket_semantics():
         assert M.moray_trace(ctx, [M.problem_to_device(W.lognormal_problem(96, 9, 16, 1))])[0]["segments"] > 0
     finally:
         M.moray_free(ctx)
+
+
+def test_overflow_alone_fails_only_its_ticket():
+    # a 4096-ray queue: the 32^3 problem (16 trees) cannot fit even alone,
+    # the 8^3 one (1 tree, phi_c 0.5: at most 12 * 4^4 = 3072 rays per level) can
+    big = M.problem_to_device(W.lognormal_problem(98, 0, 32, 4))
+    small = M.problem_to_device(W.lognormal_problem(98, 1, 8, 1, energies=(13.6,),
+                                                    params=W.Params(level_init=0, phi_c=0.5)))
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64, queue_capacity=4096)
+    ref = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        alone = M.moray_trace(ref, [small])[0]
+        tb = M.moray_trace_async(ctx, [big])
+        ts = M.moray_trace_async(ctx, [small])
+        with pytest.raises(M.MorayError) as e:
+            M.moray_query(ctx, tb, -1)
+        assert e.value.status == M.MORAY_EQUEUE
+        _same(M.moray_query(ctx, ts, -1)[0], alone, 1e-9, "after overflow")
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(ref)
