@@ -1,0 +1,131 @@
+"""Degenerate and edge cases of the method, GPU against the FP64 oracle in
+both precisions (same bars as test_gpu_parity): empty source lists,
+non-cubic and single-cell grids, sources on cell vertices and at the domain
+corner, no splitting (Phi_c = 0, or level_init = level_max), no truncation
+(p_min_frac = 0), vacuum and neutral-free cells, optically thick media, high
+seed levels, two child grids (one touching the root boundary) and a child
+grid holding the source. Inputs are seeded and built here."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1012_2865_amd import moray as M
+from paper_1012_2865_amd import workloads as W
+
+from test_gpu_parity import _check, _run
+
+pytestmark = pytest.mark.gpu
+
+DX = W.DX_C1
+
+
+def _lognormal_box(item, shape, n_src, **kw):
+    """Lognormal-like random densities on a non-cubic grid (independent cells)."""
+    rng = W.rng_for(99, item, 0)
+    nx, ny, nz = shape
+    n_h = (10 ** rng.uniform(-3.0, -1.0, (nz, ny, nx))).astype(np.float32)
+    x_hi = rng.uniform(0.5, 1.0, (nz, ny, nx)).astype(np.float32)
+    src = W.random_sources(W.rng_for(99, item, 1), n_src, (nx, ny, nz), (48.0, 50.0))
+    return W.Problem([W.Grid(n_h, x_hi, DX)], src, W.hydrogen_spectrum(W.FOUR_GROUPS_EV),
+                     kw.pop("params", W.Params()), name=f"box{shape}")
+
+
+def _no_sources():
+    p = _lognormal_box(1, (12, 10, 8), 1)
+    p.sources = np.zeros((0, 4))
+    return p
+
+
+def _single_cell():
+    g = W.uniform_grid(1, DX, 1e-2, 0.7)
+    return W.Problem([g], np.array([[0.25, 0.5, 0.75, 1e49]]), W.hydrogen_spectrum([13.6, 30.0]),
+                     W.Params(level_init=2), name="cell1")
+
+
+def _vertex_and_corner():
+    p = _lognormal_box(2, (16, 16, 16), 3)
+    p.sources[0, :3] = [8.0, 8.0, 8.0]        # cell vertex at the centre
+    p.sources[1, :3] = [0.0, 0.0, 0.0]        # domain corner
+    p.sources[2, :3] = [5.0, 11.5, 3.0]       # on two cell faces
+    return p
+
+
+def _no_split():
+    return _lognormal_box(3, (20, 14, 9), 2, params=W.Params(phi_c=0.0, level_init=2))
+
+
+def _init_is_max():
+    return _lognormal_box(4, (16, 16, 16), 2, params=W.Params(level_init=3, level_max=3))
+
+
+def _no_truncation():
+    return _lognormal_box(5, (16, 12, 20), 2, params=W.Params(p_min_frac=0.0))
+
+
+def _vacuum_and_ionised():
+    p = _lognormal_box(6, (18, 18, 18), 2)
+    g = p.grids[0]
+    g.n_h[:, :, :6] = 0.0                      # vacuum slab
+    g.x_hi[:, 12:, :] = 0.0                    # fully ionised slab
+    return p
+
+
+def _thick():
+    p = _lognormal_box(7, (16, 16, 16), 2)
+    p.grids[0].n_h *= np.float32(1e4)
+    return p
+
+
+def _high_level_init():
+    return _lognormal_box(8, (16, 16, 16), 1, params=W.Params(level_init=4))
+
+
+def _two_children():
+    n = 24
+    p = W.lognormal_problem(99, 9, n, 3)
+    rng = W.rng_for(99, 90, 0)
+    for off, cn in (((2, 3, 4), 8), ((n - 5, 10, 0), 10)):   # the second touches two root faces
+        p.grids.append(W.Grid(n_h=(10 ** rng.uniform(-2.5, -1.0, (cn,) * 3)).astype(np.float32),
+                              x_hi=rng.uniform(0.5, 1.0, (cn,) * 3).astype(np.float32),
+                              dx_cm=p.grids[0].dx_cm / 2, parent=0, offset=off))
+    p.sources[0, :3] = [4.25, 5.0, 6.5]        # inside the first child
+    p.sources[1, :3] = [float(n - 3), 12.0, 1.5]   # inside the second, near the root boundary
+    return p
+
+
+CASES = {
+    "no_sources": _no_sources,
+    "single_cell": _single_cell,
+    "vertex_and_corner": _vertex_and_corner,
+    "no_split": _no_split,
+    "init_is_max": _init_is_max,
+    "no_truncation": _no_truncation,
+    "vacuum_and_ionised": _vacuum_and_ionised,
+    "thick": _thick,
+    "high_level_init": _high_level_init,
+    "two_children": _two_children,
+}
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    c64 = M.moray_init(device=0, precision=M.MORAY_FP64)
+    c32 = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    yield {M.MORAY_FP64: c64, M.MORAY_FP32_ACC64: c32}
+    M.moray_free(c64)
+    M.moray_free(c32)
+
+
+@pytest.mark.parametrize("case", list(CASES))
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_edge_case_matches_oracle(ctxs, case, precision):
+    p = CASES[case]()
+    ref = O.trace(p)
+    res = _run(ctxs[precision], [p])[0]
+    if p.n_sources == 0:
+        assert res["emitted"] == 0.0 and res["segments"] == 0 and res["rays_seeded"] == 0
+        for q in range(len(p.grids)):
+            assert float(res["k_ph"][q].abs().max()) == 0.0
+        return
+    fp64 = precision == M.MORAY_FP64
+    _check(res, ref, 1e-9 if fp64 else 1e-4, name=f"{'fp64' if fp64 else 'fp32'} {case}", fp64=fp64)
