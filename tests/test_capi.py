@@ -101,3 +101,12 @@ def test_async_entry_points_reject_null_context():
     t = ctypes.c_ulonglong(0)
     assert lib.moray_trace_async(None, None, 1, 0, None, ctypes.byref(t)) == M.MORAY_EINVAL
     assert lib.moray_query(None, ctypes.c_ulonglong(1), 0) == M.MORAY_EINVAL
+
+
+def test_c_caller_compiles_against_the_header():
+    with tempfile.TemporaryDirectory() as d:
+        here = os.path.dirname(os.path.abspath(__file__))
+        libdir = os.path.dirname(M.LIB_PATH)
+        subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
+                               os.path.join(here, "capi_host_demo.c"), "-L", libdir, "-lmoray",
+                               "-o", os.path.join(d, "demo")])
