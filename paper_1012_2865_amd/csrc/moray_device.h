@@ -18,7 +18,9 @@ constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries
 constexpr int kCacheEntries = 1 << kCacheLog2;
 constexpr uint32_t kNoSlot = 0xffffffffu;      // empty cache entry
-constexpr int kEvictCap = 256;                 // per-wave buffer of evicted sums (drained at >= 192)
+constexpr int kEvictCap = 128;                 // per-wave buffer of evicted sums (drained at > 64)
+constexpr int kTallyLog2 = 7;                  // per-block LDS table of per-tree statistics: 128 entries
+constexpr int kTallySlots = 1 << kTallyLog2;
 constexpr int kStageFlush = 16;                // split parents staged before their children are written
 constexpr int kStageCap = kStageFlush + kWave; // one iteration adds at most 64 parents
 

@@ -170,6 +170,15 @@ struct Geom64 {
 // pairs, accurate to ~1e-14 t, so float32 arithmetic places every segment
 // where float64 would.
 // ---------------------------------------------------------------------------
+// The float path keeps each lane's float64 direction in LDS rather than in
+// registers: it is read only by the rare exact paths (a split test within
+// rounding of its threshold, entering or starting in a child grid), and
+// recomputing it from the pixel there would set the kernel's register peak.
+__device__ __forceinline__ double* lane_dir() {
+  __shared__ double sdir[3][kTraceBlock];
+  return &sdir[0][threadIdx.x];
+}
+
 struct Geom32 {
   float d0, d1, d2;
   float i0, i1, i2, j0, j1, j2;      // 1/d = i + j
@@ -181,6 +190,8 @@ struct Geom32 {
   __device__ void set_dir(const double v[3]) {
     d0 = (float)v[0]; d1 = (float)v[1]; d2 = (float)v[2];
     split_inv(v[0], i0, j0); split_inv(v[1], i1, j1); split_inv(v[2], i2, j2);
+    double* vd = lane_dir();
+    vd[0] = v[0]; vd[kTraceBlock] = v[1]; vd[2 * kTraceBlock] = v[2];
   }
   static __device__ void split_inv(double d, float& i, float& j) {
     if (d == 0.0) { i = 0.0f; j = 0.0f; return; }
@@ -188,11 +199,7 @@ struct Geom32 {
     i = (float)inv;
     j = (float)(inv - (double)i);
   }
-  __device__ double dir64(int k) const {
-    const float dk = sel3(k, d0, d1, d2);
-    if (dk == 0.0f) return 0.0;
-    return 1.0 / ((double)sel3(k, i0, i1, i2) + (double)sel3(k, j0, j1, j2));
-  }
+  __device__ double dir64(int k) const { return lane_dir()[k * kTraceBlock]; }
   __device__ float dirf(int k) const { return sel3(k, d0, d1, d2); }
   __device__ void set_radius(double r64) { rh = (float)r64; rl = (float)(r64 - (double)rh); }
   __device__ double radius64() const { return (double)rh + (double)rl; }
@@ -482,8 +489,7 @@ struct Tracer {
     const int ch = (int)(-k) - 1;
     const GridDev& G = a.grids[ch];
     const double r64 = L.g.radius64();
-    double v[3];
-    healpix_dir(L.level, L.pix, v[0], v[1], v[2]);
+    const double v[3] = {L.g.dir64(0), L.g.dir64(1), L.g.dir64(2)};
     const double x0 = __dadd_rn(L.sx, __dmul_rn(r64, v[0]));
     const double x1 = __dadd_rn(L.sy, __dmul_rn(r64, v[1]));
     const double x2 = __dadd_rn(L.sz, __dmul_rn(r64, v[2]));
@@ -505,8 +511,7 @@ struct Tracer {
       const GridDev& G = a.grids[L.q];
       o[0] = G.ox; o[1] = G.oy; o[2] = G.oz;
     }
-    double v[3];
-    healpix_dir(L.level, L.pix, v[0], v[1], v[2]);
+    const double v[3] = {L.g.dir64(0), L.g.dir64(1), L.g.dir64(2)};
     const double h = child ? 2.0 : 1.0;
     const double s[3] = {L.sx, L.sy, L.sz};
     const int c[3] = {L.c0, L.c1, L.c2};
@@ -538,44 +543,87 @@ struct Tracer {
   }
 };
 
-// Per-lane statistics of the rays a lane has finished, for one tree at a
-// time: flushed to that tree's counters only when the lane moves on to a ray
-// of another tree, and when the launch ends.
-struct Tally {
-  uint32_t sg;
-  unsigned segs, splits, n_esc, n_trunc;
-  double esc_P, trunc_P;
+// Per-tree statistics of finished rays (segments, splits, escaped and
+// truncated rays with their photon rates), combined per block in LDS: a lane
+// whose ray ends adds to its tree's entry with LDS atomics, and the block adds
+// each entry to the tree's global counters once, when all its waves are done.
+// Consecutive rays of a lane seldom share a tree, and a global atomic per ray
+// end would sit in the same in-order memory counter as the next absorber
+// gather. A tree that finds no free entry among its two probes adds to the
+// global counters directly.
+struct TallyTable {
+  uint32_t* key;                 // kTallySlots tree indices (kNoTree: free)
+  unsigned long long* cnt;       // [4][kTallySlots]: segs, splits, n_esc, n_trunc
+  double* sum;                   // [2][kTallySlots]: esc_P, trunc_P
 
-  __device__ void clear(uint32_t tree) {
-    sg = tree;
-    segs = splits = n_esc = n_trunc = 0u;
-    esc_P = trunc_P = 0.0;
-  }
-  __device__ void flush(SgStats* stats) const {
-    if (sg == kNoTree) return;
-    SgStats& st = stats[sg];
-    if (segs) atomicAdd(&st.segs, (unsigned long long)segs);
-    if (splits) atomicAdd(&st.splits, (unsigned long long)splits);
-    if (n_esc) {
-      atomicAdd(&st.n_esc, (unsigned long long)n_esc);
-      unsafeAtomicAdd(&st.esc_P, esc_P);
-    }
-    if (n_trunc) {
-      atomicAdd(&st.n_trunc, (unsigned long long)n_trunc);
-      unsafeAtomicAdd(&st.trunc_P, trunc_P);
+  // all threads of the block; followed by a block barrier
+  __device__ void init() {
+    __shared__ uint32_t skey[kTallySlots];
+    __shared__ unsigned long long scnt[4 * kTallySlots];
+    __shared__ double ssum[2 * kTallySlots];
+    key = skey; cnt = scnt; sum = ssum;
+    for (int i = threadIdx.x; i < kTallySlots; i += blockDim.x) {
+      key[i] = kNoTree;
+      cnt[i] = cnt[kTallySlots + i] = cnt[2 * kTallySlots + i] = cnt[3 * kTallySlots + i] = 0ull;
+      sum[i] = sum[kTallySlots + i] = 0.0;
     }
   }
   // kind: 0 escaped, 1 truncated, 2 split
-  template <typename R>
-  __device__ void end(SgStats* stats, const Ray<R>& L, int kind) {
-    if (L.sg != sg) {
-      flush(stats);
-      clear(L.sg);
+  __device__ void add(SgStats* stats, uint32_t sg, unsigned segs, double P, int kind) {
+    const uint32_t h0 = (sg * 0x9E3779B1u) >> (32 - kTallyLog2);
+    int slot = -1;
+#pragma unroll
+    for (int probe = 0; probe < 2; ++probe) {
+      const uint32_t h = (h0 + probe) & (kTallySlots - 1);
+      uint32_t k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (k == kNoTree) {
+        uint32_t seen = kNoTree;
+        __hip_atomic_compare_exchange_strong(&key[h], &seen, sg, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_WORKGROUP);
+        k = seen == kNoTree ? sg : seen;
+      }
+      if (k == sg) {
+        slot = (int)h;
+        break;
+      }
     }
-    segs += L.segs;
-    if (kind == 0) { ++n_esc; esc_P += L.P; }
-    else if (kind == 1) { ++n_trunc; trunc_P += L.P; }
-    else ++splits;
+    const int c = kind == 2 ? 1 : kind + 2;
+    if (slot >= 0) {
+      __hip_atomic_fetch_add(&cnt[slot], (unsigned long long)segs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      __hip_atomic_fetch_add(&cnt[c * kTallySlots + slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (kind < 2)
+        __hip_atomic_fetch_add(&sum[kind * kTallySlots + slot], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    } else {
+      SgStats& st = stats[sg];
+      if (segs) atomicAdd(&st.segs, (unsigned long long)segs);
+      if (kind == 2) {
+        atomicAdd(&st.splits, 1ull);
+      } else if (kind == 0) {
+        atomicAdd(&st.n_esc, 1ull);
+        unsafeAtomicAdd(&st.esc_P, P);
+      } else {
+        atomicAdd(&st.n_trunc, 1ull);
+        unsafeAtomicAdd(&st.trunc_P, P);
+      }
+    }
+  }
+  // all threads of the block, after a block barrier that follows every add
+  __device__ void flush(SgStats* stats) const {
+    for (int i = threadIdx.x; i < kTallySlots; i += blockDim.x) {
+      const uint32_t k = key[i];
+      if (k == kNoTree) continue;
+      SgStats& st = stats[k];
+      if (cnt[i]) atomicAdd(&st.segs, cnt[i]);
+      if (cnt[kTallySlots + i]) atomicAdd(&st.splits, cnt[kTallySlots + i]);
+      if (cnt[2 * kTallySlots + i]) {
+        atomicAdd(&st.n_esc, cnt[2 * kTallySlots + i]);
+        unsafeAtomicAdd(&st.esc_P, sum[i]);
+      }
+      if (cnt[3 * kTallySlots + i]) {
+        atomicAdd(&st.n_trunc, cnt[3 * kTallySlots + i]);
+        unsafeAtomicAdd(&st.trunc_P, sum[kTallySlots + i]);
+      }
+    }
   }
 };
 
@@ -767,11 +815,21 @@ struct SplitStage {
   }
 };
 
+// Waves per SIMD the register budget is set for: three on the float path
+// (at most 168 VGPRs), two on the float64 path, whose geometry is twice as wide.
+template <typename R> struct TraceWaves { static constexpr int n = sizeof(R) == 4 ? 3 : 2; };
+
 template <typename R, bool CACHE>
-__global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a) {
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(TraceWaves<R>::n)))
+void trace_level_kernel(TraceArgs<R> a) {
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  if (a.ctr->err & kErrBadInput) return;
+  __shared__ int s_bad;
+  TallyTable tally;
+  tally.init();
+  if (threadIdx.x == 0) s_bad = (a.ctr->err & kErrBadInput) != 0;
+  __syncthreads();
+  if (s_bad) return;      // the whole block
   const int K = a.nseg;
   const unsigned long long npix = 12ull << (2 * a.seed_level);
   const unsigned long long n_seeds = (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * npix;
@@ -781,8 +839,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   const int home = (int)((blockIdx.x * (kTraceBlock / kWave) + threadIdx.x / kWave) % (unsigned)K);
   const Tracer<R> T(a);
   Ray<R> L;
-  Tally tally;
-  tally.clear(kNoTree);
+  int ended = -1;          // kind of the lane's ray that ended and is not yet tallied
   DepositCache<CACHE> cache;
   cache.init(lane);
   SplitStage stage;
@@ -797,6 +854,10 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   bool drained = false;
 
   for (;;) {
+    if (ended >= 0) {
+      tally.add(a.stats, L.sg, L.segs, L.P, ended);
+      ended = -1;
+    }
     // ---- refill idle lanes from the wave's claim on the level queue ----
     // Every idle lane first gets its queue slot or seed number (claiming as
     // many chunks as that takes), then all of them start in one pass; lanes
@@ -857,7 +918,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
             active = true;
             steps = 0;
           } else {
-            tally.end(a.stats, L, 0);     // starts outside the root grid: escaped at once
+            ended = 0;                     // starts outside the root grid: escaped at once
           }
         }
       }
@@ -881,7 +942,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
         stage.sg[e] = L.sg;
         stage.r[e] = L.g.radius64();
         stage.P[e] = L.P;
-        tally.end(a.stats, L, 2);
+        ended = 2;
         active = false;
       }
       stage.count += __popcll(smask);
@@ -911,12 +972,12 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
       L.lin += dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
       L.g.step(ax, cnew);
       if (L.P < L.pmin) {
-        tally.end(a.stats, L, 1);
+        ended = 1;
         active = false;
       } else if (++steps > a.max_steps) {
         // cell indices move monotonically, so this bound is never reached by a correct trace
         atomicOr(&a.ctr->err, kErrInternal);
-        tally.end(a.stats, L, 0);
+        ended = 0;
         active = false;
       } else {
         // the next cell's absorber column is gathered while the deposit is combined
@@ -930,7 +991,7 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
     if (moved) {
       if (knext < (R)0) {
         if (!T.settle(L, s_ax, s_dir)) {
-          tally.end(a.stats, L, 0);
+          ended = 0;
           active = false;
         }
       } else {
@@ -943,10 +1004,12 @@ __global__ __launch_bounds__(kTraceBlock) void trace_level_kernel(TraceArgs<R> a
   }
   if (stage.count) stage.write(a, home, lane);
   cache.flush(a.acc, lane);
-  tally.flush(a.stats);
+  if (ended >= 0) tally.add(a.stats, L.sg, L.segs, L.P, ended);
   // unused slots of the wave's last reserved block become empty slots
   for (unsigned long long i = stage.o_next + lane; i < stage.o_end; i += 64)
     if (i < a.seg_cap) a.out.sg[(unsigned long long)home * a.seg_cap + i] = kNoTree;
+  __syncthreads();
+  tally.flush(a.stats);
 }
 
 // ---------------------------------------------------------------------------
