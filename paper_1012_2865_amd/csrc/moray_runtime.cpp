@@ -324,7 +324,7 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   c->queue_cap_user = p->queue_capacity;
   c->profile = p->profile;
   c->refill = p->refill_lanes ? p->refill_lanes : 16;
-  c->chunk = p->chunk_rays ? p->chunk_rays : 512;
+  c->chunk = p->chunk_rays ? p->chunk_rays : 256;
   c->reserve_user = p->reserve_rays;
   if ((he = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess ||
       c->num_cu < 1) {

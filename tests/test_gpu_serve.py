@@ -48,7 +48,7 @@ def _same(got, want, tol, name):
 
 def _mix():
     return [
-        W.lognormal_problem(96, 0, 64, 8),                       # long-running anchor
+        W.lognormal_problem(96, 0, 128, 16),                     # long-running anchor (~10 ms)
         W.lognormal_problem(96, 1, 24, 3),
         W.lognormal_problem(96, 2, 40, 2, params=W.Params(level_init=0)),
         W.lognormal_problem(96, 3, 32, 5, mean=1e-4),
