@@ -15,6 +15,7 @@ it, and so are the 64-grid batched workload and a serving run.
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
+  python bench.py --write-atomics ATOMIC_DIR LAUNCHES
 
 Prints one JSON line.
 """
@@ -36,6 +37,22 @@ BYTES_PER_SEGMENT = {"fp32": 36, "fp64": 40}     # absorber read + two float64 r
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_trace_level.json")
 KERNEL_SRC = os.path.join(ROOT, "paper_1012_2865_amd", "csrc", "moray_kernels.hip")
 COPY_BYTES = 1 << 30                              # calibration copy of the counter pass
+MICROBENCH_LIB = os.path.join(ROOT, "paper_1012_2865_amd", "libmoray_microbench.so")
+
+
+def _device_peaks():
+    """Scattered and coherent float64 atomic rates and copy bandwidth measured
+    on the device by the project's microbenchmark (None when it is not built)."""
+    import ctypes
+    if not os.path.exists(MICROBENCH_LIB):
+        return None
+    lib = ctypes.CDLL(MICROBENCH_LIB)
+    lib.moray_microbench.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.moray_microbench.restype = ctypes.c_int
+    out = (ctypes.c_double * 3)()
+    if lib.moray_microbench(0, out) != 0:
+        return None
+    return {"atomics_scattered": out[0], "atomics_coherent": out[1], "copy_GBs": out[2]}
 
 
 def _workload(name):
@@ -140,8 +157,10 @@ def _counter_pass(workload):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
+    peaks = _device_peaks()     # its scattered-atomics kernel calibrates the atomic counter
     print(json.dumps({"counter_pass": config["workload"], "segments": sum(r["segments"] for r in res),
-                      "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES}), flush=True)
+                      "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES,
+                      "peaks": peaks}), flush=True)
 
 
 def _read_counter_csv(folder, counter):
@@ -185,6 +204,51 @@ def _write_traffic(fetch_dir, write_dir, workload, launches):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def _write_atomics(atomic_dir, workload, launches):
+    """Float64 atomics per trace-kernel launch from a TCC_EA0_ATOMIC_sum pass.
+    The microbenchmark's timed scattered-atomics dispatch (64 atomics per
+    thread of its grid) calibrates the counter."""
+    import csv
+    import glob
+    rows = _read_counter_csv(atomic_dir, "TCC_EA0_ATOMIC_sum")
+    trace = [v for k, v in rows if "trace_level_kernel" in k]
+    if len(trace) < 2 * launches:
+        raise SystemExit(f"{atomic_dir}: {len(trace)} trace dispatches, expected {2 * launches}")
+    scattered = [v for k, v in rows if "atomics_scattered" in k]
+    grid = 0          # threads of the scattered-atomics dispatch; each issues 64 atomics
+    for f in glob.glob(os.path.join(atomic_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if "atomics_scattered" in r["Kernel_Name"]:
+                grid = int(r["Grid_Size"])
+    known = grid * 64
+    factor = known / scattered[-1] if (scattered and known) else 1.0
+    per_launch = sum(trace[len(trace) - launches:]) / launches * factor
+    rec = json.load(open(TRAFFIC_FILE))
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != sha:
+        raise SystemExit("the traffic record belongs to another kernel source; write the traffic first")
+    key = f"{workload}/fp32"
+    rec.setdefault("atomics_per_launch", {})[key] = per_launch
+    rec.setdefault("detail", {}).setdefault(key, {})["atomics"] = {
+        "counter_per_launch": sum(trace[len(trace) - launches:]) / launches,
+        "microbench_counter": scattered[-1] if scattered else None, "microbench_atomics": known,
+        "atomics_per_count": factor}
+    with open(TRAFFIC_FILE, "w") as f:
+        json.dump(rec, f, indent=1)
+    print(json.dumps({"atomics_per_launch": per_launch, "atomics_per_count": factor}))
+
+
+def _atomics_per_launch(workload, precision):
+    try:
+        rec = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None
+    sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
+    if rec.get("kernel_sha256") != sha:
+        return None
+    return rec.get("atomics_per_launch", {}).get(f"{workload}/{precision}")
 
 
 def _batched_c2(M, steps):
@@ -292,9 +356,14 @@ def main():
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
                     help="host only: turn FETCH_SIZE / WRITE_SIZE pass folders into the traffic record")
+    ap.add_argument("--write-atomics", nargs=2, metavar=("ATOMIC_DIR", "LAUNCHES"),
+                    help="host only: add the float64 atomics per launch from a TCC_EA0_ATOMIC_sum pass")
     args = ap.parse_args()
     if args.write_traffic:
         _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]))
+        return
+    if args.write_atomics:
+        _write_atomics(args.write_atomics[0], args.workload, int(args.write_atomics[1]))
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this tracer shards by request or by source; "
@@ -346,6 +415,17 @@ def main():
                 "kernel": "trace_level_kernel<float>", "launches_per_step": launches,
                 "avg_launch_ms": kms / launches if launches else None,
                 "algorithmic_bytes_per_launch": algo_bytes / launches if launches else None}
+    # the deposits' second bound: float64 atomics that reach the memory side
+    # (evicted LDS sums), against the device's scattered-atomic peak
+    peaks = _device_peaks()
+    apl = _atomics_per_launch(args.workload, "fp32")
+    if peaks:
+        rate = apl / (kms * 1e-3 / launches) if (apl and launches) else None
+        roofline["atomics"] = {"unit": "float64 atomics/s", "per_launch": apl,
+                               "per_segment": apl * launches / ksegs if apl else None, "achieved": rate,
+                               "peak": peaks["atomics_scattered"], "peak_coherent": peaks["atomics_coherent"],
+                               "frac": rate / peaks["atomics_scattered"] if rate else None}
+        roofline["copy_GBs_measured"] = peaks["copy_GBs"]
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -54,5 +54,18 @@ def build_library(out: str = LIB) -> str:
     return out
 
 
+MICROBENCH_LIB = os.path.join(HERE, "libmoray_microbench.so")
+
+
+def build_microbench(out: str = MICROBENCH_LIB) -> str:
+    """The device-peak microbenchmark (scattered float64 atomics, streaming
+    copy) that bench.py prices the trace kernel's rooflines against."""
+    tmp = out + ".tmp"
+    _run([HIPCC] + COMMON + ["-x", "hip", "-shared", os.path.join(CSRC, "moray_microbench.hip"), "-o", tmp])
+    os.replace(tmp, out)
+    return out
+
+
 if __name__ == "__main__":
     print(build_library())
+    print(build_microbench())
