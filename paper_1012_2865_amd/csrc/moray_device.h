@@ -112,7 +112,7 @@ struct TraceArgs {
   double* acc;             // absorbed photons/s per (problem, group, leaf cell)
   RayQueue in, out;                    // nseg segments of seg_cap slots each
   unsigned long long seg_cap;
-  int nseg;
+  int nseg;                            // segments per level queue: a power of two
   Counters* ctr;
   SgStats* stats;
   int gen;                             // launch generation (the HEALPix level in a one-shot solve)

@@ -70,6 +70,14 @@ moray_status validate(moray_ctx* c, const moray_problem& P, int pi);
 int reach_level(const moray_problem& P);
 double level_rays_bound(const moray_problem& P);
 
+// Segments of a level queue of `cap` slots: a power of two up to kSegMax, so
+// the trace kernel splits a launch's seeds among them with shifts.
+inline int queue_segments(size_t cap) {
+  int n = 1;
+  while (n < kSegMax && (size_t)(2 * n) * 65536 <= cap) n *= 2;
+  return n;
+}
+
 // serving engine (moray_serve.cpp)
 bool engine_busy(moray_ctx* c);
 void engine_stop(moray_ctx* c);

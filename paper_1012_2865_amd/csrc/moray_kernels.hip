@@ -663,6 +663,8 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
   return ((unsigned long long)hi << 32) | lo;
 }
 
+__device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
 __device__ __forceinline__ uint32_t cache_index(uint32_t key) {
   return (key * 0x9E3779B1u) >> (32 - kCacheLog2);
 }
@@ -861,7 +863,8 @@ void trace_level_kernel(TraceArgs<R> a) {
   if (threadIdx.x == 0) s_bad = (a.ctr->err & kErrBadInput) != 0;
   __syncthreads();
   if (s_bad) return;      // the whole block
-  const int K = a.nseg;
+  const int K = a.nseg;                      // a power of two
+  const int kshift = __ffs(K) - 1;
   const unsigned long long npix = 12ull << (2 * a.seed_level);
   const unsigned long long n_seeds = (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * npix;
   const unsigned long long* cnt_in = a.ctr->count[a.cin];
@@ -881,7 +884,7 @@ void trace_level_kernel(TraceArgs<R> a) {
   // the wave's current claim: [w_next, w_end) of segment w_seg, whose first
   // w_nch indices are queue slots and the rest seed numbers from w_slo on
   unsigned long long w_next = 0, w_end = 0, w_nch = 0, w_slo = 0;
-  int w_seg = home, visited = 0;
+  int w_seg = home;
   bool drained = false;
 
   for (;;) {
@@ -900,30 +903,40 @@ void trace_level_kernel(TraceArgs<R> a) {
       unsigned long long q = 0;
       while (left) {
         if (w_next >= w_end) {
-          // claim from the current segment; move on once it is exhausted
+          // Claim a chunk: every lane reads one segment's counters (one round
+          // trip for all of them), the wave picks the first segment with rays
+          // left at or after its current one, and claims there with one
+          // atomic; a claim that finds the segment used up in the meantime
+          // looks again. No segment with rays left: the level is drained.
           bool got = false;
-          while (visited < K) {
-            const int s = w_seg;
-            const unsigned long long nch = min(cnt_in[s], a.seg_cap);
-            const unsigned long long slo = ((unsigned long long)s * n_seeds) / (unsigned long long)K;
-            const unsigned long long shi = ((unsigned long long)(s + 1) * n_seeds) / (unsigned long long)K;
-            const unsigned long long size = nch + (shi - slo);
-            const unsigned long long seen = __hip_atomic_load(&head_in[s], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-            if (seen < size) {
-              unsigned long long b = 0;
-              if (lane == 0) b = atomicAdd(&head_in[s], (unsigned long long)a.chunk);
-              b = bcast64(b, 0);
-              if (b < size) {
-                w_nch = nch;
-                w_slo = slo;
-                w_next = b;
-                w_end = min(b + (unsigned long long)a.chunk, size);
-                got = true;
-                break;
-              }
+          for (;;) {
+            bool has = false;
+            if (lane < K) {
+              const unsigned long long size = min(cnt_in[lane], a.seg_cap) +
+                                              ((((unsigned long long)lane + 1) * n_seeds) >> kshift) -
+                                              (((unsigned long long)lane * n_seeds) >> kshift);
+              has = __hip_atomic_load(&head_in[lane], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < size;
             }
-            w_seg = (s + 1 == K) ? 0 : s + 1;
-            ++visited;
+            const unsigned long long live = __ballot(has);
+            if (!live) break;
+            const unsigned long long ahead = live & (~0ull << w_seg);
+            const int sg = uniform32((int)__ffsll((long long)(ahead ? ahead : live)) - 1);
+            // the chosen segment's slots and seeds, once more for the whole wave
+            const unsigned long long s_nch = min(cnt_in[sg], a.seg_cap);
+            const unsigned long long s_slo = ((unsigned long long)sg * n_seeds) >> kshift;
+            const unsigned long long s_size = s_nch + ((((unsigned long long)sg + 1) * n_seeds) >> kshift) - s_slo;
+            unsigned long long b = 0;
+            if (lane == 0) b = atomicAdd(&head_in[sg], (unsigned long long)a.chunk);
+            b = bcast64(b, 0);
+            w_seg = sg;
+            if (b < s_size) {
+              w_nch = s_nch;
+              w_slo = s_slo;
+              w_next = b;
+              w_end = min(b + (unsigned long long)a.chunk, s_size);
+              got = true;
+              break;
+            }
           }
           if (!got) { drained = true; break; }
         }

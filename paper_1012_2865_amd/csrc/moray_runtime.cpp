@@ -611,7 +611,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const double waves = (double)blocks * (kTraceBlock / kWave);
   // level queues in nseg segments (one claim and one write counter each); a
   // segment serves about waves/nseg waves, so the reserve fraction holds per segment
-  const int nseg = (int)std::min<size_t>(kSegMax, std::max<size_t>(1, cap / 65536));
+  const int nseg = queue_segments(cap);
   const unsigned long long seg_cap = cap / (size_t)nseg;
   unsigned long long reserve = (unsigned long long)std::min<double>((double)kReserveMax, (double)cap / (8.0 * waves));
   if (c->reserve_user > 0) reserve = std::min<unsigned long long>((unsigned long long)c->reserve_user, kReserveMax);

@@ -265,7 +265,7 @@ moray_status engine_setup(moray_ctx* c, Engine* E) {
       !pin((void**)&E->heexc, (size_t)E->prob_cap * kServeMaxGroups * 8) ||
       !pin((void**)&E->hstats, (size_t)E->tree_cap * sizeof(SgStats)) || !pin((void**)&E->hctr, sizeof(Counters)))
     return fail(c, MORAY_ENOMEM, "pinned host allocation failed");
-  E->nseg = (int)std::min<size_t>(kSegMax, std::max<size_t>(1, E->qcap / 65536));
+  E->nseg = queue_segments(E->qcap);
   E->seg_cap = E->qcap / (size_t)E->nseg;
   const double waves = (double)std::max(1, c->num_cu * c->blocks_per_cu) * (kTraceBlock / kWave);
   E->reserve = (unsigned long long)std::min<double>((double)kReserveMax, (double)E->qcap / (8.0 * waves));
