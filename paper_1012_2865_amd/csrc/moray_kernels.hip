@@ -664,6 +664,12 @@ __device__ __forceinline__ unsigned long long bcast64(unsigned long long v, int 
 }
 
 __device__ __forceinline__ int uniform32(int v) { return __builtin_amdgcn_readfirstlane(v); }
+// A wave-uniform 64-bit value (the first active lane's) in scalar registers.
+__device__ __forceinline__ unsigned long long uniform64(unsigned long long v) {
+  const unsigned lo = __builtin_amdgcn_readfirstlane((unsigned)v);
+  const unsigned hi = __builtin_amdgcn_readfirstlane((unsigned)(v >> 32));
+  return ((unsigned long long)hi << 32) | lo;
+}
 
 __device__ __forceinline__ uint32_t cache_index(uint32_t key) {
   return (key * 0x9E3779B1u) >> (32 - kCacheLog2);
@@ -903,13 +909,35 @@ void trace_level_kernel(TraceArgs<R> a) {
       unsigned long long q = 0;
       while (left) {
         if (w_next >= w_end) {
-          // Claim a chunk: every lane reads one segment's counters (one round
-          // trip for all of them), the wave picks the first segment with rays
-          // left at or after its current one, and claims there with one
-          // atomic; a claim that finds the segment used up in the meantime
-          // looks again. No segment with rays left: the level is drained.
+          // Claim a chunk: from the wave's current segment while it has rays
+          // left; once it is used up, every lane reads one segment's counters
+          // (one round trip for all of them), the wave picks the first segment
+          // with rays left after it, and claims there with one atomic; a claim
+          // that finds the segment used up in the meantime looks again. No
+          // segment with rays left: the level is drained.
           bool got = false;
           for (;;) {
+            // the current segment first: one load while it lasts
+            {
+              const unsigned long long c_nch = min(cnt_in[w_seg], a.seg_cap);
+              const unsigned long long c_slo = ((unsigned long long)w_seg * n_seeds) >> kshift;
+              const unsigned long long c_size = c_nch + ((((unsigned long long)w_seg + 1) * n_seeds) >> kshift) - c_slo;
+              const unsigned long long seen =
+                  uniform64(__hip_atomic_load(&head_in[w_seg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+              if (seen < c_size) {
+                unsigned long long b = 0;
+                if (lane == 0) b = atomicAdd(&head_in[w_seg], (unsigned long long)a.chunk);
+                b = bcast64(b, 0);
+                if (b < c_size) {
+                  w_nch = c_nch;
+                  w_slo = c_slo;
+                  w_next = b;
+                  w_end = min(b + (unsigned long long)a.chunk, c_size);
+                  got = true;
+                  break;
+                }
+              }
+            }
             bool has = false;
             if (lane < K) {
               const unsigned long long size = min(cnt_in[lane], a.seg_cap) +
