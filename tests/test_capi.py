@@ -110,3 +110,12 @@ def test_c_caller_compiles_against_the_header():
         subprocess.check_call(["gcc", "-std=c11", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"),
                                os.path.join(here, "capi_host_demo.c"), "-L", libdir, "-lmoray",
                                "-o", os.path.join(d, "demo")])
+
+
+def test_microbenchmark_library_exports_its_entry_point():
+    # the device-peak microbenchmark that bench.py prices the rooflines against
+    path = os.path.join(ROOT, "paper_1012_2865_amd", "libmoray_microbench.so")
+    if not os.path.exists(path):
+        pytest.skip("libmoray_microbench.so is not built (run __graft_entry__.build())")
+    out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
+    assert re.search(r" T moray_microbench$", out, flags=re.M)
