@@ -327,6 +327,18 @@ def _serving_c3(M, rate_hz, n_requests, horizon_s):
             "fields": "device-resident pool, 2 per edge"}
 
 
+def _host_cpu():
+    model = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"logical_cpus": os.cpu_count(), "model": model}
+
+
 def _cpu_baseline(problems, threads):
     from oracle import oracle as O
     t0 = time.perf_counter()
@@ -434,7 +446,15 @@ def main():
         v, dt, segs = _cpu_baseline(sample, threads)
         cpu = {"value": v, "unit": "segments/s", "cores": threads, "kind": "oracle",
                "sample": f"{'full workload' if args.workload == 'c1' else 'first 8 of 64 problems'}: "
-                         f"{segs} segments in {dt:.1f} s"}
+                         f"{segs} segments in {dt:.1f} s", "host": _host_cpu()}
+        # the plain single-threaded oracle on a bounded sample of the same workload
+        from paper_1012_2865_amd import workloads as W
+        one = [W.subset_sources(problems[0], [0, 1])] if args.workload == "c1" else problems[:1]
+        v1, dt1, segs1 = _cpu_baseline(one, 1)
+        cpu["one_thread"] = {"value": v1, "unit": "segments/s", "cores": 1, "kind": "oracle",
+                             "sample": f"{'sources 0-1 of 16' if args.workload == 'c1' else 'first problem'}: "
+                                       f"{segs1} segments in {dt1:.1f} s"}
+        cpu["gpu_speedup"] = {"over_all_cores": (seg32 / s32) / v, "over_one_thread": (seg32 / s32) / v1}
 
     extras = {}
     if not args.no_extras:

@@ -12,10 +12,12 @@
 //
 // Inside trace_level the grid is persistent: every wave keeps 64 rays in
 // flight, one per lane, marches them cell by cell (Eq. trace), tests the split
-// criterion at each cell exit (Eq. split), deposits P (1 - e^-tau) with one
-// float64 atomic per segment into the (problem, group) accumulator of the cell
-// (Eqs. dtau, flux, kph; heating is the group-weighted sum formed in finalize,
-// Eq. gamma), and refills idle lanes from a private chunk of the level queue
+// criterion at each cell exit (Eq. split), and deposits P (1 - e^-tau) into
+// the (problem, group) accumulator of the cell (Eqs. dtau, flux, kph; heating
+// is the group-weighted sum formed in finalize, Eq. gamma). Deposits combine
+// in a per-wave LDS table and reach the float64 accumulators in HBM as
+// atomics only when evicted; per-tree ray statistics combine in a per-block
+// LDS table. Idle lanes refill from a private chunk of the level queue
 // claimed with one atomic. Children of splitting lanes are compacted with a
 // wave ballot and written as four consecutive structure-of-arrays records.
 #include "moray_device.h"
