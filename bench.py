@@ -13,6 +13,7 @@ it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
+  python bench.py --equilibrium-only
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
@@ -251,6 +252,32 @@ def _atomics_per_launch(workload, precision):
     return rec.get("atomics_per_launch", {}).get(f"{workload}/{precision}")
 
 
+def _equilibrium_c1(M, updates=20):
+    """Photo-ionisation equilibrium iteration (moray_equilibrate) on the 128^3
+    workload from neutral gas: `updates` damped updates, each a full trace plus
+    the per-cell update, then the final trace."""
+    import numpy as np
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    p = W.config1()
+    p.grids[0].x_hi = np.ones_like(p.grids[0].x_hi)
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        M.moray_equilibrate(ctx, M.problem_to_device(p), tol=1e-30, max_iter=2)      # warm-up
+        pd = M.problem_to_device(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, done, _ = M.moray_equilibrate(ctx, pd, tol=1e-30, max_iter=updates)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        x = pd.grids[0].x_hi
+    finally:
+        M.moray_free(ctx)
+    return {"workload": "lognormal128_16src_4grp from neutral gas", "updates": done, "ms_total": dt * 1e3,
+            "ms_per_trace": dt * 1e3 / (done + 1), "segments_final_trace": res["segments"],
+            "ionised_fraction_final": float(1.0 - x.double().mean()), "dtype": "f32+f64acc"}
+
+
 def _batched_c2(M, steps):
     """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
     form traces all of them in one call (one launch sequence) in mixed
@@ -364,6 +391,8 @@ def main():
     ap.add_argument("--serve-only", action="store_true",
                     help="print one serving JSON line per --serve-rates value and exit")
     ap.add_argument("--serve-rates", type=str, default="10,20,50,100,200,500")
+    ap.add_argument("--equilibrium-only", action="store_true",
+                    help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
@@ -387,6 +416,9 @@ def main():
         return
     import torch
     from paper_1012_2865_amd import moray as M
+    if args.equilibrium_only:
+        print(json.dumps(_equilibrium_c1(M)), flush=True)
+        return
     if args.serve_only:
         for rate in (float(x) for x in args.serve_rates.split(",")):
             print(json.dumps(_serving_c3(M, rate, args.serve_requests, 60.0)), flush=True)
@@ -460,6 +492,9 @@ def main():
     if not args.no_extras:
         extras["batched_c2"] = _batched_c2(M, max(2, args.steps // 2))
         print(f"# batched c2: {extras['batched_c2']['batched_over_plain']:.2f}x plain fp64", file=sys.stderr, flush=True)
+        extras["equilibrium"] = _equilibrium_c1(M)
+        print(f"# equilibrium: {extras['equilibrium']['ms_per_trace']:.2f} ms per trace + update", file=sys.stderr,
+              flush=True)
         extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
         print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)

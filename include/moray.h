@@ -179,6 +179,37 @@ typedef struct {
 moray_status moray_autotune(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
                             int max_trials, moray_tune_result* out);
 
+/* Settings of moray_equilibrate. */
+typedef struct {
+  double alpha_b;             /* case-B recombination coefficient, cm^3/s (2.59e-13 at 1e4 K), > 0 */
+  double damping;             /* weight of the new root in each update, in (0, 1] */
+  double tol;                 /* stop once the largest change of x in an update is below tol, > 0 */
+  int max_iter;               /* at most this many updates, >= 1 */
+} moray_equilibrium_params;
+
+/* Photo-ionisation equilibrium around the trace (section 2.2, Eq. dndt, the
+ * update that follows the ray tracing in section 3.1), hydrogen only: no
+ * collisional term, n_e = n_p = (1 - x) n_H and dn/dt = 0, so in every cell
+ *     alpha_b n_H (1 - x)^2 = k_ph x   for the neutral fraction x.
+ * Damped fixed-point iteration: from the problem's x_hi, trace, solve that
+ * quadratic per cell (its root in [0, 1], computed as
+ * 2a / ((2a + k) + sqrt(k^2 + 4ak)) with a = alpha_b n_H, and x = 1 where
+ * n_H = 0), set x <- (1 - damping) x + damping x_root, and repeat until the
+ * largest change of x is below tol or max_iter updates are done; then trace
+ * once more with the final x into `out` (host or device results by flags, as
+ * in moray_trace; escaped_sg is filled when given).
+ * The problem must have a single grid and device-resident fields (flags must
+ * include MORAY_FIELDS_ON_DEVICE). Its x_hi array is updated in place: it
+ * holds the float32 neutral fraction of every iterate and, on return, of the
+ * last one; the iteration itself keeps x in float64, which x_out (device
+ * memory, [cells], or NULL) receives. *iterations (or NULL) receives the
+ * number of updates made. Returns MORAY_EINVAL for bad parameters, more than
+ * one grid or host fields (nothing is changed then), and the errors of
+ * moray_trace (x_hi then holds the last iterate). */
+moray_status moray_equilibrate(moray_ctx* ctx, const moray_problem* prob, unsigned flags,
+                               const moray_equilibrium_params* params, double* x_out, moray_result* out,
+                               int* iterations);
+
 /* Serving: queue n_probs problems (n_probs >= 1) for asynchronous tracing and
  * return at once with a ticket. Not part of the paper's method: this is the
  * request loop around it. A host thread of the context runs launch

@@ -24,6 +24,9 @@ hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
+hipError_t launch_equilibrium_update(hipStream_t, int, const double*, const float*, double*, float*, long long,
+                                     double, double, unsigned long long*);
+hipError_t launch_widen(hipStream_t, int, const float*, double*, long long, unsigned long long*);
 
 struct DevBuf {
   void* p = nullptr;
@@ -58,6 +61,7 @@ struct moray_ctx {
   moray::PlanHost* plan = nullptr;
   hipStream_t gstream = nullptr;   // stream of captured launch sequences
   hipEvent_t gev = nullptr;
+  moray::DevBuf eq_x, eq_kph, eq_heat, eq_dx;   // moray_equilibrate: float64 iterate, rates, largest change
 };
 
 namespace moray {

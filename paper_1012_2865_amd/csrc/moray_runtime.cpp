@@ -360,8 +360,9 @@ void moray_free(moray_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  DevBuf* all[] = {&c->grids, &c->probs, &c->sgs,     &c->stats,   &c->ctr,    &c->kappa,
-                   &c->acc,   &c->eexc,  &c->fblocks, &c->partial, &c->fields, &c->outs};
+  DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,
+                   &c->acc,     &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
+                   &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx};
   for (DevBuf* b : all) release(c, *b);
   for (int i = 0; i < 2; ++i) {
     release(c, c->q_pix[i]);
@@ -780,6 +781,57 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     c->err = "no error";
     return MORAY_OK;
   }
+}
+
+moray_status moray_equilibrate(moray_ctx* c, const moray_problem* prob, unsigned flags,
+                               const moray_equilibrium_params* ep, double* x_out, moray_result* out, int* iterations) {
+  if (!c) return MORAY_EINVAL;
+  if (!prob || !ep || !out) return fail(c, MORAY_EINVAL, "NULL problem, parameters or result");
+  if (!(ep->alpha_b > 0.0) || !(ep->damping > 0.0 && ep->damping <= 1.0) || !(ep->tol > 0.0) || ep->max_iter < 1)
+    return fail(c, MORAY_EINVAL, "alpha_b, damping, tol or max_iter out of range");
+  if (prob->n_grids != 1) return fail(c, MORAY_EINVAL, "the equilibrium iteration takes a single grid");
+  if (!(flags & MORAY_FIELDS_ON_DEVICE)) return fail(c, MORAY_EINVAL, "the equilibrium iteration needs device fields");
+  if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
+  moray_status st = validate(c, *prob, 0);
+  if (st != MORAY_OK) return st;
+  if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
+  const moray_grid& G = prob->grids[0];
+  const long long n = (long long)G.nx * G.ny * G.nz;
+  if ((st = ensure(c, c->eq_x, (size_t)n * 8, "equilibrium iterate")) ||
+      (st = ensure(c, c->eq_kph, (size_t)n * 8, "equilibrium rates")) ||
+      (st = ensure(c, c->eq_heat, (size_t)n * 8, "equilibrium rates")) ||
+      (st = ensure(c, c->eq_dx, 8, "equilibrium change")))
+    return st;
+  // the caller's x_hi array is the iterate the trace reads (updated in place, see moray.h)
+  float* x32 = const_cast<float*>(G.x_hi);
+  double* x64 = (double*)c->eq_x.p;
+  unsigned long long* dx = (unsigned long long*)c->eq_dx.p;
+  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n, dx), "equilibrium start")) return MORAY_EDEVICE;
+  moray_result mid{};
+  mid.k_ph = (double*)c->eq_kph.p;
+  mid.heating = (double*)c->eq_heat.p;
+  const unsigned mid_flags = flags | MORAY_OUT_ON_DEVICE;
+  int it = 0;
+  while (it < ep->max_iter) {
+    if ((st = moray_trace(c, prob, 1, mid_flags, &mid)) != MORAY_OK) return st;
+    ++it;
+    unsigned long long bits = 0;
+    if (!hip_ok(c, launch_equilibrium_update(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b,
+                                             ep->damping, dx),
+                "equilibrium update") ||
+        !hip_ok(c, hipMemcpyAsync(&bits, dx, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
+      return MORAY_EDEVICE;
+    double change;
+    std::memcpy(&change, &bits, 8);
+    if (change < ep->tol) break;
+  }
+  if ((st = moray_trace(c, prob, 1, flags, out)) != MORAY_OK) return st;
+  if (x_out && (!hip_ok(c, hipMemcpyAsync(x_out, x64, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream), "copy") ||
+                !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")))
+    return MORAY_EDEVICE;
+  if (iterations) *iterations = it;
+  return MORAY_OK;
 }
 
 moray_status moray_autotune(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, int max_trials,

@@ -74,14 +74,22 @@ class Result(ctypes.Structure):
                 ("t_done", ctypes.c_double), ("from_graph", ctypes.c_int)]
 
 
+class EquilibriumParams(ctypes.Structure):
+    _fields_ = [("alpha_b", ctypes.c_double), ("damping", ctypes.c_double), ("tol", ctypes.c_double),
+                ("max_iter", ctypes.c_int)]
+
+
+ALPHA_B = 2.59e-13   # case-B recombination coefficient at 1e4 K, cm^3/s (section 2.2)
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("chunk_rays", ctypes.c_int), ("refill_lanes", ctypes.c_int), ("reserve_rays", ctypes.c_int),
                 ("waves_per_cu", ctypes.c_int), ("first_ms", ctypes.c_double), ("best_ms", ctypes.c_double),
                 ("trials", ctypes.c_int)]
 
 
-ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_trace_async", "moray_query", "moray_free",
-                 "moray_last_error", "moray_version")
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_trace_async",
+                 "moray_query", "moray_free", "moray_last_error", "moray_version")
 
 _lib = None
 
@@ -100,6 +108,10 @@ def load_library(path: str = LIB_PATH):
         lib.moray_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                        ctypes.c_int, ctypes.POINTER(TuneResult)]
         lib.moray_autotune.restype = ctypes.c_int
+        lib.moray_equilibrate.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_uint,
+                                          ctypes.POINTER(EquilibriumParams), ctypes.c_void_p, ctypes.POINTER(Result),
+                                          ctypes.POINTER(ctypes.c_int)]
+        lib.moray_equilibrate.restype = ctypes.c_int
         lib.moray_trace_async.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                           ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_ulonglong)]
         lib.moray_trace_async.restype = ctypes.c_int
@@ -284,6 +296,28 @@ def moray_autotune(ctx, problems: Sequence, max_trials: int = 0) -> dict:
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
     return {name: getattr(r, name) for name, _ in TuneResult._fields_}
+
+
+def moray_equilibrate(ctx, problem, alpha_b: float = ALPHA_B, damping: float = 0.5, tol: float = 1e-6,
+                      max_iter: int = 300, out_on_device: bool = True, want_escaped_sg: bool = False,
+                      want_x64: bool = False):
+    """Photo-ionisation equilibrium of one single-grid problem whose fields
+    are torch CUDA tensors (see moray.h). The problem's x_hi tensor is updated
+    in place. Returns (result dict of the final trace, updates made, float64 x
+    as a torch tensor or None)."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal([problem], out_on_device, want_escaped_sg)
+    x64 = None
+    if want_x64:
+        import torch
+        x64 = torch.empty(problem.grids[0].n_h.shape, dtype=torch.float64, device="cuda")
+    it = ctypes.c_int(0)
+    ep = EquilibriumParams(float(alpha_b), float(damping), float(tol), int(max_iter))
+    rc = lib.moray_equilibrate(ctx, cprobs, flags, ctypes.byref(ep), x64.data_ptr() if x64 is not None else None,
+                               results, ctypes.byref(it))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return _unpack(results, outs, want_escaped_sg)[0], it.value, x64
 
 
 class Ticket:

@@ -74,6 +74,7 @@ int main(void) {
   S(moray_problem) O(moray_problem, params)
   S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
   O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)
+  S(moray_equilibrium_params) O(moray_equilibrium_params, tol) O(moray_equilibrium_params, max_iter)
   return 0;
 }
 """
@@ -87,13 +88,19 @@ def test_binding_struct_layout_matches_header():
         got = dict(line.split() for line in subprocess.check_output([exe], text=True).splitlines())
     py = {"moray_init_params": M.InitParams, "moray_source": M.Source, "moray_spectrum": M.Spectrum,
           "moray_grid": M.Grid, "moray_trace_params": M.TraceParams, "moray_problem": M.Problem,
-          "moray_result": M.Result}
+          "moray_result": M.Result, "moray_equilibrium_params": M.EquilibriumParams}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
             assert getattr(py[t], f).offset == int(val), key
         else:
             assert ctypes.sizeof(py[key]) == int(val), key
+
+
+def test_equilibrate_rejects_null_context():
+    lib = M.load_library()
+    ep = M.EquilibriumParams(M.ALPHA_B, 0.5, 1e-6, 10)
+    assert lib.moray_equilibrate(None, None, 1, ctypes.byref(ep), None, None, None) == M.MORAY_EINVAL
 
 
 def test_async_entry_points_reject_null_context():
