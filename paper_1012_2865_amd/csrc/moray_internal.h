@@ -24,6 +24,7 @@ hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
+// photo-ionisation equilibrium (moray_equilibrium.hip)
 hipError_t launch_equilibrium_update(hipStream_t, int, const double*, const float*, double*, float*, long long,
                                      double, double, unsigned long long*);
 hipError_t launch_widen(hipStream_t, int, const float*, double*, long long, unsigned long long*);
