@@ -206,6 +206,30 @@ typedef struct {
 
 typedef struct { int level; uint64_t pix; double r, P, P0; } oray;
 
+/* Covering factor of a segment (section 2.2.1, Eqs. midpoint and fc), in
+ * units of the local cell: the segment's midpoint lies D_c,i from the cell
+ * centre along each axis, D_edge = 1/2 - max_i D_c,i from the closest face;
+ * the pixel, taken as a square, is L_pix = R_0 theta_pix wide with R_0 the
+ * radius where the segment starts and theta_pix = sqrt(4 pi / N_pix);
+ * f_c = (1/2 + D_edge / L_pix)^2, and 1 once the pixel lies within the
+ * face (f_c >= 1, which includes R_0 = 0). sl: source in local cells; r, dr:
+ * entry radius and chord in root cells; h: local cells per root cell. */
+static double covering_factor(const double sl[3], const double n[3], const long c[3], double r, double dr,
+                              double h, int level) {
+  const double rmid = (r + 0.5 * dr) * h;
+  double dmax = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    const double d = fabs(sl[a] + rmid * n[a] - ((double)c[a] + 0.5));
+    if (d > dmax) dmax = d;
+  }
+  const double d_edge = 0.5 - dmax;
+  const double theta = sqrt(4.0 * PI_D / ldexp(12.0, 2 * level));
+  const double lpix = r * h * theta;
+  if (!(lpix > 0.0)) return 1.0;
+  const double f = 0.5 + d_edge / lpix;
+  return f * f >= 1.0 ? 1.0 : f * f;
+}
+
 /* Trace all seed rays of one (source, group) item, depth first. */
 static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* trunc) {
   const hier* H = J->H;
@@ -265,8 +289,9 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
           const double nabs = (double)G->n_h[cell] * (double)G->x_hi[cell];
           const double tau = sigma * nabs * ((dr * h) * G->dx_cm);
           const double dP = R.P * (-expm1(-tau));
-          A->absorbed[H->cell_off[q] + cell] += dP;
-          A->energy[H->cell_off[q] + cell] += dP * eexc;
+          const double fc = J->par->covering ? covering_factor(sl, n, c, R.r, dr, h, R.level) : 1.0;
+          A->absorbed[H->cell_off[q] + cell] += dP * fc;
+          A->energy[H->cell_off[q] + cell] += dP * fc * eexc;
           R.P -= dP;
           A->segments++;
           R.r = t_exit;

@@ -49,7 +49,7 @@ class _Spectrum(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("phi_c", ctypes.c_double), ("level_init", ctypes.c_int), ("level_max", ctypes.c_int),
-                ("p_min_frac", ctypes.c_double)]
+                ("p_min_frac", ctypes.c_double), ("covering", ctypes.c_int)]
 
 
 class _Totals(ctypes.Structure):
@@ -126,7 +126,8 @@ def trace(problem, n_threads: int = 1) -> dict:
     dp = ctypes.POINTER(ctypes.c_double)
     spec = _Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
     pr = problem.params
-    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac))
+    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
+                  1 if getattr(pr, "covering", False) else 0)
     n_cells = sum(int(np.asarray(g.n_h).size) for g in problem.grids)
     absorbed = np.zeros(n_cells)
     energy = np.zeros(n_cells)
