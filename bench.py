@@ -13,7 +13,7 @@ it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
-  python bench.py --equilibrium-only
+  python bench.py --equilibrium-only | --covering-only [--steps K]
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
@@ -278,6 +278,28 @@ def _equilibrium_c1(M, updates=20):
             "ionised_fraction_final": float(1.0 - x.double().mean()), "dtype": "f32+f64acc"}
 
 
+def _covering_c1(M, steps):
+    """The 128^3 workload with the covering-factor correction of k_ph and
+    heating switched on (section 2.3), mixed precision, beside the plain
+    trace under the same launch settings."""
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    plain = W.config1()
+    cov = W.config1()
+    cov.params = W.Params(**{**cov.params.__dict__, "covering": True})
+    dp, dc = [M.problem_to_device(plain)], [M.problem_to_device(cov)]
+    torch.cuda.synchronize()
+    ctx, _ = _tuned(M, M.MORAY_FP32_ACC64, dp)
+    try:
+        sp, segp, _ = _time_steps(M, ctx, dp, steps, 2)
+        sc, segc, res = _time_steps(M, ctx, dc, steps, 2)
+    finally:
+        M.moray_free(ctx)
+    return {"workload": "lognormal128_16src_4grp with covering factor", "ms_per_step": sc * 1e3,
+            "segments_per_s": segc / sc, "plain_ms_per_step": sp * 1e3, "overhead": sc / sp - 1.0,
+            "absorbed_over_plain_emitted": res[0]["absorbed"] / res[0]["emitted"], "dtype": "f32+f64acc"}
+
+
 def _batched_c2(M, steps):
     """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
     form traces all of them in one call (one launch sequence) in mixed
@@ -393,6 +415,8 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="10,20,50,100,200,500")
     ap.add_argument("--equilibrium-only", action="store_true",
                     help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
+    ap.add_argument("--covering-only", action="store_true",
+                    help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
@@ -418,6 +442,9 @@ def main():
     from paper_1012_2865_amd import moray as M
     if args.equilibrium_only:
         print(json.dumps(_equilibrium_c1(M)), flush=True)
+        return
+    if args.covering_only:
+        print(json.dumps(_covering_c1(M, args.steps)), flush=True)
         return
     if args.serve_only:
         for rate in (float(x) for x in args.serve_rates.split(",")):
@@ -495,6 +522,9 @@ def main():
         extras["equilibrium"] = _equilibrium_c1(M)
         print(f"# equilibrium: {extras['equilibrium']['ms_per_trace']:.2f} ms per trace + update", file=sys.stderr,
               flush=True)
+        extras["covering"] = _covering_c1(M, max(2, args.steps // 2))
+        print(f"# covering factor: {extras['covering']['ms_per_step']:.2f} ms per step "
+              f"({100 * extras['covering']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
         extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
         print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)

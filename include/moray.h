@@ -106,6 +106,10 @@ typedef struct {
   int level_init;             /* HEALPix level of the seed rays, 0 <= level_init <= level_max */
   int level_max;              /* rays at this level never split, <= 29 */
   double p_min_frac;          /* a ray ends once P < p_min_frac * P0, in [0, 1) */
+  int covering;               /* nonzero: scale each segment's contribution to k_ph and heating (not
+                                 its attenuation) by the covering factor of section 2.3 (Eqs.
+                                 midpoint, fc); the results are then not photon-conserving, and
+                                 `absorbed` reports the scaled sum */
 } moray_trace_params;
 
 typedef struct {

@@ -206,7 +206,7 @@ typedef struct {
 
 typedef struct { int level; uint64_t pix; double r, P, P0; } oray;
 
-/* Covering factor of a segment (section 2.2.1, Eqs. midpoint and fc), in
+/* Covering factor of a segment (section 2.3, Eqs. midpoint and fc), in
  * units of the local cell: the segment's midpoint lies D_c,i from the cell
  * centre along each axis, D_edge = 1/2 - max_i D_c,i from the closest face;
  * the pixel, taken as a square, is L_pix = R_0 theta_pix wide with R_0 the

@@ -45,7 +45,7 @@ typedef struct {
   double p_min_frac;       /* a ray ends once P < p_min_frac * P0 */
   int covering;            /* nonzero: scale each segment's contribution to the absorbed
                               and energy rates (not its attenuation) by the covering
-                              factor f_c of section 2.2.1 (Eqs. midpoint, fc) */
+                              factor f_c of section 2.3 (Eqs. midpoint, fc) */
 } orc_params;
 
 typedef struct {

@@ -67,6 +67,7 @@ struct SgDev {
   double sigma64;          // cross-section, cm^2
   double four_pi_phi_c;    // 4 pi phi_c of its problem
   int problem;
+  int covering;            // scale deposits into the accumulators by the covering factor
 };
 
 struct SgStats {

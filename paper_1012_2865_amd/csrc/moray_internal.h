@@ -20,14 +20,16 @@ template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
                        Counters*);
 template <typename R>
-hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool);
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
 // photo-ionisation equilibrium (moray_equilibrium.hip)
-hipError_t launch_equilibrium_update(hipStream_t, int, const double*, const float*, double*, float*, long long,
-                                     double, double, unsigned long long*);
-hipError_t launch_widen(hipStream_t, int, const float*, double*, long long, unsigned long long*);
+// dx: 1 + kEqMaxBlocks doubles; dx[0] receives the largest change of the pass
+constexpr int kEqMaxBlocks = 2048;
+hipError_t launch_equilibrium_update(hipStream_t, const double* kph, const float* n_h, double* x64, float* x32,
+                                     long long n, double alpha_b, double w, double* dx);
+hipError_t launch_widen(hipStream_t, int num_cu, const float* x32, double* x64, long long n);
 
 struct DevBuf {
   void* p = nullptr;

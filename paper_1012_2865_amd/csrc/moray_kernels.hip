@@ -160,6 +160,7 @@ struct Geom64 {
 
   __device__ void set_dir(const double v[3]) { d0 = v[0]; d1 = v[1]; d2 = v[2]; }
   __device__ double dir64(int k) const { return sel3(k, d0, d1, d2); }
+  __device__ double src64(int k) const { return sel3(k, s0, s1, s2); }
   __device__ float dirf(int k) const { return (float)sel3(k, d0, d1, d2); }
   __device__ void set_radius(double r64) { r = r64; }
   __device__ double radius64() const { return r; }
@@ -233,6 +234,7 @@ struct Geom32 {
     j = (float)(inv - (double)i);
   }
   __device__ double dir64(int k) const { return lane_dir()[k * kTraceBlock]; }
+  __device__ double src64(int k) const { return (double)sel3(k, q0, q1, q2) + (double)sel3(k, e0, e1, e2); }
   __device__ float dirf(int k) const { return sel3(k, d0, d1, d2); }
   __device__ void set_radius(double r64) { rh = (float)r64; rl = (float)(r64 - (double)rh); }
   __device__ double radius64() const { return (double)rh + (double)rl; }
@@ -359,6 +361,7 @@ struct Ray {
   int level;              // HEALPix level of the tree's rays in this launch
   double sx, sy, sz, P0;
   int root, rn0, rn1, rn2, rcell;
+  bool cover;             // its deposits are scaled by the covering factor
 };
 
 template <typename R>
@@ -478,6 +481,7 @@ struct Tracer {
     L.root = S.root_grid;
     L.rn0 = S.rnx; L.rn1 = S.rny; L.rn2 = S.rnz;
     L.rcell = (int)S.rcell_off;
+    L.cover = S.covering != 0;
     const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.sigma = S.sigma32;
@@ -573,6 +577,30 @@ struct Tracer {
       const double u = L.g.local_u(ax);
       return L.split_t < L.fpp * (u * u);
     }
+  }
+
+  // Covering factor of the segment that starts at the current radius R_0 and
+  // has chord dr (root cells), section 2.3: D_edge = 1/2 - max_i D_c,i is
+  // the distance from the segment's midpoint to the nearest face of its cell,
+  // L_pix = R_0 theta_pix the pixel's width at entry (theta_pix =
+  // sqrt(4 pi / N_pix) = sqrt(pi/3) 2^-l), both in local cells, and
+  // f_c = (1/2 + D_edge / L_pix)^2, at most 1 (1 also for R_0 = 0). Float64
+  // throughout, from the float64 direction and source.
+  __device__ double covering_factor(const Ray<R>& L, double dr) const {
+    const double h = (double)L.g.hloc;
+    const double r0 = L.g.radius64();
+    const double rmid = (r0 + 0.5 * dr) * h;
+    const int c[3] = {L.c0, L.c1, L.c2};
+    double dmax = 0.0;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) {
+      const double d = fabs(L.g.src64(k) + rmid * L.g.dir64(k) - ((double)c[k] + 0.5));
+      dmax = d > dmax ? d : dmax;
+    }
+    const double lpix = r0 * h * ldexp(1.0233267079464885, -L.level);   // sqrt(pi/3) = 1.02332670794648848...
+    if (!(lpix > 0.0)) return 1.0;
+    const double f = 0.5 + (0.5 - dmax) / lpix;
+    return f * f >= 1.0 ? 1.0 : f * f;
   }
 };
 
@@ -860,7 +888,8 @@ struct SplitStage {
 // which the LDS of a block (four waves) also allows.
 template <typename R> struct TraceWaves { static constexpr int n = 3; };
 
-template <typename R, bool CACHE>
+// COVER: some tree of the launch scales its deposits by the covering factor.
+template <typename R, bool CACHE, bool COVER>
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(TraceWaves<R>::n)))
 void trace_level_kernel(TraceArgs<R> a) {
   const int lane = threadIdx.x & (kWave - 1);
@@ -1031,6 +1060,9 @@ void trace_level_kernel(TraceArgs<R> a) {
       if (L.g.positive(dr, ax)) {
         const R tau = L.kap * L.sigma * dr;
         dval = absorb(L.P, tau);
+        if constexpr (COVER) {
+          if (L.cover) dval *= T.covering_factor(L, (double)dr);
+        }
         dkey = L.slot0 + (uint32_t)L.lin;
         dep = true;
         L.segs++;
@@ -1250,9 +1282,15 @@ hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_gr
 }
 
 template <typename R>
-hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache) {
-  if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
-  else hipLaunchKernelGGL((trace_level_kernel<R, false>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache, bool cover) {
+  const dim3 grid(blocks), block(kTraceBlock);
+  if (cover) {
+    if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, true>), grid, block, 0, s, args);
+    else hipLaunchKernelGGL((trace_level_kernel<R, false, true>), grid, block, 0, s, args);
+  } else {
+    if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, false>), grid, block, 0, s, args);
+    else hipLaunchKernelGGL((trace_level_kernel<R, false, false>), grid, block, 0, s, args);
+  }
   return hipGetLastError();
 }
 
@@ -1269,15 +1307,15 @@ template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, in
                                        long long, float*, double*, Counters*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
                                         long long, double*, double*, Counters*);
-template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool);
-template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool);
+template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool);
+template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool);
 
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu) {
   if (precision == 0)
-    return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, true>, kTraceBlock, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, false>, kTraceBlock, 0);
-  return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, true>, kTraceBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, false>, kTraceBlock, 0);
+    return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, true, false>, kTraceBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, false, false>, kTraceBlock, 0);
+  return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, true, false>, kTraceBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, false, false>, kTraceBlock, 0);
 }
 
 }  // namespace moray

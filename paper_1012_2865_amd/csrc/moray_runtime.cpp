@@ -462,6 +462,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   }
   if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
   const bool cache_ok = n_acc < (long long)kNoSlot;   // cache keys are 32-bit accumulator indices
+  bool cover = false;                                   // some problem scales its deposits by the covering factor
+  for (int i = 0; i < n_probs; ++i) cover = cover || probs[i].params.covering != 0;
 
   // finalize blocks: each covers up to kFinalBlock*kFinalCellsPerThread cells of one grid
   std::vector<FinalBlock> fblocks;
@@ -504,6 +506,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPiConst * P.params.phi_c)) : FLT_MAX;
     d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
     d.problem = K.prob;
+    d.covering = P.params.covering != 0;
     d.root_grid = pd.root_grid;
     d.rnx = grids[pd.root_grid].nx; d.rny = grids[pd.root_grid].ny; d.rnz = grids[pd.root_grid].nz;
     d.rcell_off = grids[pd.root_grid].cell_off;
@@ -696,7 +699,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok);
+          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok, cover);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -705,7 +708,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok);
+          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok, cover);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], strm);
@@ -800,13 +803,13 @@ moray_status moray_equilibrate(moray_ctx* c, const moray_problem* prob, unsigned
   if ((st = ensure(c, c->eq_x, (size_t)n * 8, "equilibrium iterate")) ||
       (st = ensure(c, c->eq_kph, (size_t)n * 8, "equilibrium rates")) ||
       (st = ensure(c, c->eq_heat, (size_t)n * 8, "equilibrium rates")) ||
-      (st = ensure(c, c->eq_dx, 8, "equilibrium change")))
+      (st = ensure(c, c->eq_dx, (size_t)(1 + kEqMaxBlocks) * 8, "equilibrium change")))
     return st;
   // the caller's x_hi array is the iterate the trace reads (updated in place, see moray.h)
   float* x32 = const_cast<float*>(G.x_hi);
   double* x64 = (double*)c->eq_x.p;
-  unsigned long long* dx = (unsigned long long*)c->eq_dx.p;
-  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n, dx), "equilibrium start")) return MORAY_EDEVICE;
+  double* dx = (double*)c->eq_dx.p;
+  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n), "equilibrium start")) return MORAY_EDEVICE;
   moray_result mid{};
   mid.k_ph = (double*)c->eq_kph.p;
   mid.heating = (double*)c->eq_heat.p;
@@ -815,15 +818,12 @@ moray_status moray_equilibrate(moray_ctx* c, const moray_problem* prob, unsigned
   while (it < ep->max_iter) {
     if ((st = moray_trace(c, prob, 1, mid_flags, &mid)) != MORAY_OK) return st;
     ++it;
-    unsigned long long bits = 0;
-    if (!hip_ok(c, launch_equilibrium_update(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b,
-                                             ep->damping, dx),
+    double change = 0.0;
+    if (!hip_ok(c, launch_equilibrium_update(c->stream, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b, ep->damping, dx),
                 "equilibrium update") ||
-        !hip_ok(c, hipMemcpyAsync(&bits, dx, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !hip_ok(c, hipMemcpyAsync(&change, dx, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
         !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
       return MORAY_EDEVICE;
-    double change;
-    std::memcpy(&change, &bits, 8);
     if (change < ep->tol) break;
   }
   if ((st = moray_trace(c, prob, 1, flags, out)) != MORAY_OK) return st;

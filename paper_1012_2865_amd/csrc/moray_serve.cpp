@@ -390,6 +390,7 @@ moray_status write_tables(Engine* E, ServeProblem* p) {
       d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPiConst * P.params.phi_c)) : FLT_MAX;
       d.acc_slot = pd.acc_off + (long long)g * pd.n_cells - pd.cell_off;
       d.problem = p->pslot;
+      d.covering = P.params.covering != 0;
       d.root_grid = p->gbase;
       d.rnx = rg.nx; d.rny = rg.ny; d.rnz = rg.nz;
       d.rcell_off = rg.cell_off;
@@ -663,8 +664,10 @@ bool trip(Engine* E) {
   const int cin = g & 1, cout = (g + 1) & 1;
   unsigned max_steps = 64;
   int tlo = E->tree_cap, thi = 0;
+  bool cover = false;               // some running problem scales its deposits by the covering factor
   for (ServeProblem* p : E->running) {
     max_steps = std::max(max_steps, p->max_steps);
+    cover = cover || p->prob.params.covering != 0;
     if (p->ntrees) {
       tlo = std::min(tlo, p->tbase);
       thi = std::max(thi, p->tbase + p->ntrees);
@@ -689,7 +692,7 @@ bool trip(Engine* E) {
       A.gen = g; A.cin = cin; A.cout = cout; A.seed_level = seed_level;
       A.seed_sg_begin = seed_lo; A.seed_sg_end = seed_hi;
       A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = E->reserve;
-      e = launch_trace_level<float>(s, blocks, A, c->cache);
+      e = launch_trace_level<float>(s, blocks, A, c->cache, cover);
     } else {
       TraceArgs<double> A{};
       A.grids = (GridDev*)E->grids.p; A.probs = (ProblemDev*)E->probs.p; A.sgs = (SgDev*)E->sgs.p;
@@ -698,7 +701,7 @@ bool trip(Engine* E) {
       A.gen = g; A.cin = cin; A.cout = cout; A.seed_level = seed_level;
       A.seed_sg_begin = seed_lo; A.seed_sg_end = seed_hi;
       A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = E->reserve;
-      e = launch_trace_level<double>(s, blocks, A, c->cache);
+      e = launch_trace_level<double>(s, blocks, A, c->cache, cover);
     }
   }
   if (!eok(E, e, "trace") ||

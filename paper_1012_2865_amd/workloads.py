@@ -75,7 +75,7 @@ class Params:
     level_init: int = 1         # HEALPix level of the seed rays
     level_max: int = 14         # rays at this level never split
     p_min_frac: float = 1e-8    # a ray ends when P < p_min_frac * P0
-    covering: bool = False      # scale k_ph and heating by the covering factor (section 2.2.1)
+    covering: bool = False      # scale k_ph and heating by the covering factor (section 2.3)
 
 
 @dataclass

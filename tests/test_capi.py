@@ -70,7 +70,7 @@ int main(void) {
   S(moray_init_params) O(moray_init_params, hip_stream) O(moray_init_params, profile) O(moray_init_params, deposit_cache) O(moray_init_params, reserve_rays)
   S(moray_source) S(moray_spectrum) O(moray_spectrum, e_ion_ev)
   S(moray_grid) O(moray_grid, offset) O(moray_grid, n_h) O(moray_grid, x_hi)
-  S(moray_trace_params) O(moray_trace_params, p_min_frac)
+  S(moray_trace_params) O(moray_trace_params, p_min_frac) O(moray_trace_params, covering)
   S(moray_problem) O(moray_problem, params)
   S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
   O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)

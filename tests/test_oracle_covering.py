@@ -1,4 +1,4 @@
-"""Pins of the oracle's covering-factor correction (section 2.2.1, Eqs.
+"""Pins of the oracle's covering-factor correction (section 2.3, Eqs.
 midpoint and fc), none of which re-types the oracle's formula:
 
 * Closed form on axis rays. With phi_c = 0 the level-0 base pixels 4 and 6
@@ -14,7 +14,7 @@ midpoint and fc), none of which re-types the oracle's formula:
   corrected rate is between a quarter and all of the plain one.
 * The paper's purpose for it: in the optically thin test the corrected k_ph
   scatters less about sigma Ndot e^-tau / (4 pi r^2) than the plain one at low
-  phi_c (section 7.2, the covering-factor improvements).
+  phi_c (section 8.1, the improvements from the covering factor).
 """
 import math
 
