@@ -13,7 +13,7 @@ it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
-  python bench.py --equilibrium-only | --covering-only [--steps K]
+  python bench.py --equilibrium-only | --evolve-only | --covering-only [--steps K]
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
@@ -300,6 +300,41 @@ def _covering_c1(M, steps):
             "absorbed_over_plain_emitted": res[0]["absorbed"] / res[0]["emitted"], "dtype": "f32+f64acc"}
 
 
+def _evolve_test1(M):
+    """The paper's Test 1 (section 4.1) end to end on the device: a 5e48 ph/s
+    source at the corner of a 6.6 kpc, 64^3 box of n_H = 1e-3, evolved for
+    500 Myr with moray_evolve (eps_ion = 0.1, steps of at most t_rec / 400),
+    mixed precision; the ionised volume's equivalent radius against
+    R_s (1 - e^{-t/t_rec})^{1/3}."""
+    import math
+    import numpy as np
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    n, box, alpha = 64, 6.6 * W.KPC_CM, M.ALPHA_B
+    t_rec, myr = 1.0 / (alpha * 1e-3), 3.15576e13
+
+    def problem():
+        g = W.uniform_grid(n, box / n, 1e-3, 1.0 - 1.2e-3)
+        return M.problem_to_device(W.Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), W.hydrogen_spectrum([13.6]),
+                                             W.Params()))
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        M.moray_evolve(ctx, problem(), 10 * myr, dt_max=t_rec / 400)               # warm-up
+        pd = problem()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res, steps, t, x64, _ = M.moray_evolve(ctx, pd, 500 * myr, dt_max=t_rec / 400, want_x64=True)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        x = x64.cpu().numpy()
+    finally:
+        M.moray_free(ctx)
+    r = (6.0 * float(np.sum(1.0 - x)) * (box / n) ** 3 / math.pi) ** (1.0 / 3.0)
+    rs = (3.0 * 5e48 / (4.0 * math.pi * alpha * 1e-6)) ** (1.0 / 3.0) * (1.0 - math.exp(-t / t_rec)) ** (1.0 / 3.0)
+    return {"workload": "Test 1 (64^3, 6.6 kpc, 5e48 ph/s) to 500 Myr", "steps": steps, "s_total": dt,
+            "ms_per_step": dt * 1e3 / steps, "front_over_analytic": r / rs, "dtype": "f32+f64acc"}
+
+
 def _batched_c2(M, steps):
     """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
     form traces all of them in one call (one launch sequence) in mixed
@@ -415,6 +450,8 @@ def main():
     ap.add_argument("--serve-rates", type=str, default="10,20,50,100,200,500")
     ap.add_argument("--equilibrium-only", action="store_true",
                     help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
+    ap.add_argument("--evolve-only", action="store_true",
+                    help="print the time-stepped Test 1 measurement (64^3 to 500 Myr) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--counter-pass", action="store_true",
@@ -442,6 +479,9 @@ def main():
     from paper_1012_2865_amd import moray as M
     if args.equilibrium_only:
         print(json.dumps(_equilibrium_c1(M)), flush=True)
+        return
+    if args.evolve_only:
+        print(json.dumps(_evolve_test1(M)), flush=True)
         return
     if args.covering_only:
         print(json.dumps(_covering_c1(M, args.steps)), flush=True)
@@ -525,6 +565,9 @@ def main():
         extras["covering"] = _covering_c1(M, max(2, args.steps // 2))
         print(f"# covering factor: {extras['covering']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['covering']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
+        extras["evolve_test1"] = _evolve_test1(M)
+        print(f"# Test 1 to 500 Myr: {extras['evolve_test1']['steps']} steps in "
+              f"{extras['evolve_test1']['s_total']:.2f} s", file=sys.stderr, flush=True)
         extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
         print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)

@@ -214,6 +214,48 @@ moray_status moray_equilibrate(moray_ctx* ctx, const moray_problem* prob, unsign
                                const moray_equilibrium_params* params, double* x_out, moray_result* out,
                                int* iterations);
 
+/* Settings of moray_evolve. */
+typedef struct {
+  double alpha_b;             /* case-B recombination coefficient, cm^3/s (2.59e-13 at 1e4 K), > 0 */
+  double eps_ion;             /* largest fractional change of the neutral density per step (Eq. dtelec), > 0 */
+  double tau_front;           /* a cell limits the step when its own optical depth sigma_bar n_H x dx
+                                 exceeds this (0.5), >= 0 */
+  double dt_max;              /* step of the cells outside the front and bound of every step, s, > 0 */
+  double t_end;               /* time to evolve for, s, > 0 */
+  int max_steps;              /* at most this many steps, >= 1 */
+} moray_evolve_params;
+
+/* Time-stepped photo-ionisation (the radiative-transfer timestep of section
+ * 3.4.1 around the cycle of section 3.1, with the hydrogen-only rate equation
+ * of section 2.2, Eq. dndt, as its chemistry step: no collisional term,
+ * n_e = n_p = (1 - x) n_H for the neutral fraction x). From the problem's x_hi
+ * and t = 0, each step
+ *   1. traces with the current x (k_ph per cell, as moray_trace);
+ *   2. takes per cell dt_cell = eps_ion / (k_ph + n_e alpha_b) (Eq. dtelec)
+ *      where the cell's own optical depth sigma_bar n_H x dx exceeds tau_front
+ *      (sigma_bar = sum_g photon_frac_g sigma_g), dt_max elsewhere, and at
+ *      most dt_max; smooths that field over 3^3 cells with the binomial
+ *      weights (1/4, 1/2, 1/4) per axis, normalised over the neighbours inside
+ *      the grid; dt = its minimum, at most twice the previous step (Eq.
+ *      dtchange, from the second step on), dt_max and t_end - t;
+ *   3. advances every cell by the exact solution over dt of
+ *      dx/dt = alpha_b n_H (1 - x)^2 - k_ph x with k_ph held (cells with
+ *      n_H = 0 keep x), and t += dt;
+ * until t reaches t_end or max_steps steps are done; then traces once more
+ * with the final x into `out` (host or device results by flags, as in
+ * moray_trace; escaped_sg is filled when given).
+ * The problem must have a single grid and device-resident fields (flags must
+ * include MORAY_FIELDS_ON_DEVICE). Its x_hi array is updated in place and
+ * holds the float32 neutral fraction of every step; the evolution keeps x in
+ * float64, which x_out (device memory, [cells], or NULL) receives. *steps,
+ * *t_reached and dt_steps (host memory, [max_steps]) receive, when not NULL,
+ * the steps taken, the time reached and each step's dt. Returns MORAY_EINVAL
+ * for bad parameters, more than one grid or host fields (nothing is changed
+ * then), and the errors of moray_trace (x_hi then holds the last step's x). */
+moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned flags,
+                          const moray_evolve_params* params, double* x_out, moray_result* out, int* steps,
+                          double* t_reached, double* dt_steps);
+
 /* Serving: queue n_probs problems (n_probs >= 1) for asynchronous tracing and
  * return at once with a ticket. Not part of the paper's method: this is the
  * request loop around it. A host thread of the context runs launch

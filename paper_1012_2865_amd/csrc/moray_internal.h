@@ -30,6 +30,12 @@ constexpr int kEqMaxBlocks = 2048;
 hipError_t launch_equilibrium_update(hipStream_t, const double* kph, const float* n_h, double* x64, float* x32,
                                      long long n, double alpha_b, double w, double* dx);
 hipError_t launch_widen(hipStream_t, int num_cu, const float* x32, double* x64, long long n);
+// moray_evolve: lim receives the per-cell limits, dmin (1 + kEqMaxBlocks doubles) their smoothed minimum in dmin[0]
+hipError_t launch_step_limit(hipStream_t, int num_cu, const double* kph, const float* n_h, const double* x64, int nx,
+                             int ny, int nz, double alpha_b, double sigma_bar, double dx_cm, double eps,
+                             double tau_front, double dt_max, double* lim, double* dmin);
+hipError_t launch_evolve_update(hipStream_t, int num_cu, const double* kph, const float* n_h, double* x64, float* x32,
+                                long long n, double alpha_b, double dt);
 
 struct DevBuf {
   void* p = nullptr;
@@ -64,7 +70,9 @@ struct moray_ctx {
   moray::PlanHost* plan = nullptr;
   hipStream_t gstream = nullptr;   // stream of captured launch sequences
   hipEvent_t gev = nullptr;
-  moray::DevBuf eq_x, eq_kph, eq_heat, eq_dx;   // moray_equilibrate: float64 iterate, rates, largest change
+  moray::DevBuf eq_x, eq_kph, eq_heat, eq_dx;   // moray_equilibrate / moray_evolve: float64 iterate, rates,
+                                                 // reduction partials
+  moray::DevBuf ev_lim;                          // moray_evolve: per-cell step limits
 };
 
 namespace moray {

@@ -362,7 +362,7 @@ void moray_free(moray_ctx* c) {
   else (void)hipDeviceSynchronize();
   DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,
                    &c->acc,     &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
-                   &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx};
+                   &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx,  &c->ev_lim};
   for (DevBuf* b : all) release(c, *b);
   for (int i = 0; i < 2; ++i) {
     release(c, c->q_pix[i]);
@@ -831,6 +831,71 @@ moray_status moray_equilibrate(moray_ctx* c, const moray_problem* prob, unsigned
                 !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")))
     return MORAY_EDEVICE;
   if (iterations) *iterations = it;
+  return MORAY_OK;
+}
+
+moray_status moray_evolve(moray_ctx* c, const moray_problem* prob, unsigned flags, const moray_evolve_params* ep,
+                          double* x_out, moray_result* out, int* steps, double* t_reached, double* dt_steps) {
+  if (!c) return MORAY_EINVAL;
+  if (!prob || !ep || !out) return fail(c, MORAY_EINVAL, "NULL problem, parameters or result");
+  if (!(ep->alpha_b > 0.0) || !(ep->eps_ion > 0.0) || !(ep->tau_front >= 0.0) || !(ep->dt_max > 0.0) ||
+      !(ep->t_end > 0.0) || !std::isfinite(ep->t_end) || !std::isfinite(ep->dt_max) || ep->max_steps < 1)
+    return fail(c, MORAY_EINVAL, "alpha_b, eps_ion, tau_front, dt_max, t_end or max_steps out of range");
+  if (prob->n_grids != 1) return fail(c, MORAY_EINVAL, "the time-stepped evolution takes a single grid");
+  if (!(flags & MORAY_FIELDS_ON_DEVICE)) return fail(c, MORAY_EINVAL, "the time-stepped evolution needs device fields");
+  if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
+  moray_status st = validate(c, *prob, 0);
+  if (st != MORAY_OK) return st;
+  if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
+  const moray_grid& G = prob->grids[0];
+  const long long n = (long long)G.nx * G.ny * G.nz;
+  if ((st = ensure(c, c->eq_x, (size_t)n * 8, "evolution iterate")) ||
+      (st = ensure(c, c->eq_kph, (size_t)n * 8, "evolution rates")) ||
+      (st = ensure(c, c->eq_heat, (size_t)n * 8, "evolution rates")) ||
+      (st = ensure(c, c->ev_lim, (size_t)n * 8, "evolution step limits")) ||
+      (st = ensure(c, c->eq_dx, (size_t)(1 + kEqMaxBlocks) * 8, "evolution step")))
+    return st;
+  // photon-weighted cross-section of the spectrum: the front test's sigma
+  const moray_spectrum& Sp = *prob->spectrum;
+  double sigma_bar = 0.0;
+  for (int g = 0; g < Sp.n_groups; ++g) sigma_bar += Sp.photon_frac[g] * Sp.sigma_cm2[g];
+  // the caller's x_hi array is the field the trace reads (updated in place, see moray.h)
+  float* x32 = const_cast<float*>(G.x_hi);
+  double* x64 = (double*)c->eq_x.p;
+  double* dmin = (double*)c->eq_dx.p;
+  double* lim = (double*)c->ev_lim.p;
+  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n), "evolution start")) return MORAY_EDEVICE;
+  moray_result mid{};
+  mid.k_ph = (double*)c->eq_kph.p;
+  mid.heating = (double*)c->eq_heat.p;
+  const unsigned mid_flags = flags | MORAY_OUT_ON_DEVICE;
+  double t = 0.0, dt_prev = 0.0;
+  int k = 0;
+  while (t < ep->t_end && k < ep->max_steps) {
+    if ((st = moray_trace(c, prob, 1, mid_flags, &mid)) != MORAY_OK) return st;
+    double dt = 0.0;
+    if (!hip_ok(c, launch_step_limit(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, G.nx, G.ny, G.nz, ep->alpha_b,
+                                     sigma_bar, G.dx_cm, ep->eps_ion, ep->tau_front, ep->dt_max, lim, dmin),
+                "evolution step") ||
+        !hip_ok(c, hipMemcpyAsync(&dt, dmin, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
+        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
+      return MORAY_EDEVICE;
+    if (k > 0) dt = std::min(dt, 2.0 * dt_prev);          // Eq. dtchange
+    dt = std::min(dt, std::min(ep->dt_max, ep->t_end - t));
+    if (!hip_ok(c, launch_evolve_update(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b, dt),
+                "evolution update"))
+      return MORAY_EDEVICE;
+    t += dt;
+    dt_prev = dt;
+    if (dt_steps) dt_steps[k] = dt;
+    ++k;
+  }
+  if ((st = moray_trace(c, prob, 1, flags, out)) != MORAY_OK) return st;
+  if (x_out && (!hip_ok(c, hipMemcpyAsync(x_out, x64, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream), "copy") ||
+                !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")))
+    return MORAY_EDEVICE;
+  if (steps) *steps = k;
+  if (t_reached) *t_reached = t;
   return MORAY_OK;
 }
 

@@ -82,14 +82,19 @@ class EquilibriumParams(ctypes.Structure):
 ALPHA_B = 2.59e-13   # case-B recombination coefficient at 1e4 K, cm^3/s (section 2.2)
 
 
+class EvolveParams(ctypes.Structure):
+    _fields_ = [("alpha_b", ctypes.c_double), ("eps_ion", ctypes.c_double), ("tau_front", ctypes.c_double),
+                ("dt_max", ctypes.c_double), ("t_end", ctypes.c_double), ("max_steps", ctypes.c_int)]
+
+
 class TuneResult(ctypes.Structure):
     _fields_ = [("chunk_rays", ctypes.c_int), ("refill_lanes", ctypes.c_int), ("reserve_rays", ctypes.c_int),
                 ("waves_per_cu", ctypes.c_int), ("first_ms", ctypes.c_double), ("best_ms", ctypes.c_double),
                 ("trials", ctypes.c_int)]
 
 
-ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_trace_async",
-                 "moray_query", "moray_free", "moray_last_error", "moray_version")
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_evolve",
+                 "moray_trace_async", "moray_query", "moray_free", "moray_last_error", "moray_version")
 
 _lib = None
 
@@ -112,6 +117,11 @@ def load_library(path: str = LIB_PATH):
                                           ctypes.POINTER(EquilibriumParams), ctypes.c_void_p, ctypes.POINTER(Result),
                                           ctypes.POINTER(ctypes.c_int)]
         lib.moray_equilibrate.restype = ctypes.c_int
+        lib.moray_evolve.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_uint,
+                                     ctypes.POINTER(EvolveParams), ctypes.c_void_p, ctypes.POINTER(Result),
+                                     ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
+                                     ctypes.POINTER(ctypes.c_double)]
+        lib.moray_evolve.restype = ctypes.c_int
         lib.moray_trace_async.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                           ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_ulonglong)]
         lib.moray_trace_async.restype = ctypes.c_int
@@ -319,6 +329,34 @@ def moray_equilibrate(ctx, problem, alpha_b: float = ALPHA_B, damping: float = 0
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
     return _unpack(results, outs, want_escaped_sg)[0], it.value, x64
+
+
+def moray_evolve(ctx, problem, t_end: float, eps_ion: float = 0.1, tau_front: float = 0.5,
+                 dt_max: float | None = None, max_steps: int = 100000, alpha_b: float = ALPHA_B,
+                 out_on_device: bool = True, want_escaped_sg: bool = False, want_x64: bool = False,
+                 want_dts: bool = False):
+    """Time-stepped photo-ionisation of one single-grid problem whose fields
+    are torch CUDA tensors (see moray.h), for t_end seconds; dt_max defaults
+    to t_end. The problem's x_hi tensor is updated in place. Returns (result
+    dict of the final trace, steps taken, time reached, float64 x as a torch
+    tensor or None, numpy array of the steps' dt or None)."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal([problem], out_on_device, want_escaped_sg)
+    x64 = None
+    if want_x64:
+        import torch
+        x64 = torch.empty(problem.grids[0].n_h.shape, dtype=torch.float64, device="cuda")
+    dts = np.zeros(max(1, int(max_steps)), dtype=np.float64) if want_dts else None
+    steps, t = ctypes.c_int(0), ctypes.c_double(0.0)
+    ep = EvolveParams(float(alpha_b), float(eps_ion), float(tau_front), float(t_end if dt_max is None else dt_max),
+                      float(t_end), int(max_steps))
+    rc = lib.moray_evolve(ctx, cprobs, flags, ctypes.byref(ep), x64.data_ptr() if x64 is not None else None,
+                          results, ctypes.byref(steps), ctypes.byref(t),
+                          dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dts is not None else None)
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return (_unpack(results, outs, want_escaped_sg)[0], steps.value, t.value, x64,
+            dts[:steps.value].copy() if dts is not None else None)
 
 
 class Ticket:

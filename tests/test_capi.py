@@ -75,6 +75,7 @@ int main(void) {
   S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
   O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)
   S(moray_equilibrium_params) O(moray_equilibrium_params, tol) O(moray_equilibrium_params, max_iter)
+  S(moray_evolve_params) O(moray_evolve_params, tau_front) O(moray_evolve_params, t_end) O(moray_evolve_params, max_steps)
   return 0;
 }
 """
@@ -88,7 +89,8 @@ def test_binding_struct_layout_matches_header():
         got = dict(line.split() for line in subprocess.check_output([exe], text=True).splitlines())
     py = {"moray_init_params": M.InitParams, "moray_source": M.Source, "moray_spectrum": M.Spectrum,
           "moray_grid": M.Grid, "moray_trace_params": M.TraceParams, "moray_problem": M.Problem,
-          "moray_result": M.Result, "moray_equilibrium_params": M.EquilibriumParams}
+          "moray_result": M.Result, "moray_equilibrium_params": M.EquilibriumParams,
+          "moray_evolve_params": M.EvolveParams}
     for key, val in got.items():
         if "." in key:
             t, f = key.split(".")
@@ -101,6 +103,12 @@ def test_equilibrate_rejects_null_context():
     lib = M.load_library()
     ep = M.EquilibriumParams(M.ALPHA_B, 0.5, 1e-6, 10)
     assert lib.moray_equilibrate(None, None, 1, ctypes.byref(ep), None, None, None) == M.MORAY_EINVAL
+
+
+def test_evolve_rejects_null_context():
+    lib = M.load_library()
+    ep = M.EvolveParams(M.ALPHA_B, 0.1, 0.5, 1e13, 1e14, 10)
+    assert lib.moray_evolve(None, None, 1, ctypes.byref(ep), None, None, None, None, None) == M.MORAY_EINVAL
 
 
 def test_async_entry_points_reject_null_context():

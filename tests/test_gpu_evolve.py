@@ -1,0 +1,133 @@
+"""Time-stepped photo-ionisation (moray_evolve) on the GPU, against the
+oracle's evolution harness (oracle/evolve.py), which runs the same steps
+around the FP64 oracle trace, and against the Test 1 front radius of section
+4.1 (Eq. rstr), which pins both independently:
+
+* float64 mode: the same number of steps as the harness, every step's dt
+  within 1e-9 and the final neutral fraction within 1e-8 (its k_ph differs
+  from the oracle's by atomic summation order only);
+* mixed mode: its k_ph carries up to 1e-4 relative error, which moves the
+  steps by as much and the front cells' x a little more: dt within 1e-3,
+  x within 2e-3, the ionised volume within 1e-3 of the harness's;
+* the paper's Test 1 at its own resolution (64^3, 6.6 kpc, n_H = 1e-3,
+  5e48 ph/s at the corner): the ionised volume's equivalent radius within 3 %
+  of R_s (1 - e^{-t/t_rec})^{1/3} at 30 Myr and 4 % at 500 Myr, where the
+  partly ionised front cells (fewer recombinations than the sharp front of
+  the analytic model) hold it a little outside;
+* settings out of range, several grids or host fields are rejected and the
+  field is left as it was.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import evolve as EV
+from paper_1012_2865_amd import moray as M
+from paper_1012_2865_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+ALPHA = M.ALPHA_B
+T_REC = 1.0 / (ALPHA * 1e-3)
+MYR = 3.15576e13
+
+
+def _test1(n):
+    box = 6.6 * W.KPC_CM
+    g = W.uniform_grid(n, box / n, 1e-3, 1.0 - 1.2e-3)
+    return W.Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), W.hydrogen_spectrum([13.6]), W.Params())
+
+
+def _radius_ratio(x, n, t):
+    box = 6.6 * W.KPC_CM
+    v_ion = float(np.sum(1.0 - x)) * (box / n) ** 3
+    r = (6.0 * v_ion / math.pi) ** (1.0 / 3.0)                  # one octant of a sphere
+    rs = (3.0 * 5e48 / (4.0 * math.pi * ALPHA * 1e-6)) ** (1.0 / 3.0)
+    return r / (rs * (1.0 - math.exp(-t / T_REC)) ** (1.0 / 3.0))
+
+
+@pytest.fixture(scope="module")
+def harness():
+    p = _test1(32)
+    x, res, steps, t, dts = EV.evolve(p, 0.1 * T_REC, eps=0.1, dt_max=T_REC / 400)
+    return p, x, res, steps, t, np.array(dts)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_evolution_matches_the_oracle_harness(harness, precision):
+    p, x_ref, res_ref, steps_ref, t_ref, dts_ref = harness
+    pd = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        res, steps, t, x64, dts = M.moray_evolve(ctx, pd, 0.1 * T_REC, eps_ion=0.1, dt_max=T_REC / 400,
+                                                  want_x64=True, want_dts=True)
+    finally:
+        M.moray_free(ctx)
+    x = x64.cpu().numpy()
+    dx = float(np.max(np.abs(x - x_ref)))
+    m = min(len(dts), len(dts_ref))
+    ddt = float(np.max(np.abs(dts[:m] / dts_ref[:m] - 1.0)))
+    vol = float(np.sum(1.0 - x)) / float(np.sum(1.0 - x_ref)) - 1.0
+    print(f"[precision {precision}] steps {steps} (harness {steps_ref}), t {t / T_REC:.6f} t_rec, max dt rel "
+          f"{ddt:.2e}, max |x - x_ref| {dx:.2e}, ionised volume {vol:+.2e}", flush=True)
+    assert np.array_equal(pd.grids[0].x_hi.cpu().numpy(), x.astype(np.float32))
+    assert t == pytest.approx(t_ref, rel=1e-12)
+    if precision == M.MORAY_FP64:
+        assert steps == steps_ref
+        assert ddt <= 1e-9
+        assert dx <= 1e-8
+        k, k_ref = res["k_ph"][0].cpu().numpy(), res_ref["k_ph"][0]
+        mk = k_ref > 1e-6 * k_ref.max()
+        assert float(np.max(np.abs(k[mk] - k_ref[mk]) / k_ref[mk])) <= 1e-9
+    else:
+        assert abs(steps - steps_ref) <= 2
+        assert ddt <= 1e-3
+        assert dx <= 2e-3
+        assert abs(vol) <= 1e-3
+
+
+@pytest.mark.parametrize("t_myr,tol", [(30.0, 0.03), (500.0, 0.04)])
+def test_test1_at_the_papers_resolution(t_myr, tol):
+    n = 64
+    pd = M.problem_to_device(_test1(n))
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        res, steps, t, x64, _ = M.moray_evolve(ctx, pd, t_myr * MYR, eps_ion=0.1, dt_max=T_REC / 400,
+                                                want_x64=True)
+    finally:
+        M.moray_free(ctx)
+    ratio = _radius_ratio(x64.cpu().numpy(), n, t)
+    print(f"[Test 1, 64^3] {t_myr} Myr in {steps} steps: r_I / r_s = {ratio:.4f}", flush=True)
+    assert t == pytest.approx(t_myr * MYR, rel=1e-12)
+    assert abs(ratio - 1.0) < tol
+
+
+def test_evolution_rejects_bad_settings_and_leaves_the_field():
+    p = _test1(16)
+    pd = M.problem_to_device(p)
+    before = pd.grids[0].x_hi.clone()
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
+    try:
+        for kw in ({"alpha_b": 0.0}, {"eps_ion": 0.0}, {"tau_front": -1.0}, {"dt_max": 0.0},
+                   {"dt_max": float("inf")}, {"max_steps": 0}):
+            with pytest.raises(M.MorayError) as e:
+                M.moray_evolve(ctx, pd, T_REC, **kw)
+            assert e.value.status == M.MORAY_EINVAL, kw
+        for t_end in (0.0, -1.0, float("nan")):
+            with pytest.raises(M.MorayError) as e:
+                M.moray_evolve(ctx, pd, t_end, dt_max=1e13)
+            assert e.value.status == M.MORAY_EINVAL
+        two = W.lognormal_problem(99, 9, 24, 1)
+        two.grids.append(W.Grid(n_h=np.full((8, 8, 8), 1e-2, np.float32), x_hi=np.ones((8, 8, 8), np.float32),
+                                dx_cm=two.grids[0].dx_cm / 2, parent=0, offset=(4, 4, 4)))
+        with pytest.raises(M.MorayError) as e:
+            M.moray_evolve(ctx, M.problem_to_device(two), T_REC)
+        assert e.value.status == M.MORAY_EINVAL
+        with pytest.raises(M.MorayError) as e:
+            M.moray_evolve(ctx, p, T_REC)                        # host fields
+        assert e.value.status == M.MORAY_EINVAL
+    finally:
+        M.moray_free(ctx)
+    assert torch.equal(pd.grids[0].x_hi, before)
