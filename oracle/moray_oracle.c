@@ -50,6 +50,8 @@
 #endif
 
 #define EV_ERG 1.602176634e-12
+#define C_CMS 2.99792458e10          /* speed of light, cm/s (exact) */
+#define M_H_G 1.6735575e-24          /* mass of a hydrogen atom, g */
 #define PI_D 3.14159265358979323846
 #define MAX_LEVEL 29
 #define STACK_MAX 512
@@ -193,6 +195,7 @@ static int locate(const hier* H, const double s[3], const double n[3], double r,
 typedef struct {
   double* absorbed;
   double* energy;
+  double* mom;         /* NULL, or 3 planes of n_cells: momentum rate absorbed per cell (dyn) */
   uint64_t segments, splits, seeded, n_escaped, n_truncated;
 } acc;
 
@@ -292,6 +295,16 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
           const double fc = J->par->covering ? covering_factor(sl, n, c, R.r, dr, h, R.level) : 1.0;
           A->absorbed[H->cell_off[q] + cell] += dP * fc;
           A->energy[H->cell_off[q] + cell] += dP * fc * eexc;
+          if (A->mom) {
+            /* radiation pressure (section 2.5.4, Eq. radpres): the absorbed
+               photons' momentum dP E_ph / c along the ray; the covering
+               factor scales only k_ph and heating, not the absorption */
+            const double m = dP * (J->spec->energy_ev[gi] * EV_ERG) / C_CMS;
+            const size_t o = H->cell_off[q] + cell;
+            A->mom[o] += m * n[0];
+            A->mom[H->n_cells + o] += m * n[1];
+            A->mom[2 * H->n_cells + o] += m * n[2];
+          }
           R.P -= dP;
           A->segments++;
           R.r = t_exit;
@@ -384,6 +397,13 @@ static int validate(const orc_grid* g, int ng, const orc_source* src, int ns, co
 int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
               const orc_params* par, int n_threads, double* absorbed, double* energy, double* k_ph,
               double* heating, double* escaped_sg, orc_totals* tot) {
+  return orc_trace_accel(grids, n_grids, src, n_src, spec, par, n_threads, absorbed, energy, k_ph, heating,
+                         escaped_sg, NULL, tot);
+}
+
+int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
+                    const orc_params* par, int n_threads, double* absorbed, double* energy, double* k_ph,
+                    double* heating, double* escaped_sg, double* accel, orc_totals* tot) {
   if (validate(grids, n_grids, src, n_src, spec, par) != 0) return -1;
   if (!absorbed || !energy || !k_ph || !heating || !tot) return -1;
   hier H;
@@ -418,6 +438,7 @@ int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_s
   for (int t = 0; t < T; ++t) {
     A[t].absorbed = (double*)calloc(H.n_cells, sizeof(double));
     A[t].energy = (double*)calloc(H.n_cells, sizeof(double));
+    A[t].mom = accel ? (double*)calloc(3 * H.n_cells, sizeof(double)) : NULL;
   }
   csum* esc = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
   csum* trn = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
@@ -479,6 +500,25 @@ int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_s
         heating[o] = 0.0;
       }
     }
+  }
+  /* radiation-pressure acceleration a = dp / (rho V) with rho = m_H n_H
+     (section 2.5.4; dt_P cancels as P is a rate) */
+  if (accel) {
+    for (int q = 0; q < n_grids; ++q) {
+      const orc_grid* G = &grids[q];
+      const double vol = G->dx_cm * G->dx_cm * G->dx_cm;
+      const size_t nc = (size_t)G->nx * G->ny * G->nz;
+      for (size_t i = 0; i < nc; ++i) {
+        const size_t o = H.cell_off[q] + i;
+        const double rho = M_H_G * (double)G->n_h[i];
+        for (int k = 0; k < 3; ++k) {
+          double m = 0.0;
+          for (int t = 0; t < T; ++t) m += A[t].mom[k * H.n_cells + o];
+          accel[k * H.n_cells + o] = rho > 0.0 ? m / (rho * vol) : 0.0;
+        }
+      }
+    }
+    for (int t = 0; t < T; ++t) free(A[t].mom);
   }
   free(A);
   free(esc);

@@ -66,6 +66,17 @@ int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_s
               double* absorbed, double* energy, double* k_ph, double* heating,
               double* escaped_sg, orc_totals* tot);
 
+/* orc_trace, and when accel is not NULL also the radiation-pressure
+ * acceleration of the gas (section 2.5.4, Eq. radpres): every absorbed
+ * photon rate dP hands the momentum rate dP E_ph / c along its ray to its
+ * cell, and accel = (that sum) / (m_H n_H V), m_H = 1.6735575e-24 g, in
+ * cm/s^2 (0 where n_H = 0). accel holds 3 planes (x, y, z) of the
+ * concatenated cells: accel[k * total_cells + cell]. */
+int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, int n_src,
+                    const orc_spectrum* spec, const orc_params* par, int n_threads,
+                    double* absorbed, double* energy, double* k_ph, double* heating,
+                    double* escaped_sg, double* accel, orc_totals* tot);
+
 /* HEALPix nested-scheme pixel centre as a unit vector (z = polar axis,
  * phi = 0 along +x). */
 void orc_pix2vec_nest(int level, uint64_t pix, double v[3]);

@@ -72,6 +72,10 @@ def _load():
                                   ctypes.POINTER(_Spectrum), ctypes.POINTER(_Params), ctypes.c_int,
                                   dp, dp, dp, dp, dp, ctypes.POINTER(_Totals)]
         lib.orc_trace.restype = ctypes.c_int
+        lib.orc_trace_accel.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.POINTER(_Source), ctypes.c_int,
+                                        ctypes.POINTER(_Spectrum), ctypes.POINTER(_Params), ctypes.c_int,
+                                        dp, dp, dp, dp, dp, dp, ctypes.POINTER(_Totals)]
+        lib.orc_trace_accel.restype = ctypes.c_int
         lib.orc_pix2vec_nest.argtypes = [ctypes.c_int, ctypes.c_uint64, dp]
         lib.orc_pix2vec_nest.restype = None
         lib.orc_const_ev_erg.restype = ctypes.c_double
@@ -97,8 +101,10 @@ class OracleError(ValueError):
     pass
 
 
-def trace(problem, n_threads: int = 1) -> dict:
-    """Run the oracle on one problem; returns per-grid fields and totals."""
+def trace(problem, n_threads: int = 1, want_accel: bool = False) -> dict:
+    """Run the oracle on one problem; returns per-grid fields and totals, and
+    with want_accel the radiation-pressure acceleration per grid, shaped
+    (3, nz, ny, nx) in cm/s^2."""
     lib = _load()
     keep = []
     grids = (_Grid * len(problem.grids))()
@@ -134,11 +140,12 @@ def trace(problem, n_threads: int = 1) -> dict:
     k_ph = np.zeros(n_cells)
     heating = np.zeros(n_cells)
     esc = np.zeros(max(1, len(S) * len(e)))
+    accel = np.zeros(3 * n_cells) if want_accel else None
     tot = _Totals()
-    rc = lib.orc_trace(grids, len(problem.grids), srcs, len(S), ctypes.byref(spec), ctypes.byref(par),
-                       int(n_threads), absorbed.ctypes.data_as(dp), energy.ctypes.data_as(dp),
-                       k_ph.ctypes.data_as(dp), heating.ctypes.data_as(dp), esc.ctypes.data_as(dp),
-                       ctypes.byref(tot))
+    rc = lib.orc_trace_accel(grids, len(problem.grids), srcs, len(S), ctypes.byref(spec), ctypes.byref(par),
+                             int(n_threads), absorbed.ctypes.data_as(dp), energy.ctypes.data_as(dp),
+                             k_ph.ctypes.data_as(dp), heating.ctypes.data_as(dp), esc.ctypes.data_as(dp),
+                             accel.ctypes.data_as(dp) if accel is not None else None, ctypes.byref(tot))
     if rc != 0:
         raise OracleError("oracle rejected the problem")
 
@@ -151,5 +158,9 @@ def trace(problem, n_threads: int = 1) -> dict:
         return out
 
     totals = {name: getattr(tot, name) for name, _ in _Totals._fields_}
-    return {"absorbed": split(absorbed), "energy": split(energy), "k_ph": split(k_ph), "heating": split(heating),
-            "escaped_sg": esc[:len(S) * len(e)].reshape(len(S), len(e)), "totals": totals}
+    out = {"absorbed": split(absorbed), "energy": split(energy), "k_ph": split(k_ph), "heating": split(heating),
+           "escaped_sg": esc[:len(S) * len(e)].reshape(len(S), len(e)), "totals": totals}
+    if accel is not None:
+        planes = [split(accel[k * n_cells:(k + 1) * n_cells]) for k in range(3)]
+        out["accel"] = [np.stack([planes[k][q] for k in range(3)]) for q in range(len(problem.grids))]
+    return out
