@@ -13,7 +13,7 @@ it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
-  python bench.py --equilibrium-only | --evolve-only | --covering-only [--steps K]
+  python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only [--steps K]
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
@@ -335,6 +335,37 @@ def _evolve_test1(M):
             "ms_per_step": dt * 1e3 / steps, "front_over_analytic": r / rs, "dtype": "f32+f64acc"}
 
 
+def _radpres_c1(M, steps):
+    """The 128^3 workload with the radiation-pressure acceleration (section
+    2.5.4) asked for, mixed precision, beside the plain trace under the same
+    launch settings and result buffers."""
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    dev = [M.problem_to_device(W.config1())]
+    n = dev[0].grids[0].n_h.numel()
+    outs = [(torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"),
+             torch.empty(3 * n, dtype=torch.float64, device="cuda"))]
+    torch.cuda.synchronize()
+    ctx, _ = _tuned(M, M.MORAY_FP32_ACC64, dev)
+    try:
+        sp, _, _ = _time_steps(M, ctx, dev, steps, 2)
+        res = None
+        for i in range(2):
+            res = M.moray_trace(ctx, dev, outputs=outs)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(steps):
+            res = M.moray_trace(ctx, dev, outputs=outs)
+        torch.cuda.synchronize()
+        sr = (time.perf_counter() - t0) / steps
+    finally:
+        M.moray_free(ctx)
+    segs = res[0]["segments"]
+    return {"workload": "lognormal128_16src_4grp with radiation pressure", "ms_per_step": sr * 1e3,
+            "segments_per_s": segs / sr, "plain_ms_per_step": sp * 1e3, "overhead": sr / sp - 1.0,
+            "dtype": "f32+f64acc"}
+
+
 def _batched_c2(M, steps):
     """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
     form traces all of them in one call (one launch sequence) in mixed
@@ -452,6 +483,8 @@ def main():
                     help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
     ap.add_argument("--evolve-only", action="store_true",
                     help="print the time-stepped Test 1 measurement (64^3 to 500 Myr) as one JSON line and exit")
+    ap.add_argument("--radpres-only", action="store_true",
+                    help="print the radiation-pressure measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--counter-pass", action="store_true",
@@ -485,6 +518,9 @@ def main():
         return
     if args.covering_only:
         print(json.dumps(_covering_c1(M, args.steps)), flush=True)
+        return
+    if args.radpres_only:
+        print(json.dumps(_radpres_c1(M, args.steps)), flush=True)
         return
     if args.serve_only:
         for rate in (float(x) for x in args.serve_rates.split(",")):
@@ -565,6 +601,9 @@ def main():
         extras["covering"] = _covering_c1(M, max(2, args.steps // 2))
         print(f"# covering factor: {extras['covering']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['covering']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
+        extras["radpres"] = _radpres_c1(M, max(2, args.steps // 2))
+        print(f"# radiation pressure: {extras['radpres']['ms_per_step']:.2f} ms per step "
+              f"({100 * extras['radpres']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
         extras["evolve_test1"] = _evolve_test1(M)
         print(f"# Test 1 to 500 Myr: {extras['evolve_test1']['steps']} steps in "
               f"{extras['evolve_test1']['s_total']:.2f} s", file=sys.stderr, flush=True)

@@ -125,6 +125,16 @@ typedef struct {
   double* k_ph;               /* [total cells] caller-owned output, 1/s per absorber */
   double* heating;            /* [total cells] caller-owned output, erg/s per absorber */
   double* escaped_sg;         /* optional host [n_sources*n_groups] escaped photons/s, or NULL */
+  double* accel;              /* optional [3 * total cells] caller-owned output (host or device like
+                                 k_ph), or NULL: the radiation-pressure acceleration of the gas
+                                 (section 2.5.4, Eq. radpres), cm/s^2, component-major over the
+                                 problem's concatenated cells, accel[k * total_cells + cell] for
+                                 k = x, y, z. Every absorbed photon rate dP hands the momentum rate
+                                 dP E_ph / c along its ray to its cell (the covering factor does not
+                                 scale it); a = that sum / (m_H n_H V) with m_H = 1.6735575e-24 g,
+                                 0 where n_H = 0. Asking for it runs a variant of the trace kernel
+                                 with three more sums per segment. moray_trace only: the serving
+                                 engine rejects it. */
   /* filled by the library: */
   double emitted;             /* sum over sources and groups of the photon rate */
   double absorbed;            /* sum over cells of the absorbed photon rate */

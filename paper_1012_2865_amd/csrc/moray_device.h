@@ -18,6 +18,8 @@ constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries
 constexpr int kCacheEntries = 1 << kCacheLog2;
 constexpr uint32_t kNoSlot = 0xffffffffu;      // empty cache entry
+constexpr double kHydrogenMassG = 1.6735575e-24;   // mass of a hydrogen atom, g
+constexpr double kLightCms = 2.99792458e10;        // speed of light, cm/s
 constexpr int kEvictCap = 128;                 // per-wave buffer of evicted sums (drained at > 64)
 constexpr int kTallyLog2 = 7;                  // per-block LDS table of per-tree statistics: 128 entries
 constexpr int kTallySlots = 1 << kTallyLog2;
@@ -36,6 +38,8 @@ struct GridDev {
   const float* x_hi;
   double* out_kph;         // where finalize writes this grid's k_ph and heating
   double* out_heat;
+  double* out_acc;         // radiation-pressure acceleration: component k of local cell i at
+                           // out_acc[k * (problem's cells) + i]; NULL when not asked for
 };
 
 struct ProblemDev {
@@ -46,6 +50,8 @@ struct ProblemDev {
   long long acc_off;       // first accumulator slot: group g of cell c is acc_off + g*n_cells + (c - cell_off)
   int eexc_off;            // first of its n_groups (E - E_ion) values in erg
   int pad;
+  long long mom_off = -1;  // first momentum accumulator (component k of cell c at
+                           // mom_off + k*n_cells + (c - cell_off)), or -1 without radiation pressure
 };
 
 // One (source, group) ray tree, with the shape of its problem's root grid so
@@ -68,6 +74,9 @@ struct SgDev {
   double four_pi_phi_c;    // 4 pi phi_c of its problem
   int problem;
   int covering;            // scale deposits into the accumulators by the covering factor
+  uint32_t mom_slot0;      // radiation pressure: component k of cell c (batch numbering) sums at
+  uint32_t mom_stride;     //   acc[mom_slot0 + k * mom_stride + c]
+  double mom_scale;        // E_ph / c of the group (erg s/cm), 0 without radiation pressure
 };
 
 struct SgStats {

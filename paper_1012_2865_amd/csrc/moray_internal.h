@@ -20,7 +20,7 @@ template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
                        Counters*);
 template <typename R>
-hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover);
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);

@@ -362,6 +362,8 @@ struct Ray {
   double sx, sy, sz, P0;
   int root, rn0, rn1, rn2, rcell;
   bool cover;             // its deposits are scaled by the covering factor
+  uint32_t mom0, mstride; // radiation pressure: momentum sums of the tree's problem
+  double mscale;          // E_ph / c, 0 when the problem does not ask for them
 };
 
 template <typename R>
@@ -482,6 +484,9 @@ struct Tracer {
     L.rn0 = S.rnx; L.rn1 = S.rny; L.rn2 = S.rnz;
     L.rcell = (int)S.rcell_off;
     L.cover = S.covering != 0;
+    L.mom0 = S.mom_slot0;
+    L.mstride = S.mom_stride;
+    L.mscale = S.mom_scale;
     const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.sigma = S.sigma32;
@@ -888,10 +893,16 @@ struct SplitStage {
 // which the LDS of a block (four waves) also allows.
 template <typename R> struct TraceWaves { static constexpr int n = 3; };
 
-// COVER: some tree of the launch scales its deposits by the covering factor.
-template <typename R, bool CACHE, bool COVER>
+// PHYS selects the optional physics some tree of the launch asks for:
+// kPhysCover scales deposits by the covering factor (section 2.3), kPhysRadp
+// adds the absorbed momentum E_ph dP / c n to three more sums per cell
+// (radiation pressure, section 2.5.4). PHYS = 0 is the plain trace.
+constexpr int kPhysCover = 1, kPhysRadp = 2;
+
+template <typename R, bool CACHE, int PHYS>
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(TraceWaves<R>::n)))
 void trace_level_kernel(TraceArgs<R> a) {
+  constexpr bool COVER = (PHYS & kPhysCover) != 0, RADP = (PHYS & kPhysRadp) != 0;
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ int s_bad;
@@ -1050,9 +1061,9 @@ void trace_level_kernel(TraceArgs<R> a) {
       }
       stage.count += __popcll(smask);
     }
-    bool dep = false, moved = false;
-    uint32_t dkey = 0;
-    double dval = 0.0;
+    bool dep = false, moved = false, mdep = false;
+    uint32_t dkey = 0, mkey = 0;
+    double dval = 0.0, mval = 0.0;
     R knext = (R)0;
     int s_ax = 0, s_dir = 0;
     if (active) {
@@ -1060,6 +1071,12 @@ void trace_level_kernel(TraceArgs<R> a) {
       if (L.g.positive(dr, ax)) {
         const R tau = L.kap * L.sigma * dr;
         dval = absorb(L.P, tau);
+        if constexpr (RADP) {
+          // the absorbed radiation itself, before any covering-factor scaling
+          mdep = L.mscale != 0.0;
+          mval = dval * L.mscale;
+          mkey = L.mom0 + (uint32_t)L.lin;
+        }
         if constexpr (COVER) {
           if (L.cover) dval *= T.covering_factor(L, (double)dr);
         }
@@ -1094,6 +1111,13 @@ void trace_level_kernel(TraceArgs<R> a) {
       }
     }
     cache.add(a.acc, dkey, dval, dep, lane);
+    if constexpr (RADP) {
+      if (__ballot(mdep)) {
+#pragma unroll
+        for (int k = 0; k < 3; ++k)
+          cache.add(a.acc, mkey + (uint32_t)k * L.mstride, mdep ? mval * L.g.dir64(k) : 0.0, mdep, lane);
+      }
+    }
     if (moved) {
       if (knext < (R)0) {
         if (!T.settle(L, s_ax, s_dir)) {
@@ -1197,10 +1221,13 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
     kappa[c] = k;
     const long long base = P.acc_off + (c - P.cell_off);
     for (int gr = 0; gr < P.n_groups; ++gr) acc[base + gr * P.n_cells] = 0.0;
+    if (P.mom_off >= 0)
+      for (int k = 0; k < 3; ++k) acc[P.mom_off + k * P.n_cells + (c - P.cell_off)] = 0.0;
   }
 }
 
 // k_ph = sum_g absorbed_g / (n_H x_HI V); heating = sum_g absorbed_g (E_g - E_ion) / (n_H x_HI V);
+// with radiation pressure, accel = (absorbed momentum rate) / (m_H n_H V) per component;
 // per-block sums of the absorbed rate (no atomics).
 __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* grids, const ProblemDev* probs,
                                                                const FinalBlock* blocks, const double* acc,
@@ -1231,6 +1258,13 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
     }
     G.out_kph[local] = k;
     G.out_heat[local] = h;
+    if (P.mom_off >= 0 && G.out_acc) {
+      const double rho = kHydrogenMassG * (double)G.n_h[local];
+      for (int d = 0; d < 3; ++d) {
+        const double m = acc[P.mom_off + d * P.n_cells + (c - P.cell_off)];
+        G.out_acc[d * P.n_cells + local] = rho > 0.0 ? m / (rho * vol) : 0.0;
+      }
+    }
     sum += ab;
   }
   for (int off = kWave / 2; off > 0; off >>= 1) sum += __shfl_down(sum, off);
@@ -1281,16 +1315,19 @@ hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_gr
   return hipGetLastError();
 }
 
+template <typename R, int PHYS>
+static void launch_phys(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache) {
+  if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+  else hipLaunchKernelGGL((trace_level_kernel<R, false, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+}
+
 template <typename R>
-hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache, bool cover) {
-  const dim3 grid(blocks), block(kTraceBlock);
-  if (cover) {
-    if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, true>), grid, block, 0, s, args);
-    else hipLaunchKernelGGL((trace_level_kernel<R, false, true>), grid, block, 0, s, args);
-  } else {
-    if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, false>), grid, block, 0, s, args);
-    else hipLaunchKernelGGL((trace_level_kernel<R, false, false>), grid, block, 0, s, args);
-  }
+hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache, bool cover,
+                              bool radp) {
+  if (cover && radp) launch_phys<R, kPhysCover | kPhysRadp>(s, blocks, args, cache);
+  else if (cover) launch_phys<R, kPhysCover>(s, blocks, args, cache);
+  else if (radp) launch_phys<R, kPhysRadp>(s, blocks, args, cache);
+  else launch_phys<R, 0>(s, blocks, args, cache);
   return hipGetLastError();
 }
 
@@ -1307,15 +1344,15 @@ template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, in
                                        long long, float*, double*, Counters*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
                                         long long, double*, double*, Counters*);
-template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool);
-template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool);
+template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool);
+template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool);
 
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu) {
   if (precision == 0)
-    return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, true, false>, kTraceBlock, 0)
-                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, false, false>, kTraceBlock, 0);
-  return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, true, false>, kTraceBlock, 0)
-               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, false, false>, kTraceBlock, 0);
+    return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, true, 0>, kTraceBlock, 0)
+                 : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<double, false, 0>, kTraceBlock, 0);
+  return cache ? hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, true, 0>, kTraceBlock, 0)
+               : hipOccupancyMaxActiveBlocksPerMultiprocessor(blocks_per_cu, trace_level_kernel<float, false, 0>, kTraceBlock, 0);
 }
 
 }  // namespace moray

@@ -84,7 +84,7 @@ std::string plan_key(const moray_ctx* c, const moray_problem* probs, int n, unsi
     for (int g = 0; g < S.n_groups; ++g) {
       put(k, S.energy_ev[g]); put(k, S.sigma_cm2[g]); put(k, S.photon_frac[g]);
     }
-    put(k, outs[i].k_ph); put(k, outs[i].heating);
+    put(k, outs[i].k_ph); put(k, outs[i].heating); put(k, outs[i].accel);
   }
   return k;
 }
@@ -461,7 +461,18 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     min_l0 = std::min(min_l0, P.params.level_init);
   }
   if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
-  const bool cache_ok = n_acc < (long long)kNoSlot;   // cache keys are 32-bit accumulator indices
+  // radiation-pressure momentum sums (3 per cell) of the problems that ask for them, after the others
+  long long n_mom = 0;
+  for (int i = 0; i < n_probs; ++i)
+    if (outs[i].accel) {
+      pdev[i].mom_off = n_acc + n_mom;
+      n_mom += 3 * pdev[i].n_cells;
+    }
+  const bool radp = n_mom > 0;
+  const long long n_sums = n_acc + n_mom;
+  if (radp && n_sums >= (long long)kNoSlot)
+    return fail(c, MORAY_EINVAL, "radiation pressure needs fewer than 2^32 accumulators per batch");
+  const bool cache_ok = n_sums < (long long)kNoSlot;  // cache keys are 32-bit accumulator indices
   bool cover = false;                                   // some problem scales its deposits by the covering factor
   for (int i = 0; i < n_probs; ++i) cover = cover || probs[i].params.covering != 0;
 
@@ -507,6 +518,11 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
     d.problem = K.prob;
     d.covering = P.params.covering != 0;
+    if (pd.mom_off >= 0) {
+      d.mom_slot0 = (uint32_t)(pd.mom_off - pd.cell_off);
+      d.mom_stride = (uint32_t)pd.n_cells;
+      d.mom_scale = Sp.energy_ev[K.grp] * kEvErgConst / kLightCms;
+    }
     d.root_grid = pd.root_grid;
     d.rnx = grids[pd.root_grid].nx; d.rny = grids[pd.root_grid].ny; d.rnz = grids[pd.root_grid].nz;
     d.rcell_off = grids[pd.root_grid].cell_off;
@@ -521,8 +537,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   for (double b : sg_bound) need += b;
   size_t cap = c->queue_cap_user;
   const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
-  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_acc * 8 + (fdev ? 0 : (size_t)n_cells * 8) +
-                       (odev ? 0 : (size_t)n_cells * 16) + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
+  const size_t out_stage = odev ? 0 : (size_t)n_cells * (radp ? 40 : 16);
+  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
                        grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) + (64 << 20);
   if (!cap) {
     const size_t room = c->budget > c->allocated + fixed ? c->budget - fixed : 0;
@@ -540,13 +556,13 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       (st = ensure(c, c->stats, std::max<size_t>(1, n_sg) * sizeof(SgStats), "statistics")) ||
       (st = ensure(c, c->ctr, sizeof(Counters), "counters")) ||
       (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
-      (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_acc) * 8, "accumulators")) ||
+      (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_sums) * 8, "accumulators")) ||
       (st = ensure(c, c->eexc, eexc.size() * 8, "group energies")) ||
       (st = ensure(c, c->fblocks, fblocks.size() * sizeof(FinalBlock), "finalize blocks")) ||
       (st = ensure(c, c->partial, fblocks.size() * 8, "partial sums")))
     return st;
   if (!fdev && (st = ensure(c, c->fields, (size_t)n_cells * 8, "field upload"))) return st;
-  if (!odev && (st = ensure(c, c->outs, (size_t)n_cells * 16, "result staging"))) return st;
+  if (!odev && (st = ensure(c, c->outs, out_stage, "result staging"))) return st;
   for (int i = 0; i < 2; ++i) {
     if ((st = ensure(c, c->q_pix[i], cap * 8, "ray queue")) || (st = ensure(c, c->q_sg[i], cap * 4, "ray queue")) ||
         (st = ensure(c, c->q_r[i], cap * 8, "ray queue")) || (st = ensure(c, c->q_P[i], cap * 8, "ray queue")))
@@ -578,9 +594,12 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         if (odev) {
           d.out_kph = outs[i].k_ph + within;
           d.out_heat = outs[i].heating + within;
+          d.out_acc = outs[i].accel ? outs[i].accel + within : nullptr;
         } else {
           d.out_kph = obuf + d.cell_off;
           d.out_heat = obuf + n_cells + d.cell_off;
+          // the problem's three planes follow one another in the staging area
+          d.out_acc = outs[i].accel ? obuf + 2 * n_cells + 3 * pdev[i].cell_off + within : nullptr;
         }
         within += nc;
       }
@@ -699,7 +718,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok, cover);
+          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok, cover, radp);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -708,7 +727,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok, cover);
+          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok, cover, radp);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], strm);
@@ -777,7 +796,9 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       for (int i = 0; i < n_probs; ++i) {
         const long long off = pdev[i].cell_off, nc = pdev[i].n_cells;
         if (!hip_ok(c, hipMemcpy(outs[i].k_ph, obuf + off, nc * 8, hipMemcpyDeviceToHost), "copy results") ||
-            !hip_ok(c, hipMemcpy(outs[i].heating, obuf + n_cells + off, nc * 8, hipMemcpyDeviceToHost), "copy results"))
+            !hip_ok(c, hipMemcpy(outs[i].heating, obuf + n_cells + off, nc * 8, hipMemcpyDeviceToHost), "copy results") ||
+            (outs[i].accel && !hip_ok(c, hipMemcpy(outs[i].accel, obuf + 2 * n_cells + 3 * off, 3 * nc * 8,
+                                                   hipMemcpyDeviceToHost), "copy results")))
           return MORAY_EDEVICE;
       }
     }

@@ -692,7 +692,7 @@ bool trip(Engine* E) {
       A.gen = g; A.cin = cin; A.cout = cout; A.seed_level = seed_level;
       A.seed_sg_begin = seed_lo; A.seed_sg_end = seed_hi;
       A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = E->reserve;
-      e = launch_trace_level<float>(s, blocks, A, c->cache, cover);
+      e = launch_trace_level<float>(s, blocks, A, c->cache, cover, false);
     } else {
       TraceArgs<double> A{};
       A.grids = (GridDev*)E->grids.p; A.probs = (ProblemDev*)E->probs.p; A.sgs = (SgDev*)E->sgs.p;
@@ -701,7 +701,7 @@ bool trip(Engine* E) {
       A.gen = g; A.cin = cin; A.cout = cout; A.seed_level = seed_level;
       A.seed_sg_begin = seed_lo; A.seed_sg_end = seed_hi;
       A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = E->reserve;
-      e = launch_trace_level<double>(s, blocks, A, c->cache, cover);
+      e = launch_trace_level<double>(s, blocks, A, c->cache, cover, false);
     }
   }
   if (!eok(E, e, "trace") ||
@@ -844,6 +844,7 @@ moray_status moray_trace_async(moray_ctx* c, const moray_problem* probs, int n_p
     const moray_status s = validate(c, probs[i], i);
     if (s != MORAY_OK) return s;
     if (!outs[i].k_ph || !outs[i].heating) return fail(c, MORAY_EINVAL, "result buffers are NULL");
+    if (outs[i].accel) return fail(c, MORAY_EINVAL, "radiation pressure is computed by moray_trace only");
     if (probs[i].spectrum->n_groups > kServeMaxGroups) return fail(c, MORAY_EINVAL, "more than 64 groups");
   }
   if (!c->engine) {

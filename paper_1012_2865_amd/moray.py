@@ -66,7 +66,7 @@ class Problem(ctypes.Structure):
 
 class Result(ctypes.Structure):
     _fields_ = [("k_ph", ctypes.c_void_p), ("heating", ctypes.c_void_p), ("escaped_sg", ctypes.POINTER(ctypes.c_double)),
-                ("emitted", ctypes.c_double), ("absorbed", ctypes.c_double), ("escaped", ctypes.c_double),
+                ("accel", ctypes.c_void_p), ("emitted", ctypes.c_double), ("absorbed", ctypes.c_double), ("escaped", ctypes.c_double),
                 ("truncated", ctypes.c_double), ("segments", ctypes.c_ulonglong), ("rays_seeded", ctypes.c_ulonglong),
                 ("splits", ctypes.c_ulonglong), ("rays_escaped", ctypes.c_ulonglong),
                 ("rays_truncated", ctypes.c_ulonglong), ("peak_level_rays", ctypes.c_ulonglong),
@@ -186,10 +186,11 @@ def _ptr(a, dtype_np, keep: list):
     return arr.ctypes.data
 
 
-def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, outputs=None):
+def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, outputs=None, want_accel: bool = False):
     """C structs for a list of problems, plus everything they point into.
-    outputs: optional list of (k_ph, heating) flat float64 buffers per
-    problem (torch CUDA tensors when out_on_device, else numpy arrays)."""
+    outputs: optional list of (k_ph, heating) or (k_ph, heating, accel) flat
+    float64 buffers per problem (torch CUDA tensors when out_on_device, else
+    numpy arrays); want_accel asks for the radiation-pressure acceleration."""
     keep: list = []
     n = len(problems)
     cprobs = (Problem * n)()
@@ -235,8 +236,10 @@ def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, out
         cprobs[i] = Problem(grids, len(pb.grids), srcs, len(S), ctypes.pointer(cspec),
                             TraceParams(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
                                         1 if getattr(pr, "covering", False) else 0))
+        acc = None
         if outputs is not None:
-            kph, heat = outputs[i]
+            kph, heat = outputs[i][0], outputs[i][1]
+            acc = outputs[i][2] if len(outputs[i]) > 2 else None
             assert (kph.numel() if hasattr(kph, "numel") else kph.size) >= n_cells
             if out_on_device:
                 assert _is_torch_cuda(kph) and _is_torch_cuda(heat) and kph.is_contiguous() and heat.is_contiguous()
@@ -251,10 +254,19 @@ def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, out
         else:
             kph, heat = np.empty(n_cells), np.empty(n_cells)
             results[i].k_ph, results[i].heating = kph.ctypes.data, heat.ctypes.data
+        if want_accel and acc is None:
+            if out_on_device:
+                import torch
+                acc = torch.empty(3 * n_cells, dtype=torch.float64, device="cuda")
+            else:
+                acc = np.empty(3 * n_cells)
+        if acc is not None:
+            assert (acc.numel() if hasattr(acc, "numel") else acc.size) >= 3 * n_cells
+            results[i].accel = acc.data_ptr() if out_on_device else acc.ctypes.data
         esc = np.zeros(max(1, len(S) * len(e)))
         if want_escaped_sg:
             results[i].escaped_sg = esc.ctypes.data_as(dp)
-        outs.append((kph, heat, shapes, esc, len(S), len(e)))
+        outs.append((kph, heat, shapes, esc, len(S), len(e), acc, n_cells))
     flags = (MORAY_FIELDS_ON_DEVICE if on_dev else 0) | (MORAY_OUT_ON_DEVICE if out_on_device else 0)
     return cprobs, results, keep, outs, flags
 
@@ -262,16 +274,21 @@ def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, out
 def _unpack(results, outs, want_escaped_sg: bool) -> List[dict]:
     out = []
     for i in range(len(outs)):
-        kph, heat, shapes, esc, ns, ng = outs[i]
-        kl, hl, o = [], [], 0
+        kph, heat, shapes, esc, ns, ng, acc, n_cells = outs[i]
+        kl, hl, al, o = [], [], [], 0
         for shp in shapes:
             m = int(np.prod(shp))
             kl.append(kph[o:o + m].reshape(shp))
             hl.append(heat[o:o + m].reshape(shp))
+            if acc is not None:
+                al.append(acc[:3 * n_cells].reshape(3, n_cells)[:, o:o + m].reshape((3,) + tuple(shp)))
             o += m
         R = results[i]
-        d = {name: getattr(R, name) for name, _ in Result._fields_ if name not in ("k_ph", "heating", "escaped_sg")}
+        d = {name: getattr(R, name) for name, _ in Result._fields_
+             if name not in ("k_ph", "heating", "escaped_sg", "accel")}
         d["k_ph"], d["heating"] = kl, hl
+        if acc is not None:
+            d["accel"] = al
         if want_escaped_sg:
             d["escaped_sg"] = esc[:ns * ng].reshape(ns, ng)
         out.append(d)
@@ -279,7 +296,7 @@ def _unpack(results, outs, want_escaped_sg: bool) -> List[dict]:
 
 
 def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escaped_sg: bool = False,
-                outputs=None) -> List[dict]:
+                outputs=None, want_accel: bool = False) -> List[dict]:
     """Trace a batch of problems in one call.
 
     Each problem is duck-typed: ``grids`` (``n_h``, ``x_hi`` as torch CUDA
@@ -289,9 +306,11 @@ def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escape
     ``level_max``, ``p_min_frac``). Returns one dict per problem with ``k_ph``
     and ``heating`` (lists per grid) and the totals. ``outputs`` optionally
     names the result buffers (see _marshal); reusing them across calls lets
-    the library replay its captured launch sequence."""
+    the library replay its captured launch sequence. want_accel adds
+    ``accel``, the radiation-pressure acceleration per grid, shaped
+    (3, nz, ny, nx)."""
     lib = load_library()
-    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg, outputs)
+    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg, outputs, want_accel)
     rc = lib.moray_trace(ctx, cprobs, len(problems), flags, results)
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))

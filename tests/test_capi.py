@@ -72,7 +72,7 @@ int main(void) {
   S(moray_grid) O(moray_grid, offset) O(moray_grid, n_h) O(moray_grid, x_hi)
   S(moray_trace_params) O(moray_trace_params, p_min_frac) O(moray_trace_params, covering)
   S(moray_problem) O(moray_problem, params)
-  S(moray_result) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
+  S(moray_result) O(moray_result, accel) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
   O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)
   S(moray_equilibrium_params) O(moray_equilibrium_params, tol) O(moray_equilibrium_params, max_iter)
   S(moray_evolve_params) O(moray_evolve_params, tau_front) O(moray_evolve_params, t_end) O(moray_evolve_params, max_steps)
