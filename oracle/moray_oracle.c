@@ -207,7 +207,18 @@ typedef struct {
   double four_pi_phi_c;
 } job;
 
-typedef struct { int level; uint64_t pix; double r, P, P0; } oray;
+/* a ray: HEALPix level and pixel, radius, photon rate, its unattenuated
+   share P0, the radius where it halts in this step (infinite in a single
+   pass) and the steps since its emission */
+typedef struct { int level; uint64_t pix; double r, P, P0, rh; int age; } oray;
+
+/* rays halted in this step (time-dependent rays) */
+typedef struct {
+  orc_tray* ray;
+  size_t cap, n;
+  int overflow;
+  csum held;             /* their photon rate */
+} halted;
 
 /* Covering factor of a segment (section 2.3, Eqs. midpoint and fc), in
  * units of the local cell: the segment's midpoint lies D_c,i from the cell
@@ -233,22 +244,22 @@ static double covering_factor(const double sl[3], const double n[3], const long 
   return f * f >= 1.0 ? 1.0 : f * f;
 }
 
-/* Trace all seed rays of one (source, group) item, depth first. */
-static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* trunc) {
+/* Trace one ray of item (si, gi) and all its descendants, depth first.
+   A ray whose segment would end beyond its halting radius rh deposits up to
+   rh and is recorded in *hl (time-dependent rays, section 2.1 and section
+   3.1 step 3j) instead of going on. */
+static void march(const job* J, int si, int gi, oray first, acc* A, csum* esc, csum* trunc, halted* hl) {
   const hier* H = J->H;
   const orc_source* S = &J->src[si];
   const double s[3] = {S->x, S->y, S->z};
   const double sigma = J->spec->sigma_cm2[gi];
   const double eexc = (J->spec->energy_ev[gi] - J->spec->e_ion_ev) * EV_ERG;
-  const int l0 = J->par->level_init, lmax = J->par->level_max;
-  const uint64_t npix0 = (uint64_t)12 << (2 * l0);
-  const double P0 = J->spec->frac[gi] * S->ndot / (double)npix0;
+  const int lmax = J->par->level_max;
 
   oray stack[STACK_MAX];
-  for (uint64_t p0 = 0; p0 < npix0; ++p0) {
+  {
     int sp = 0;
-    stack[sp++] = (oray){l0, p0, 0.0, P0, P0};
-    A->seeded++;
+    stack[sp++] = first;
     while (sp > 0) {
       oray R = stack[--sp];
     new_ray:;
@@ -281,12 +292,15 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
           if (ldexp(12.0, 2 * R.level) < J->four_pi_phi_c * (u * u)) {
             A->splits++;
             for (int k = 3; k >= 1; --k)
-              stack[sp++] = (oray){R.level + 1, 4 * R.pix + (uint64_t)k, R.r, 0.25 * R.P, 0.25 * R.P0};
-            R = (oray){R.level + 1, 4 * R.pix, R.r, 0.25 * R.P, 0.25 * R.P0};
+              stack[sp++] = (oray){R.level + 1, 4 * R.pix + (uint64_t)k, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age};
+            R = (oray){R.level + 1, 4 * R.pix, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age};
             goto new_ray;
           }
         }
-        const double dr = t_exit - R.r;
+        /* a ray that reaches its halting radius inside this cell stops there */
+        const int halt = t_exit > R.rh;
+        const double t_end = halt ? R.rh : t_exit;
+        const double dr = t_end - R.r;
         if (dr > 0.0) {
           const size_t cell = (size_t)c[0] + (size_t)G->nx * ((size_t)c[1] + (size_t)G->ny * (size_t)c[2]);
           const double nabs = (double)G->n_h[cell] * (double)G->x_hi[cell];
@@ -307,7 +321,16 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
           }
           R.P -= dP;
           A->segments++;
-          R.r = t_exit;
+          R.r = t_end;
+        }
+        if (halt) {
+          if (hl->n < hl->cap)
+            hl->ray[hl->n] = (orc_tray){si, gi, R.level, R.age, R.pix, R.r, R.P, R.P0};
+          else
+            hl->overflow = 1;
+          hl->n++;
+          cs_add(&hl->held, R.P);
+          break;
         }
         const int dir = (n[ax] > 0.0) ? 1 : -1;
         c[ax] += dir;
@@ -348,6 +371,20 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
         }
       }
     }
+  }
+}
+
+
+/* Trace all seed rays of one (source, group) item (single pass). */
+static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* trunc) {
+  const orc_source* S = &J->src[si];
+  const int l0 = J->par->level_init;
+  const uint64_t npix0 = (uint64_t)12 << (2 * l0);
+  const double P0 = J->spec->frac[gi] * S->ndot / (double)npix0;
+  halted none = {NULL, 0, 0, 0, {0.0, 0.0}};
+  for (uint64_t p0 = 0; p0 < npix0; ++p0) {
+    A->seeded++;
+    march(J, si, gi, (oray){l0, p0, 0.0, P0, P0, INFINITY, 0}, A, esc, trunc, &none);
   }
 }
 
@@ -401,11 +438,24 @@ int orc_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_s
                          escaped_sg, NULL, tot);
 }
 
-int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
-                    const orc_params* par, int n_threads, double* absorbed, double* energy, double* k_ph,
-                    double* heating, double* escaped_sg, double* accel, orc_totals* tot) {
+/* One trace of a problem. Single pass: in == NULL, emit = 1, cdt infinite.
+   Time-dependent step (one thread): the rays in[0..n_in) continue one step
+   older, the sources emit new seed rays when emit is set, every ray halts at
+   (age + 1) * cdt root cells from its source, and the halted rays go to
+   out[0..out_cap) (their count to *n_out, their photon rate to *held). */
+static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, int n_src,
+                     const orc_spectrum* spec, const orc_params* par, int n_threads, double* absorbed,
+                     double* energy, double* k_ph, double* heating, double* escaped_sg, double* accel,
+                     orc_totals* tot, const orc_tray* in, size_t n_in, int emit, double cdt, orc_tray* out,
+                     size_t out_cap, size_t* n_out, double* held) {
   if (validate(grids, n_grids, src, n_src, spec, par) != 0) return -1;
   if (!absorbed || !energy || !k_ph || !heating || !tot) return -1;
+  const int td = in != NULL || out != NULL;
+  if (td && (!(cdt > 0.0) || (n_in > 0 && !in) || !n_out || !held)) return -1;
+  for (size_t i = 0; i < n_in; ++i)
+    if (in[i].src < 0 || in[i].src >= n_src || in[i].grp < 0 || in[i].grp >= spec->n_groups || in[i].level < 0 ||
+        in[i].level > par->level_max || in[i].age < 0)
+      return -1;
   hier H;
   H.g = grids;
   H.n_grids = n_grids;
@@ -432,7 +482,7 @@ int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, i
 
   job J = {&H, src, spec, par, 4.0 * PI_D * par->phi_c};
   const int n_items = n_src * spec->n_groups;
-  int T = n_threads < 1 ? 1 : n_threads;
+  int T = n_threads < 1 || td ? 1 : n_threads;
   if (T > n_items && n_items > 0) T = n_items;
   acc* A = (acc*)calloc((size_t)T, sizeof(acc));
   for (int t = 0; t < T; ++t) {
@@ -443,21 +493,47 @@ int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, i
   csum* esc = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
   csum* trn = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
 
+  halted hl = {out, out_cap, 0, 0, {0.0, 0.0}};
+  if (!td) {
 #ifdef _OPENMP
 #pragma omp parallel num_threads(T)
-  {
-    const int t = omp_get_thread_num();
+    {
+      const int t = omp_get_thread_num();
 #else
-  for (int t = 0; t < T; ++t) {
+    for (int t = 0; t < T; ++t) {
 #endif
-    for (int it = t; it < n_items; it += T)
-      trace_item(&J, it / spec->n_groups, it % spec->n_groups, &A[t], &esc[it], &trn[it]);
+      for (int it = t; it < n_items; it += T)
+        trace_item(&J, it / spec->n_groups, it % spec->n_groups, &A[t], &esc[it], &trn[it]);
+    }
+  } else {
+    /* the rays in flight first, in their order, then the new seeds */
+    for (size_t i = 0; i < n_in; ++i) {
+      const orc_tray* T0 = &in[i];
+      const int age = T0->age + 1;
+      march(&J, T0->src, T0->grp, (oray){T0->level, T0->pix, T0->r, T0->P, T0->P0, (double)(age + 1) * cdt, age},
+            &A[0], &esc[T0->src * spec->n_groups + T0->grp], &trn[T0->src * spec->n_groups + T0->grp], &hl);
+    }
+    if (emit) {
+      const int l0 = par->level_init;
+      const uint64_t npix0 = (uint64_t)12 << (2 * l0);
+      for (int it = 0; it < n_items; ++it) {
+        const int si = it / spec->n_groups, gi = it % spec->n_groups;
+        const double P0 = spec->frac[gi] * src[si].ndot / (double)npix0;
+        for (uint64_t p0 = 0; p0 < npix0; ++p0) {
+          A[0].seeded++;
+          march(&J, si, gi, (oray){l0, p0, 0.0, P0, P0, cdt, 0}, &A[0], &esc[it], &trn[it], &hl);
+        }
+      }
+    }
+    *n_out = hl.n;
+    *held = cs_get(&hl.held);
   }
 
   memset(tot, 0, sizeof(*tot));
   csum cem = {0, 0}, cab = {0, 0}, ces = {0, 0}, ctr = {0, 0};
-  for (int i = 0; i < n_src; ++i)
-    for (int k = 0; k < spec->n_groups; ++k) cs_add(&cem, spec->frac[k] * src[i].ndot);
+  if (emit)
+    for (int i = 0; i < n_src; ++i)
+      for (int k = 0; k < spec->n_groups; ++k) cs_add(&cem, spec->frac[k] * src[i].ndot);
   for (int it = 0; it < n_items; ++it) {
     cs_add(&ces, cs_get(&esc[it]));
     cs_add(&ctr, cs_get(&trn[it]));
@@ -525,5 +601,22 @@ int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, i
   free(trn);
   free(H.cover);
   free(H.cell_off);
-  return 0;
+  return hl.overflow ? -2 : 0;
+}
+
+int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
+                    const orc_params* par, int n_threads, double* absorbed, double* energy, double* k_ph,
+                    double* heating, double* escaped_sg, double* accel, orc_totals* tot) {
+  return run_trace(grids, n_grids, src, n_src, spec, par, n_threads, absorbed, energy, k_ph, heating, escaped_sg,
+                   accel, tot, NULL, 0, 1, INFINITY, NULL, 0, NULL, NULL);
+}
+
+int orc_trace_td(const orc_grid* grids, int n_grids, const orc_source* src, int n_src, const orc_spectrum* spec,
+                 const orc_params* par, double c_dt, int emit, const orc_tray* in, size_t n_in, orc_tray* out,
+                 size_t out_cap, size_t* n_out, double* held, double* absorbed, double* energy, double* k_ph,
+                 double* heating, orc_totals* tot) {
+  if (!out && out_cap > 0) return -1;
+  orc_tray dummy;
+  return run_trace(grids, n_grids, src, n_src, spec, par, 1, absorbed, energy, k_ph, heating, NULL, NULL, tot, in,
+                   n_in, emit, c_dt, out ? out : &dummy, out ? out_cap : 0, n_out, held);
 }

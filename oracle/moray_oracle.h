@@ -14,6 +14,7 @@
  */
 #ifndef MORAY_ORACLE_H
 #define MORAY_ORACLE_H
+#include <stddef.h>
 #include <stdint.h>
 #ifdef __cplusplus
 extern "C" {
@@ -76,6 +77,35 @@ int orc_trace_accel(const orc_grid* grids, int n_grids, const orc_source* src, i
                     const orc_spectrum* spec, const orc_params* par, int n_threads,
                     double* absorbed, double* energy, double* k_ph, double* heating,
                     double* escaped_sg, double* accel, orc_totals* tot);
+
+/* A ray in flight between the steps of a time-dependent trace. */
+typedef struct {
+  int src, grp;            /* its source and group */
+  int level;               /* HEALPix level */
+  int age;                 /* steps completed since its emission */
+  uint64_t pix;            /* nested pixel */
+  double r, P, P0;         /* radius (root cells), photon rate, unattenuated share */
+} orc_tray;
+
+/* One step of a trace with time-dependent rays (section 2.1: a ray is
+ * halted once it has travelled c dt_P and continues from there in the next
+ * step; section 3.1 step 3j). The rays in[0..n_in) continue, one step older;
+ * when emit is set the sources emit new seed rays (their totals count as
+ * this step's `emitted`). A ray that has completed a steps since its emission
+ * halts at the radius (a + 1) c_dt (root cells, c_dt = c dt_P / dx_root):
+ * its segment in that cell ends there and deposits accordingly, and the ray,
+ * with its remaining photons, goes to out (at most out_cap; *n_out receives
+ * the count, and when it exceeds out_cap the call returns -2). *held
+ * receives the photon rate of the halted rays. Splitting, truncation and
+ * escape are those of the single pass, so once every ray of a static problem
+ * has had time to leave, a step's k_ph equals the single pass's.
+ * One thread; outputs as in orc_trace. Returns 0, -1 on invalid input, -2
+ * when out is too small. */
+int orc_trace_td(const orc_grid* grids, int n_grids, const orc_source* src, int n_src,
+                 const orc_spectrum* spec, const orc_params* par, double c_dt, int emit,
+                 const orc_tray* in, size_t n_in, orc_tray* out, size_t out_cap, size_t* n_out,
+                 double* held, double* absorbed, double* energy, double* k_ph, double* heating,
+                 orc_totals* tot);
 
 /* HEALPix nested-scheme pixel centre as a unit vector (z = polar axis,
  * phi = 0 along +x). */

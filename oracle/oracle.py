@@ -76,6 +76,12 @@ def _load():
                                         ctypes.POINTER(_Spectrum), ctypes.POINTER(_Params), ctypes.c_int,
                                         dp, dp, dp, dp, dp, dp, ctypes.POINTER(_Totals)]
         lib.orc_trace_accel.restype = ctypes.c_int
+        sz = ctypes.c_size_t
+        lib.orc_trace_td.argtypes = [ctypes.POINTER(_Grid), ctypes.c_int, ctypes.POINTER(_Source), ctypes.c_int,
+                                     ctypes.POINTER(_Spectrum), ctypes.POINTER(_Params), ctypes.c_double, ctypes.c_int,
+                                     ctypes.c_void_p, sz, ctypes.c_void_p, sz, ctypes.POINTER(sz), dp,
+                                     dp, dp, dp, dp, ctypes.POINTER(_Totals)]
+        lib.orc_trace_td.restype = ctypes.c_int
         lib.orc_pix2vec_nest.argtypes = [ctypes.c_int, ctypes.c_uint64, dp]
         lib.orc_pix2vec_nest.restype = None
         lib.orc_const_ev_erg.restype = ctypes.c_double
@@ -99,6 +105,88 @@ def pix2vec_all(level: int) -> np.ndarray:
 
 class OracleError(ValueError):
     pass
+
+
+TRAY = np.dtype([("src", "<i4"), ("grp", "<i4"), ("level", "<i4"), ("age", "<i4"), ("pix", "<u8"),
+                 ("r", "<f8"), ("P", "<f8"), ("P0", "<f8")])
+
+
+def trace_td(problem, c_dt: float, rays_in=None, emit: bool = True, out_cap: int = 1 << 22):
+    """One step of the time-dependent trace (orc_trace_td): the rays in
+    flight (a TRAY array, or None) continue one step older, the sources emit
+    when `emit`, every ray halts at (age + 1) c_dt root cells. Returns the
+    result dict (fields of this step, totals, plus "held": the photon rate
+    of the halted rays) and the TRAY array of the halted rays."""
+    lib = _load()
+    args, keep, n_cells, shapes = _c_problem(problem)
+    grids, n_grids, srcs, n_src, spec, par = args
+    rin = np.ascontiguousarray(rays_in if rays_in is not None else np.zeros(0, TRAY), dtype=TRAY)
+    rout = np.zeros(out_cap, TRAY)
+    n_out = ctypes.c_size_t(0)
+    held = ctypes.c_double(0.0)
+    absorbed, energy, k_ph, heating = (np.zeros(n_cells) for _ in range(4))
+    dp = ctypes.POINTER(ctypes.c_double)
+    tot = _Totals()
+    rc = lib.orc_trace_td(grids, n_grids, srcs, n_src, ctypes.byref(spec), ctypes.byref(par), float(c_dt),
+                          1 if emit else 0, rin.ctypes.data if rin.size else None, rin.size, rout.ctypes.data,
+                          out_cap, ctypes.byref(n_out), ctypes.byref(held), absorbed.ctypes.data_as(dp),
+                          energy.ctypes.data_as(dp), k_ph.ctypes.data_as(dp), heating.ctypes.data_as(dp),
+                          ctypes.byref(tot))
+    if rc != 0:
+        raise OracleError("oracle rejected the step" if rc == -1 else "too many rays in flight")
+    split = _splitter(shapes)
+    totals = {name: getattr(tot, name) for name, _ in _Totals._fields_}
+    res = {"absorbed": split(absorbed), "energy": split(energy), "k_ph": split(k_ph), "heating": split(heating),
+           "totals": totals, "held": held.value}
+    return res, rout[:n_out.value].copy()
+
+
+def _splitter(shapes):
+    def split(a):
+        out, o = [], 0
+        for shp in shapes:
+            n = int(np.prod(shp))
+            out.append(a[o:o + n].reshape(shp))
+            o += n
+        return out
+    return split
+
+
+def _c_problem(problem):
+    """C structs of one problem and the arrays they point into."""
+    keep = []
+    grids = (_Grid * len(problem.grids))()
+    shapes = []
+    for q, g in enumerate(problem.grids):
+        n_h = np.ascontiguousarray(g.n_h, dtype=np.float32)
+        x_hi = np.ascontiguousarray(g.x_hi, dtype=np.float32)
+        keep += [n_h, x_hi]
+        nz, ny, nx = n_h.shape
+        shapes.append(n_h.shape)
+        grids[q].nx, grids[q].ny, grids[q].nz = nx, ny, nz
+        grids[q].dx_cm = float(g.dx_cm)
+        grids[q].n_h = n_h.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        grids[q].x_hi = x_hi.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+        grids[q].parent = int(g.parent)
+        for a in range(3):
+            grids[q].offset[a] = int(g.offset[a])
+    S = np.asarray(problem.sources, dtype=np.float64).reshape(-1, 4)
+    srcs = (_Source * max(1, len(S)))()
+    for i, row in enumerate(S):
+        srcs[i].x, srcs[i].y, srcs[i].z, srcs[i].ndot = (float(v) for v in row)
+    sp = problem.spectrum
+    e = np.ascontiguousarray(sp.energy_ev, dtype=np.float64)
+    sg = np.ascontiguousarray(sp.sigma_cm2, dtype=np.float64)
+    fr = np.ascontiguousarray(sp.frac, dtype=np.float64)
+    keep += [e, sg, fr, grids, srcs]
+    dp = ctypes.POINTER(ctypes.c_double)
+    spec = _Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
+    pr = problem.params
+    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
+                  1 if getattr(pr, "covering", False) else 0)
+    keep += [spec, par]
+    n_cells = sum(int(np.prod(shp)) for shp in shapes)
+    return (grids, len(problem.grids), srcs, len(S), spec, par), keep, n_cells, shapes
 
 
 def trace(problem, n_threads: int = 1, want_accel: bool = False) -> dict:
