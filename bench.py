@@ -13,7 +13,7 @@ it, and so are the 64-grid batched workload and a serving run.
 
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
-  python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only [--steps K]
+  python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only | --td-only
   python bench.py --counter-pass            (under rocprofv3 --pmc)
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
@@ -366,6 +366,37 @@ def _radpres_c1(M, steps):
             "dtype": "f32+f64acc"}
 
 
+def _td_c1(M, steps=10, c_dt=32.0):
+    """Time-dependent rays on the 128^3 workload (section 2.1): rays halt after
+    c dt_P = 32 root cells per step and continue in the next; `steps` steps
+    from an empty box, mixed precision, each timed on its own. The steps from
+    the fifth on have every emission batch in flight."""
+    import torch
+    from paper_1012_2865_amd import workloads as W
+    dev = M.problem_to_device(W.config1())
+    n = dev.grids[0].n_h.numel()
+    outs = [(torch.empty(n, dtype=torch.float64, device="cuda"), torch.empty(n, dtype=torch.float64, device="cuda"))]
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    td = None
+    try:
+        td = M.moray_td_create(ctx, dev, c_dt, 1 << 25)
+        ms, segs, held = [], [], 0.0
+        for _ in range(steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            res, held = M.moray_td_step(ctx, td, dev, outputs=outs)
+            ms.append((time.perf_counter() - t0) * 1e3)
+            segs.append(res["segments"])
+    finally:
+        if td:
+            M.moray_td_free(ctx, td)
+        M.moray_free(ctx)
+    late = slice(4, steps)
+    return {"workload": "lognormal128_16src_4grp, time-dependent rays, c dt_P = 32 cells", "steps": steps,
+            "ms_per_step": ms, "segments_per_step": segs, "held_after_last": held,
+            "segments_per_s_late": sum(segs[late]) / (sum(ms[late]) * 1e-3), "dtype": "f32+f64acc"}
+
+
 def _batched_c2(M, steps):
     """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
     form traces all of them in one call (one launch sequence) in mixed
@@ -483,6 +514,8 @@ def main():
                     help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
     ap.add_argument("--evolve-only", action="store_true",
                     help="print the time-stepped Test 1 measurement (64^3 to 500 Myr) as one JSON line and exit")
+    ap.add_argument("--td-only", action="store_true",
+                    help="print the time-dependent-ray measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--radpres-only", action="store_true",
                     help="print the radiation-pressure measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
@@ -518,6 +551,9 @@ def main():
         return
     if args.covering_only:
         print(json.dumps(_covering_c1(M, args.steps)), flush=True)
+        return
+    if args.td_only:
+        print(json.dumps(_td_c1(M)), flush=True)
         return
     if args.radpres_only:
         print(json.dumps(_radpres_c1(M, args.steps)), flush=True)
@@ -604,6 +640,9 @@ def main():
         extras["radpres"] = _radpres_c1(M, max(2, args.steps // 2))
         print(f"# radiation pressure: {extras['radpres']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['radpres']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
+        extras["td_rays"] = _td_c1(M)
+        print(f"# time-dependent rays: {extras['td_rays']['segments_per_s_late']:.3e} segments/s", file=sys.stderr,
+              flush=True)
         extras["evolve_test1"] = _evolve_test1(M)
         print(f"# Test 1 to 500 Myr: {extras['evolve_test1']['steps']} steps in "
               f"{extras['evolve_test1']['s_total']:.2f} s", file=sys.stderr, flush=True)

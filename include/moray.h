@@ -266,6 +266,41 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
                           const moray_evolve_params* params, double* x_out, moray_result* out, int* steps,
                           double* t_reached, double* dt_steps);
 
+/* Time-dependent rays (section 2.1: a ray halts once it has travelled c dt_P
+ * and continues from there in the next step, which keeps the time derivative
+ * of the transfer equation; section 3.1 step 3j). A moray_td holds, on the
+ * device, the rays in flight between steps of one single-grid problem.
+ *
+ * moray_td_create: state for problems shaped like prob (its grid size, source
+ * and group counts and level_init; its fields may change from step to step).
+ * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (>= 1024)
+ * bounds the rays in flight and each level's queue. The covering factor is
+ * not taken. Returns MORAY_EINVAL for bad arguments, MORAY_ENOMEM when the
+ * buffers do not fit the context's HBM budget.
+ *
+ * moray_td_step: one step. The rays in flight continue; when emit is nonzero
+ * the sources emit new seed rays with their current ndot (a source that emits
+ * in some steps only is a pulsed source). A ray that has completed a steps
+ * since its emission halts at the radius (a + 1) c_dt from its source: its
+ * segment in that cell ends there and deposits accordingly, and it keeps its
+ * remaining photons for the next step. Splits, truncation and escape are
+ * those of moray_trace, so when the fields and sources stay fixed, a step
+ * made after every ray has had time to leave deposits what moray_trace does.
+ * flags must be MORAY_FIELDS_ON_DEVICE | MORAY_OUT_ON_DEVICE; out receives
+ * this step's k_ph, heating and totals (emitted counts this step's emission;
+ * emitted + the previous step's held = absorbed + escaped + truncated + held)
+ * and *held (or NULL) the photon rate of the rays in flight after the step.
+ * accel must be NULL. MORAY_EQUEUE when the pool or a level queue overflows:
+ * the state is then unusable (free it). Not thread-safe per state.
+ *
+ * moray_td_free: release the state (before its context). */
+typedef struct moray_td moray_td;
+moray_status moray_td_create(moray_ctx* ctx, const moray_problem* prob, double c_dt, size_t pool_rays,
+                             moray_td** td);
+moray_status moray_td_step(moray_ctx* ctx, moray_td* td, const moray_problem* prob, unsigned flags, int emit,
+                           moray_result* out, double* held);
+void moray_td_free(moray_ctx* ctx, moray_td* td);
+
 /* Serving: queue n_probs problems (n_probs >= 1) for asynchronous tracing and
  * return at once with a ticket. Not part of the paper's method: this is the
  * request loop around it. A host thread of the context runs launch

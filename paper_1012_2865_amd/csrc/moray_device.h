@@ -77,6 +77,8 @@ struct SgDev {
   uint32_t mom_slot0;      // radiation pressure: component k of cell c (batch numbering) sums at
   uint32_t mom_stride;     //   acc[mom_slot0 + k * mom_stride + c]
   double mom_scale;        // E_ph / c of the group (erg s/cm), 0 without radiation pressure
+  double r_halt = __builtin_huge_val();   // time-dependent rays: radius (root cells) where the
+                                          // tree's rays halt in this step
 };
 
 struct SgStats {
@@ -98,6 +100,8 @@ struct Counters {
   double lost_P;
   unsigned int err;                             // bit flags, see kErr*
   unsigned int pad;
+  unsigned long long halt_count;                // time-dependent rays halted in this step
+  unsigned long long halt_levels[kLevels];      // of them, per HEALPix level
 };
 
 constexpr unsigned kErrOverflow = 1u;
@@ -133,6 +137,10 @@ struct TraceArgs {
   int refill;                          // idle lanes that trigger a refill
   unsigned max_steps;                  // hard cap on cells per ray (never reached)
   unsigned long long reserve;          // next-level slots a wave reserves at once (multiple of 4)
+  // time-dependent rays: where rays halted in this step go (halt_cap records; level in halt_lev)
+  RayQueue halt;
+  int* halt_lev;
+  unsigned long long halt_cap;
 };
 
 // One finalize block: cells [first, first + count) of one grid.

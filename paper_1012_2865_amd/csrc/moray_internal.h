@@ -21,6 +21,12 @@ hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const Problem
                        Counters*);
 template <typename R>
 hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp);
+template <typename R>
+hipError_t launch_trace_level_halt(hipStream_t, int, const TraceArgs<R>&, bool cache);
+hipError_t launch_prefill_level(hipStream_t, int num_cu, const RayQueue& pool, const int* pool_lev,
+                                unsigned long long n_pool, int level, const RayQueue& q, unsigned long long seg_cap,
+                                int nseg, Counters* ctr, int row);
+hipError_t launch_sum_blocks(hipStream_t, int blocks, const double* v, unsigned long long n, double* part);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);

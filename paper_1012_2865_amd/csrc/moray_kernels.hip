@@ -182,6 +182,7 @@ struct Geom64 {
     return ax;
   }
   __device__ double te(int ax) const { return sel3(ax, t0, t1, t2); }
+  __device__ double exit64(int ax) const { return te(ax); }
   __device__ double chord(int ax) const { return te(ax) - r; }
   __device__ bool positive(double dr, int) const { return dr > 0.0; }
   __device__ void advance(int ax) { r = te(ax); }
@@ -277,6 +278,7 @@ struct Geom32 {
   __device__ bool positive(float dr, int ax) const { return dr > sel3(ax, h0, h1, h2) * 9.094947e-13f; }
   __device__ void advance(int ax) { rh = sel3(ax, h0, h1, h2); rl = sel3(ax, l0, l1, l2); }
   __device__ float local_u(int ax) const { return sel3(ax, h0, h1, h2) * hloc; }
+  __device__ double exit64(int ax) const { return (double)sel3(ax, h0, h1, h2) + (double)sel3(ax, l0, l1, l2); }
   // The exit axis always has a nonzero direction component (an axis with
   // none is at infinity), so its next plane needs no special case; selects
   // instead of a branch per axis keep the wave converged.
@@ -364,6 +366,7 @@ struct Ray {
   bool cover;             // its deposits are scaled by the covering factor
   uint32_t mom0, mstride; // radiation pressure: momentum sums of the tree's problem
   double mscale;          // E_ph / c, 0 when the problem does not ask for them
+  double rhalt;           // time-dependent rays: radius where the tree's rays halt in this step
 };
 
 template <typename R>
@@ -487,6 +490,7 @@ struct Tracer {
     L.mom0 = S.mom_slot0;
     L.mstride = S.mom_stride;
     L.mscale = S.mom_scale;
+    L.rhalt = S.r_halt;
     const bool can_split = level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.sigma = S.sigma32;
@@ -634,7 +638,8 @@ struct TallyTable {
       sum[i] = sum[kTallySlots + i] = 0.0;
     }
   }
-  // kind: 0 escaped, 1 truncated, 2 split
+  // kind: 0 escaped, 1 truncated, 2 split, 3 halted (its segments only: the
+  // photons it holds are summed from the halt list)
   __device__ void add(SgStats* stats, uint32_t sg, unsigned segs, double P, int kind) {
     const uint32_t h0 = (sg * 0x9E3779B1u) >> (32 - kTallyLog2);
     int slot = -1;
@@ -656,7 +661,8 @@ struct TallyTable {
     const int c = kind == 2 ? 1 : kind + 2;
     if (slot >= 0) {
       __hip_atomic_fetch_add(&cnt[slot], (unsigned long long)segs, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-      __hip_atomic_fetch_add(&cnt[c * kTallySlots + slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (kind < 3)
+        __hip_atomic_fetch_add(&cnt[c * kTallySlots + slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       if (kind < 2)
         __hip_atomic_fetch_add(&sum[kind * kTallySlots + slot], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
@@ -664,6 +670,7 @@ struct TallyTable {
       if (segs) atomicAdd(&st.segs, (unsigned long long)segs);
       if (kind == 2) {
         atomicAdd(&st.splits, 1ull);
+      } else if (kind == 3) {
       } else if (kind == 0) {
         atomicAdd(&st.n_esc, 1ull);
         unsafeAtomicAdd(&st.esc_P, P);
@@ -896,13 +903,17 @@ template <typename R> struct TraceWaves { static constexpr int n = 3; };
 // PHYS selects the optional physics some tree of the launch asks for:
 // kPhysCover scales deposits by the covering factor (section 2.3), kPhysRadp
 // adds the absorbed momentum E_ph dP / c n to three more sums per cell
-// (radiation pressure, section 2.5.4). PHYS = 0 is the plain trace.
-constexpr int kPhysCover = 1, kPhysRadp = 2;
+// (radiation pressure, section 2.5.4), kPhysHalt halts every ray at its
+// tree's radius r_halt (time-dependent rays, section 2.1 and section 3.1
+// step 3j): the segment in that cell ends there and the ray, with the
+// photons it still carries, goes to the halt list for the next step. PHYS = 0
+// is the plain trace.
+constexpr int kPhysCover = 1, kPhysRadp = 2, kPhysHalt = 4;
 
 template <typename R, bool CACHE, int PHYS>
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(TraceWaves<R>::n)))
 void trace_level_kernel(TraceArgs<R> a) {
-  constexpr bool COVER = (PHYS & kPhysCover) != 0, RADP = (PHYS & kPhysRadp) != 0;
+  constexpr bool COVER = (PHYS & kPhysCover) != 0, RADP = (PHYS & kPhysRadp) != 0, HALT = (PHYS & kPhysHalt) != 0;
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ int s_bad;
@@ -1066,9 +1077,19 @@ void trace_level_kernel(TraceArgs<R> a) {
     double dval = 0.0, mval = 0.0;
     R knext = (R)0;
     int s_ax = 0, s_dir = 0;
+    bool halt = false;
     if (active) {
-      const R dr = L.g.chord(ax);
-      if (L.g.positive(dr, ax)) {
+      R dr = L.g.chord(ax);
+      bool pos = L.g.positive(dr, ax);
+      if constexpr (HALT) {
+        // the ray reaches its halting radius inside this cell: the segment ends there
+        if (L.g.exit64(ax) > L.rhalt) {
+          halt = true;
+          dr = (R)(L.rhalt - L.g.radius64());
+          pos = dr > (R)0;
+        }
+      }
+      if (pos) {
         const R tau = L.kap * L.sigma * dr;
         dval = absorb(L.P, tau);
         if constexpr (RADP) {
@@ -1083,8 +1104,11 @@ void trace_level_kernel(TraceArgs<R> a) {
         dkey = L.slot0 + (uint32_t)L.lin;
         dep = true;
         L.segs++;
-        L.g.advance(ax);
+        if (HALT && halt) L.g.set_radius(L.rhalt);
+        else L.g.advance(ax);
       }
+    }
+    if (active && !(HALT && halt)) {
       // step across the exit face
       const int dir = L.g.dirf(ax) > 0.0f ? 1 : -1;
       const int cnew = sel3(ax, L.c0, L.c1, L.c2) + dir;
@@ -1108,6 +1132,32 @@ void trace_level_kernel(TraceArgs<R> a) {
         s_ax = ax;
         s_dir = dir;
         moved = true;
+      }
+    }
+    if constexpr (HALT) {
+      // halted rays of the wave take consecutive records of the halt list
+      const unsigned long long hm = __ballot(halt);
+      if (hm) {
+        unsigned long long base = 0;
+        if (lane == 0) {
+          base = atomicAdd(&a.ctr->halt_count, (unsigned long long)__popcll(hm));
+          atomicAdd(&a.ctr->halt_levels[a.gen], (unsigned long long)__popcll(hm));
+        }
+        base = bcast64(base, 0);
+        if (halt) {
+          const unsigned long long i = base + __popcll(hm & below);
+          if (i < a.halt_cap) {
+            a.halt.pix[i] = L.pix;
+            a.halt.sg[i] = L.sg;
+            a.halt.r[i] = dep ? L.rhalt : L.g.radius64();
+            a.halt.P[i] = L.P;
+            a.halt_lev[i] = a.gen;
+          } else {
+            atomicOr(&a.ctr->err, kErrOverflow);
+          }
+          ended = 3;
+          active = false;
+        }
       }
     }
     cache.add(a.acc, dkey, dval, dep, lane);
@@ -1163,6 +1213,8 @@ __global__ void reset_kernel(Counters* ctr, SgStats* stats, int n_sg) {
   if (i == 0) {
     ctr->lost_rays = 0; ctr->lost_P = 0.0; ctr->err = 0;
   }
+  if (i < kLevels) ctr->halt_levels[i] = 0;
+  if (i == 0) ctr->halt_count = 0;
   if (i < n_sg) stats[i] = SgStats{0.0, 0.0, 0ull, 0ull, 0ull, 0ull};
 }
 
@@ -1331,6 +1383,82 @@ hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& arg
   return hipGetLastError();
 }
 
+template <typename R>
+hipError_t launch_trace_level_halt(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache) {
+  launch_phys<R, kPhysHalt>(s, blocks, args, cache);
+  return hipGetLastError();
+}
+
+// Time-dependent rays: the rays of HEALPix level `level` among the n_pool
+// rays halted in the previous step join level queue q (counter row `row`).
+// Each wave pass takes 64 records and puts its matching ones, with one
+// atomic, at the end of one of the queue's nseg segments (a power of two),
+// chosen by the pass; a segment that is full flags an overflow.
+__global__ __launch_bounds__(256) void prefill_level_kernel(RayQueue pool, const int* __restrict__ pool_lev,
+                                                            unsigned long long n_pool, int level, RayQueue q,
+                                                            unsigned long long seg_cap, int nseg, Counters* ctr,
+                                                            int row) {
+  const int lane = threadIdx.x & (kWave - 1);
+  const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  const unsigned long long waves = (unsigned long long)gridDim.x * (blockDim.x / kWave);
+  const unsigned long long wave = blockIdx.x * (unsigned long long)(blockDim.x / kWave) + threadIdx.x / kWave;
+  for (unsigned long long w = wave; w * kWave < n_pool; w += waves) {
+    const unsigned long long i = w * kWave + lane;
+    const bool mine = i < n_pool && pool_lev[i] == level;
+    const unsigned long long m = __ballot(mine);
+    if (!m) continue;
+    const int seg = (int)(w & (unsigned long long)(nseg - 1));
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&ctr->count[row][seg], (unsigned long long)__popcll(m));
+    base = bcast64(base, 0);
+    if (mine) {
+      const unsigned long long pos = base + __popcll(m & below);
+      if (pos < seg_cap) {
+        const unsigned long long o = (unsigned long long)seg * seg_cap + pos;
+        q.pix[o] = pool.pix[i];
+        q.sg[o] = pool.sg[i];
+        q.r[o] = pool.r[i];
+        q.P[o] = pool.P[i];
+      } else {
+        atomicOr(&ctr->err, kErrOverflow);
+      }
+    }
+  }
+}
+
+// Per-block sums of v[0..n) (the photons the halted rays hold).
+__global__ __launch_bounds__(256) void sum_blocks_kernel(const double* __restrict__ v, unsigned long long n,
+                                                         double* __restrict__ part) {
+  __shared__ double red[256 / kWave];
+  double s = 0.0;
+  for (unsigned long long i = blockIdx.x * 256ull + threadIdx.x; i < n; i += (unsigned long long)gridDim.x * 256ull)
+    s += v[i];
+  for (int off = kWave / 2; off > 0; off >>= 1) s += __shfl_down(s, off);
+  if ((threadIdx.x & (kWave - 1)) == 0) red[threadIdx.x / kWave] = s;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double t = 0.0;
+    for (int w = 0; w < 256 / kWave; ++w) t += red[w];
+    part[blockIdx.x] = t;
+  }
+}
+
+hipError_t launch_sum_blocks(hipStream_t s, int blocks, const double* v, unsigned long long n, double* part) {
+  hipLaunchKernelGGL(sum_blocks_kernel, dim3(blocks), dim3(256), 0, s, v, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_prefill_level(hipStream_t s, int num_cu, const RayQueue& pool, const int* pool_lev,
+                                unsigned long long n_pool, int level, const RayQueue& q, unsigned long long seg_cap,
+                                int nseg, Counters* ctr, int row) {
+  if (n_pool == 0) return hipSuccess;
+  unsigned long long blocks = (n_pool + 255) / 256;
+  if (blocks > 16ull * (unsigned long long)num_cu) blocks = 16ull * (unsigned long long)num_cu;
+  hipLaunchKernelGGL(prefill_level_kernel, dim3((unsigned)blocks), dim3(256), 0, s, pool, pool_lev, n_pool, level, q,
+                     seg_cap, nseg, ctr, row);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, const ProblemDev* probs,
                            const FinalBlock* blocks, const double* acc, const double* eexc, double* partial,
                            const Counters* ctr) {
@@ -1346,6 +1474,8 @@ template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, i
                                         long long, double*, double*, Counters*);
 template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool);
 template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool);
+template hipError_t launch_trace_level_halt<float>(hipStream_t, int, const TraceArgs<float>&, bool);
+template hipError_t launch_trace_level_halt<double>(hipStream_t, int, const TraceArgs<double>&, bool);
 
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu) {
   if (precision == 0)

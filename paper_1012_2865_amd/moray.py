@@ -94,7 +94,8 @@ class TuneResult(ctypes.Structure):
 
 
 ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_evolve",
-                 "moray_trace_async", "moray_query", "moray_free", "moray_last_error", "moray_version")
+                 "moray_td_create", "moray_td_step", "moray_td_free", "moray_trace_async", "moray_query",
+                 "moray_free", "moray_last_error", "moray_version")
 
 _lib = None
 
@@ -122,6 +123,14 @@ def load_library(path: str = LIB_PATH):
                                      ctypes.POINTER(ctypes.c_int), ctypes.POINTER(ctypes.c_double),
                                      ctypes.POINTER(ctypes.c_double)]
         lib.moray_evolve.restype = ctypes.c_int
+        lib.moray_td_create.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_double, ctypes.c_size_t,
+                                        ctypes.POINTER(ctypes.c_void_p)]
+        lib.moray_td_create.restype = ctypes.c_int
+        lib.moray_td_step.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_uint,
+                                      ctypes.c_int, ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_double)]
+        lib.moray_td_step.restype = ctypes.c_int
+        lib.moray_td_free.argtypes = [ctypes.c_void_p, ctypes.c_void_p]
+        lib.moray_td_free.restype = None
         lib.moray_trace_async.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                           ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_ulonglong)]
         lib.moray_trace_async.restype = ctypes.c_int
@@ -376,6 +385,35 @@ def moray_evolve(ctx, problem, t_end: float, eps_ion: float = 0.1, tau_front: fl
         raise MorayError(rc, moray_last_error(ctx))
     return (_unpack(results, outs, want_escaped_sg)[0], steps.value, t.value, x64,
             dts[:steps.value].copy() if dts is not None else None)
+
+
+def moray_td_create(ctx, problem, c_dt: float, pool_rays: int = 1 << 22):
+    """Device state of time-dependent rays for problems shaped like this one
+    (see moray.h); c_dt is c dt_P in root cells. Returns the handle."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal([problem], True, False)
+    h = ctypes.c_void_p()
+    rc = lib.moray_td_create(ctx, cprobs, float(c_dt), int(pool_rays), ctypes.byref(h))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return h.value
+
+
+def moray_td_step(ctx, td, problem, emit: bool = True, want_escaped_sg: bool = False, outputs=None):
+    """One step of time-dependent rays for a problem with torch CUDA fields.
+    Returns (result dict of the step, photon rate of the rays in flight)."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal([problem], True, want_escaped_sg, outputs)
+    held = ctypes.c_double(0.0)
+    rc = lib.moray_td_step(ctx, td, cprobs, flags, 1 if emit else 0, results, ctypes.byref(held))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return _unpack(results, outs, want_escaped_sg)[0], held.value
+
+
+def moray_td_free(ctx, td) -> None:
+    if td:
+        load_library().moray_td_free(ctx, td)
 
 
 class Ticket:

@@ -1,0 +1,134 @@
+"""Time-dependent rays (moray_td_*) on the GPU, step by step against the
+oracle's orc_trace_td on the same seeded inputs, through the C ABI:
+
+* every step's k_ph within 1e-9 (float64 path) or 1e-4 (mixed path) of the
+  oracle's wherever it exceeds 1e-6 of its maximum; the photon rate held in
+  flight, escaped and absorbed to the same bar; segment, split, escape and
+  truncation counts exact in float64; per-step photon bookkeeping
+  emitted + held before = absorbed + escaped + truncated + held after;
+* a pulse (emission in the first step only) against the oracle's pulse;
+* c dt_P beyond the box: one step equals moray_trace;
+* a pool too small fails the step with MORAY_EQUEUE and the state refuses
+  further steps; bad arguments are rejected.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1012_2865_amd import moray as M
+from paper_1012_2865_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def _np(a):
+    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+
+
+def _rel(got, want):
+    got, want = _np(got).ravel(), np.asarray(want).ravel()
+    if want.max() == 0.0:
+        return 0.0, float(np.abs(got).max())
+    m = want > 1e-6 * want.max()
+    return float(np.max(np.abs(got[m] - want[m]) / want[m])), float(np.max(np.abs(got - want)) / want.max())
+
+
+def _problem(item=1):
+    return W.lognormal_problem(92, item, 20, 2, mean=1e-4)
+
+
+def _compare_steps(precision, emits, cdt=4.0, item=1):
+    p = _problem(item)
+    dev = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=precision)
+    td = None
+    fp64 = precision == M.MORAY_FP64
+    tol = 1e-9 if fp64 else 1e-4
+    try:
+        td = M.moray_td_create(ctx, dev, cdt, 1 << 21)
+        rays, held_prev = None, 0.0
+        for step, emit in enumerate(emits):
+            ref, rays = O.trace_td(p, cdt, rays, emit=emit)
+            res, held = M.moray_td_step(ctx, td, dev, emit=emit)
+            T = ref["totals"]
+            rel, absr = _rel(res["k_ph"][0], ref["k_ph"][0])
+            print(f"[td prec {precision} step {step} emit {emit}] k_ph max rel {rel:.2e}, held {held:.4e} "
+                  f"(oracle {ref['held']:.4e}), in flight {len(rays)}, segments {res['segments']}/{T['segments']}",
+                  flush=True)
+            assert rel <= tol and absr <= max(tol, 1e-6), (step, rel, absr)
+            assert held == pytest.approx(ref["held"], rel=tol, abs=1e-12 * max(T["emitted"], held_prev, 1.0))
+            for k in ("escaped", "absorbed", "truncated"):
+                assert res[k] == pytest.approx(T[k], rel=max(tol, 1e-12), abs=1e-12 * max(T["emitted"], held_prev)), k
+            assert res["emitted"] == pytest.approx(T["emitted"], rel=1e-14)
+            bal = res["emitted"] + held_prev - res["absorbed"] - res["escaped"] - res["truncated"] - held
+            assert abs(bal) <= 1e-9 * max(res["emitted"], held_prev), (step, bal)
+            if fp64:
+                for k in ("segments", "splits", "rays_escaped", "rays_truncated", "rays_seeded"):
+                    assert res[k] == T[k], (step, k, res[k], T[k])
+            held_prev = held
+    finally:
+        if td:
+            M.moray_td_free(ctx, td)
+        M.moray_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_steps_match_the_oracle(precision):
+    _compare_steps(precision, [True] * 8)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_a_pulse_matches_the_oracle(precision):
+    _compare_steps(precision, [True, False, False, False], cdt=3.0, item=2)
+
+
+def test_infinite_speed_of_light_is_moray_trace():
+    p = _problem(3)
+    dev = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
+    try:
+        one = M.moray_trace(ctx, [dev])[0]
+        td = M.moray_td_create(ctx, dev, 1e6, 1 << 21)
+        try:
+            res, held = M.moray_td_step(ctx, td, dev)
+        finally:
+            M.moray_td_free(ctx, td)
+    finally:
+        M.moray_free(ctx)
+    assert held == 0.0
+    a, b = _np(res["k_ph"][0]), _np(one["k_ph"][0])
+    assert np.allclose(a, b, rtol=1e-12, atol=1e-14 * b.max())
+    for k in ("segments", "splits", "rays_escaped", "rays_truncated", "rays_seeded"):
+        assert res[k] == one[k], k
+
+
+def test_overflow_and_bad_arguments():
+    p = _problem(4)
+    dev = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        for c_dt, pool in ((0.0, 1 << 16), (float("inf"), 1 << 16), (4.0, 100)):
+            with pytest.raises(M.MorayError) as e:
+                M.moray_td_create(ctx, dev, c_dt, pool)
+            assert e.value.status == M.MORAY_EINVAL
+        td = M.moray_td_create(ctx, dev, 4.0, 1024)        # far too small for this problem's rays
+        try:
+            with pytest.raises(M.MorayError) as e:
+                for _ in range(4):
+                    M.moray_td_step(ctx, td, dev)
+            assert e.value.status == M.MORAY_EQUEUE
+            with pytest.raises(M.MorayError) as e:
+                M.moray_td_step(ctx, td, dev)
+            assert e.value.status == M.MORAY_EINVAL
+        finally:
+            M.moray_td_free(ctx, td)
+        td = M.moray_td_create(ctx, dev, 4.0, 1 << 16)
+        try:
+            other = M.problem_to_device(W.lognormal_problem(92, 5, 16, 2, mean=1e-4))
+            with pytest.raises(M.MorayError) as e:
+                M.moray_td_step(ctx, td, other)                  # another grid size
+            assert e.value.status == M.MORAY_EINVAL
+        finally:
+            M.moray_td_free(ctx, td)
+    finally:
+        M.moray_free(ctx)
