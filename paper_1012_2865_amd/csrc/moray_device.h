@@ -141,6 +141,8 @@ struct TraceArgs {
   RayQueue halt;
   int* halt_lev;
   unsigned long long halt_cap;
+  uint32_t tree_fold;                  // statistics of tree k are kept under k % tree_fold (the trees
+                                       // of one batch), so the block tables hold one batch's trees
 };
 
 // One finalize block: cells [first, first + count) of one grid.

@@ -27,6 +27,14 @@ hipError_t launch_prefill_level(hipStream_t, int num_cu, const RayQueue& pool, c
                                 unsigned long long n_pool, int level, const RayQueue& q, unsigned long long seg_cap,
                                 int nseg, Counters* ctr, int row);
 hipError_t launch_sum_blocks(hipStream_t, int blocks, const double* v, unsigned long long n, double* part);
+// moray_td_kernels.hip: the halt list sorted by (level, tree, pixel), and its per-level runs as queue input
+hipError_t td_sort_temp_bytes(unsigned long long cap, size_t* bytes);
+hipError_t launch_td_sort(hipStream_t, int num_cu, const RayQueue& pool, const int* lev, unsigned long long n,
+                          int tree_bits, int pix_bits, unsigned long long* keys_in, unsigned long long* keys_out,
+                          uint32_t* idx_in, uint32_t* idx_out, void* temp, size_t temp_bytes);
+hipError_t launch_prefill_sorted(hipStream_t, int num_cu, const RayQueue& pool, const uint32_t* order,
+                                 unsigned long long first, unsigned long long count, const RayQueue& q,
+                                 unsigned long long seg_cap, int nseg, Counters* ctr, int row);
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);

@@ -948,7 +948,7 @@ void trace_level_kernel(TraceArgs<R> a) {
 
   for (;;) {
     if (ended >= 0) {
-      tally.add(a.stats, L.sg, L.segs, L.P, ended);
+      tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
       ended = -1;
     }
     // ---- refill idle lanes from the wave's claim on the level queue ----
@@ -1184,7 +1184,7 @@ void trace_level_kernel(TraceArgs<R> a) {
   }
   if (stage.count) stage.write(a, home, lane);
   cache.flush(a.acc, lane);
-  if (ended >= 0) tally.add(a.stats, L.sg, L.segs, L.P, ended);
+  if (ended >= 0) tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
   // unused slots of the wave's last reserved block become empty slots
   for (unsigned long long i = stage.o_next + lane; i < stage.o_end; i += 64)
     if (i < a.seg_cap) a.out.sg[(unsigned long long)home * a.seg_cap + i] = kNoTree;

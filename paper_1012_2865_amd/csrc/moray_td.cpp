@@ -39,6 +39,8 @@ struct moray_td {
   DevBuf pix[2], sg[2], r[2], P[2], lev[2];
   DevBuf qpix[2], qsg[2], qr[2], qP[2];
   DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial;
+  DevBuf keys[2], order[2], sort_temp;  // the halt list sorted by (level, tree, pixel)
+  size_t sort_bytes = 0;
   std::vector<FinalBlock> fb;
   void* h_stage = nullptr;
 };
@@ -52,7 +54,10 @@ static void td_release(moray_ctx* c, moray_td* t) {
   DevBuf* all[] = {&t->grids, &t->probs, &t->sgs, &t->stats, &t->ctr, &t->kappa, &t->acc, &t->eexc, &t->fblocks,
                    &t->partial};
   for (DevBuf* b : all) release(c, *b);
+  release(c, t->sort_temp);
   for (int i = 0; i < 2; ++i) {
+    release(c, t->keys[i]);
+    release(c, t->order[i]);
     release(c, t->pix[i]); release(c, t->sg[i]); release(c, t->r[i]); release(c, t->P[i]); release(c, t->lev[i]);
     release(c, t->qpix[i]); release(c, t->qsg[i]); release(c, t->qr[i]); release(c, t->qP[i]);
   }
@@ -120,6 +125,15 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
        (st = ensure(c, t->fblocks, t->fb.size() * sizeof(FinalBlock), "finalize blocks")) ||
        (st = ensure(c, t->partial, t->fb.size() * 8, "partial sums"))))
     ;
+  if (st == MORAY_OK && pool_rays < ((size_t)1 << 32)) {
+    // sorting needs 32-bit record indices; larger pools are resumed unsorted
+    if (!hip_ok(c, td_sort_temp_bytes(pool_rays, &t->sort_bytes), "sort")) st = MORAY_EDEVICE;
+    for (int i = 0; i < 2 && st == MORAY_OK; ++i)
+      if ((st = ensure(c, t->keys[i], pool_rays * 8, "sort keys")) ||
+          (st = ensure(c, t->order[i], pool_rays * 4, "sort order")))
+        break;
+    if (st == MORAY_OK) st = ensure(c, t->sort_temp, std::max<size_t>(t->sort_bytes, 256), "sort scratch");
+  }
   if (st == MORAY_OK && hipHostMalloc(&t->h_stage, stage, hipHostMallocDefault) != hipSuccess) {
     t->h_stage = nullptr;
     st = fail(c, MORAY_ENOMEM, "pinned staging allocation failed");
@@ -179,6 +193,7 @@ static hipError_t launch_level(moray_ctx* c, moray_td* t, int l, int seed_lo, in
   A.halt = RayQueue{(uint64_t*)t->pix[b].p, (uint32_t*)t->sg[b].p, (double*)t->r[b].p, (double*)t->P[b].p};
   A.halt_lev = (int*)t->lev[b].p;
   A.halt_cap = t->cap;
+  A.tree_fold = (uint32_t)(t->n_src * t->n_grp);
   return launch_trace_level_halt<R>(c->stream, std::max(1, c->num_cu * c->blocks_per_cu), A, c->cache);
 }
 
@@ -291,15 +306,32 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
                                    (double*)t->kappa.p, (double*)t->acc.p, ctr);
   if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
   int launches = 0;
-  if (l_lo <= l_hi) {
-    if (t->lev_in[l_lo] &&
-        !hip_ok(c, launch_prefill_level(s, c->num_cu, pool_in, (const int*)t->lev[a].p, t->n_in, l_lo, queue(l_lo),
-                                        t->seg_cap, t->nseg, ctr, l_lo), "prefill"))
+  // the rays in flight sorted by (level, tree, pixel) when the key fits 64 bits
+  int tree_bits = 1;
+  while (tree_bits < 31 && ((long long)1 << tree_bits) < n_sg) ++tree_bits;
+  const int pix_bits = 2 * l_hi + 4;
+  const bool sorted = t->n_in > 0 && t->keys[0].p && 5 + tree_bits + pix_bits <= 64;
+  unsigned long long first[kLevels] = {};
+  if (sorted) {
+    unsigned long long o = 0;
+    for (int l = 0; l < kLevels; ++l) { first[l] = o; o += t->lev_in[l]; }
+    if (!hip_ok(c, launch_td_sort(s, c->num_cu, pool_in, (const int*)t->lev[a].p, t->n_in, tree_bits, pix_bits,
+                                  (unsigned long long*)t->keys[0].p, (unsigned long long*)t->keys[1].p,
+                                  (uint32_t*)t->order[0].p, (uint32_t*)t->order[1].p, t->sort_temp.p, t->sort_bytes),
+                "sort"))
       return MORAY_EDEVICE;
+  }
+  auto prefill = [&](int l) {
+    if (sorted)
+      return launch_prefill_sorted(s, c->num_cu, pool_in, (const uint32_t*)t->order[1].p, first[l], t->lev_in[l],
+                                   queue(l), t->seg_cap, t->nseg, ctr, l);
+    return launch_prefill_level(s, c->num_cu, pool_in, (const int*)t->lev[a].p, t->n_in, l, queue(l), t->seg_cap,
+                                t->nseg, ctr, l);
+  };
+  if (l_lo <= l_hi) {
+    if (t->lev_in[l_lo] && !hip_ok(c, prefill(l_lo), "prefill")) return MORAY_EDEVICE;
     for (int l = l_lo; l <= l_hi; ++l) {
-      if (l + 1 <= l_hi && l + 1 < kLevels && t->lev_in[l + 1] &&
-          !hip_ok(c, launch_prefill_level(s, c->num_cu, pool_in, (const int*)t->lev[a].p, t->n_in, l + 1,
-                                          queue(l + 1), t->seg_cap, t->nseg, ctr, l + 1), "prefill"))
+      if (l + 1 <= l_hi && l + 1 < kLevels && t->lev_in[l + 1] && !hip_ok(c, prefill(l + 1), "prefill"))
         return MORAY_EDEVICE;
       const bool seeds = emit && l == P.params.level_init;
       const int lo = seeds ? cur_slot * per : 0, hi = seeds ? (cur_slot + 1) * per : 0;
