@@ -111,6 +111,16 @@ def test_evolve_rejects_null_context():
     assert lib.moray_evolve(None, None, 1, ctypes.byref(ep), None, None, None, None, None) == M.MORAY_EINVAL
 
 
+def test_time_dependent_entry_points_reject_null_context():
+    lib = M.load_library()
+    h = ctypes.c_void_p()
+    assert lib.moray_td_create(None, None, 4.0, 1 << 16, ctypes.byref(h)) == M.MORAY_EINVAL
+    assert not h.value
+    held = ctypes.c_double(0.0)
+    assert lib.moray_td_step(None, None, None, 3, 1, None, ctypes.byref(held)) == M.MORAY_EINVAL
+    lib.moray_td_free(None, None)
+
+
 def test_async_entry_points_reject_null_context():
     lib = M.load_library()
     t = ctypes.c_ulonglong(0)
