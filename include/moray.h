@@ -273,8 +273,11 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
  *
  * moray_td_create: state for problems shaped like prob (its grid size, source
  * and group counts and level_init; its fields may change from step to step).
- * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (>= 1024)
- * bounds the rays in flight and each level's queue. The covering factor is
+ * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (1024 to
+ * 2^34) bounds the rays in flight and each level's queue; the state holds
+ * about 144 bytes of device memory per pool ray (two pools of 32 B, two
+ * level queues of 28 B and the 24 B of sort buffers that order the rays in
+ * flight, the latter only below 2^32 rays). The covering factor is
  * not taken. Returns MORAY_EINVAL for bad arguments, MORAY_ENOMEM when the
  * buffers do not fit the context's HBM budget.
  *

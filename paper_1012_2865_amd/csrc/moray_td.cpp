@@ -113,18 +113,18 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
         (st = ensure(c, t->qP[i], pool_rays * 8, "ray queue")))
       break;
   }
-  if (st == MORAY_OK &&
-      ((st = ensure(c, t->grids, sizeof(GridDev), "grid table")) ||
-       (st = ensure(c, t->probs, sizeof(ProblemDev), "problem table")) ||
-       (st = ensure(c, t->sgs, (size_t)n_sg * sizeof(SgDev), "source table")) ||
-       (st = ensure(c, t->stats, (size_t)n_sg * sizeof(SgStats), "statistics")) ||
-       (st = ensure(c, t->ctr, sizeof(Counters), "counters")) ||
-       (st = ensure(c, t->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
-       (st = ensure(c, t->acc, (size_t)n_cells * t->n_grp * 8, "accumulators")) ||
-       (st = ensure(c, t->eexc, (size_t)t->n_grp * 8, "group energies")) ||
-       (st = ensure(c, t->fblocks, t->fb.size() * sizeof(FinalBlock), "finalize blocks")) ||
-       (st = ensure(c, t->partial, t->fb.size() * 8, "partial sums"))))
-    ;
+  if (st == MORAY_OK) {
+    (void)((st = ensure(c, t->grids, sizeof(GridDev), "grid table")) ||
+           (st = ensure(c, t->probs, sizeof(ProblemDev), "problem table")) ||
+           (st = ensure(c, t->sgs, (size_t)n_sg * sizeof(SgDev), "source table")) ||
+           (st = ensure(c, t->stats, (size_t)n_sg * sizeof(SgStats), "statistics")) ||
+           (st = ensure(c, t->ctr, sizeof(Counters), "counters")) ||
+           (st = ensure(c, t->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
+           (st = ensure(c, t->acc, (size_t)n_cells * t->n_grp * 8, "accumulators")) ||
+           (st = ensure(c, t->eexc, (size_t)t->n_grp * 8, "group energies")) ||
+           (st = ensure(c, t->fblocks, t->fb.size() * sizeof(FinalBlock), "finalize blocks")) ||
+           (st = ensure(c, t->partial, t->fb.size() * 8, "partial sums")));
+  }
   if (st == MORAY_OK && pool_rays < ((size_t)1 << 32)) {
     // sorting needs 32-bit record indices; larger pools are resumed unsorted
     if (!hip_ok(c, td_sort_temp_bytes(pool_rays, &t->sort_bytes), "sort")) st = MORAY_EDEVICE;
