@@ -571,7 +571,7 @@ def main():
     # the library's default launch settings are the ones the autotuner picks
     # for this workload; the batched form below runs the autotuner itself
     ctx32 = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
-    tune = {"chunk_rays": 256, "refill_lanes": 16, "reserve_rays": 0, "waves_per_cu": 0, "source": "library defaults"}
+    tune = {"chunk_rays": 256, "refill_lanes": 64, "reserve_rays": 0, "waves_per_cu": 0, "source": "library defaults"}
     try:
         s32, seg32, res32 = _time_steps(M, ctx32, dev, args.steps, max(2, args.warmup))
     finally:

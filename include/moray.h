@@ -69,7 +69,8 @@ typedef struct {
   size_t hbm_budget_bytes;    /* cap on the context's device memory; 0 = half of the free memory */
   size_t queue_capacity;      /* rays per level buffer; 0 = sized from each problem's worst case */
   int waves_per_cu;           /* persistent trace waves per compute unit; 0 = default */
-  int refill_lanes;           /* a wave refetches rays once this many of its 64 lanes are idle; 0 = default (16) */
+  int refill_lanes;           /* a wave refetches rays once this many of its 64 lanes are idle; 0 = default (64:
+                                 once the whole wave is idle, so new rays start together) */
   int chunk_rays;             /* rays a wave claims from the level queue per atomic; 0 = default (256) */
   void* hip_stream;           /* hipStream_t for every launch; NULL = the null stream */
   int profile;                /* nonzero: time every trace-kernel launch with HIP events */

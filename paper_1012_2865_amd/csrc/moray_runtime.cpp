@@ -323,7 +323,7 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   c->stream = (hipStream_t)p->hip_stream;
   c->queue_cap_user = p->queue_capacity;
   c->profile = p->profile;
-  c->refill = p->refill_lanes ? p->refill_lanes : 16;
+  c->refill = p->refill_lanes ? p->refill_lanes : 64;
   c->chunk = p->chunk_rays ? p->chunk_rays : 256;
   c->reserve_user = p->reserve_rays;
   if ((he = hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, p->device)) != hipSuccess ||
@@ -979,7 +979,7 @@ moray_status moray_autotune(moray_ctx* c, const moray_problem* probs, int n_prob
   std::vector<int> bpcs;
   for (int b = 1; b <= bpc_max; ++b) bpcs.push_back(b);
   std::vector<Knob> knobs = {{&c->chunk, {128, 256, 512}},
-                             {&c->refill, {8, 12, 16, 24}},
+                             {&c->refill, {8, 16, 24, 64}},
                              {&c->reserve_user, {64, 128, 256}},
                              {&c->blocks_per_cu, bpcs}};
   for (Knob& k : knobs) {
