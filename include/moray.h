@@ -163,7 +163,10 @@ moray_status moray_init(moray_ctx** ctx, const moray_init_params* params);
  * of them through the same launch sequence. Inputs are read-only and must stay
  * valid until the call returns; outputs are written only on success (on
  * MORAY_EINVAL they are untouched, on device-side errors their content is
- * undefined). Blocks until the results are complete.
+ * undefined). Blocks until the results are complete. A batch holds fewer than
+ * 2^31 - 1 cells and fewer than 2^32 - 1 accumulators (cells x groups summed
+ * over its problems, plus 3 per cell of the problems that ask for the
+ * radiation-pressure acceleration); larger batches return MORAY_EINVAL.
  * With both MORAY_FIELDS_ON_DEVICE and MORAY_OUT_ON_DEVICE (and profiling
  * off), a call whose descriptors, field and result pointers and settings
  * equal the previous call's captures its launch sequence in a HIP graph, and

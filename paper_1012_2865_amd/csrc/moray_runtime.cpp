@@ -470,9 +470,10 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     }
   const bool radp = n_mom > 0;
   const long long n_sums = n_acc + n_mom;
-  if (radp && n_sums >= (long long)kNoSlot)
-    return fail(c, MORAY_EINVAL, "radiation pressure needs fewer than 2^32 accumulators per batch");
-  const bool cache_ok = n_sums < (long long)kNoSlot;  // cache keys are 32-bit accumulator indices
+  // the trace kernel addresses accumulators with 32-bit indices
+  if (n_sums >= (long long)kNoSlot)
+    return fail(c, MORAY_EINVAL, "a batch needs fewer than 2^32 - 1 accumulators (cells x groups, + 3 per cell "
+                                 "with radiation pressure)");
   bool cover = false;                                   // some problem scales its deposits by the covering factor
   for (int i = 0; i < n_probs; ++i) cover = cover || probs[i].params.covering != 0;
 
@@ -718,7 +719,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(strm, blocks, A, c->cache && cache_ok, cover, radp);
+          e = launch_trace_level<float>(strm, blocks, A, c->cache, cover, radp);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -727,7 +728,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(strm, blocks, A, c->cache && cache_ok, cover, radp);
+          e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp);
         }
         if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], strm);

@@ -82,6 +82,8 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
   const double need_slots = std::ceil(diag / c_dt) + 2.0;
   const long long per = (long long)prob->n_sources * prob->spectrum->n_groups;
   if (need_slots * (double)per >= 2.0e9) return fail(c, MORAY_EINVAL, "c_dt too small for this many trees");
+  if ((double)G.nx * G.ny * G.nz * prob->spectrum->n_groups >= (double)kNoSlot)
+    return fail(c, MORAY_EINVAL, "the grid needs fewer than 2^32 - 1 accumulators (cells x groups)");
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
 
   moray_td* t = new moray_td();
