@@ -129,3 +129,16 @@ def test_edge_case_matches_oracle(ctxs, case, precision):
         return
     fp64 = precision == M.MORAY_FP64
     _check(res, ref, 1e-9 if fp64 else 1e-4, name=f"{'fp64' if fp64 else 'fp32'} {case}", fp64=fp64)
+
+
+def test_batches_beyond_32_bit_accumulators_are_rejected(ctxs):
+    # 256^3 cells x 256 groups = 2^32 accumulators: one more than 32-bit indices address
+    n = 256
+    g = W.Grid(np.full((n, n, n), 1e-3, np.float32), np.ones((n, n, n), np.float32), DX)
+    energies = np.linspace(13.6, 60.0, 256)
+    p = W.Problem([g], np.array([[10.5, 20.5, 30.5, 1e48]]), W.hydrogen_spectrum(energies), W.Params())
+    for ctx in ctxs.values():
+        with pytest.raises(M.MorayError) as e:
+            M.moray_trace(ctx, [p], out_on_device=False)
+        assert e.value.status == M.MORAY_EINVAL
+        assert "2^32" in str(e.value)
