@@ -278,7 +278,7 @@ def _equilibrium_c1(M, updates=20):
             "ionised_fraction_final": float(1.0 - x.double().mean()), "dtype": "f32+f64acc"}
 
 
-def _covering_c1(M, steps):
+def _covering_c1(M, steps, oracle_threads=0):
     """The 128^3 workload with the covering-factor correction of k_ph and
     heating switched on (section 2.3), mixed precision, beside the plain
     trace under the same launch settings."""
@@ -295,9 +295,18 @@ def _covering_c1(M, steps):
         sc, segc, res = _time_steps(M, ctx, dc, steps, 2)
     finally:
         M.moray_free(ctx)
-    return {"workload": "lognormal128_16src_4grp with covering factor", "ms_per_step": sc * 1e3,
-            "segments_per_s": segc / sc, "plain_ms_per_step": sp * 1e3, "overhead": sc / sp - 1.0,
-            "absorbed_over_plain_emitted": res[0]["absorbed"] / res[0]["emitted"], "dtype": "f32+f64acc"}
+    out = {"workload": "lognormal128_16src_4grp with covering factor", "ms_per_step": sc * 1e3,
+           "segments_per_s": segc / sc, "plain_ms_per_step": sp * 1e3, "overhead": sc / sp - 1.0,
+           "absorbed_over_plain_emitted": res[0]["absorbed"] / res[0]["emitted"], "dtype": "f32+f64acc"}
+    if oracle_threads:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        segs = O.trace(cov, n_threads=oracle_threads)["totals"]["segments"]
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": segs / dt, "unit": "segments/s", "cores": oracle_threads, "kind": "oracle",
+                             "sample": f"full workload with the correction: {segs} segments in {dt:.1f} s",
+                             "gpu_speedup": (segc / sc) / (segs / dt)}
+    return out
 
 
 def _evolve_test1(M):
@@ -335,7 +344,7 @@ def _evolve_test1(M):
             "ms_per_step": dt * 1e3 / steps, "front_over_analytic": r / rs, "dtype": "f32+f64acc"}
 
 
-def _radpres_c1(M, steps):
+def _radpres_c1(M, steps, oracle_threads=0):
     """The 128^3 workload with the radiation-pressure acceleration (section
     2.5.4) asked for, mixed precision, beside the plain trace under the same
     launch settings and result buffers."""
@@ -361,12 +370,21 @@ def _radpres_c1(M, steps):
     finally:
         M.moray_free(ctx)
     segs = res[0]["segments"]
-    return {"workload": "lognormal128_16src_4grp with radiation pressure", "ms_per_step": sr * 1e3,
-            "segments_per_s": segs / sr, "plain_ms_per_step": sp * 1e3, "overhead": sr / sp - 1.0,
-            "dtype": "f32+f64acc"}
+    out = {"workload": "lognormal128_16src_4grp with radiation pressure", "ms_per_step": sr * 1e3,
+           "segments_per_s": segs / sr, "plain_ms_per_step": sp * 1e3, "overhead": sr / sp - 1.0,
+           "dtype": "f32+f64acc"}
+    if oracle_threads:
+        from oracle import oracle as O
+        t0 = time.perf_counter()
+        osegs = O.trace(W.config1(), n_threads=oracle_threads, want_accel=True)["totals"]["segments"]
+        dt = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": osegs / dt, "unit": "segments/s", "cores": oracle_threads, "kind": "oracle",
+                             "sample": f"full workload with the acceleration: {osegs} segments in {dt:.1f} s",
+                             "gpu_speedup": (segs / sr) / (osegs / dt)}
+    return out
 
 
-def _td_c1(M, steps=10, c_dt=32.0):
+def _td_c1(M, steps=10, c_dt=32.0, oracle=False):
     """Time-dependent rays on the 128^3 workload (section 2.1): rays halt after
     c dt_P = 32 root cells per step and continue in the next; `steps` steps
     from an empty box, mixed precision, each timed on its own. The steps from
@@ -392,9 +410,39 @@ def _td_c1(M, steps=10, c_dt=32.0):
             M.moray_td_free(ctx, td)
         M.moray_free(ctx)
     late = slice(4, steps)
-    return {"workload": "lognormal128_16src_4grp, time-dependent rays, c dt_P = 32 cells", "steps": steps,
-            "ms_per_step": ms, "segments_per_step": segs, "held_after_last": held,
-            "segments_per_s_late": sum(segs[late]) / (sum(ms[late]) * 1e-3), "dtype": "f32+f64acc"}
+    out = {"workload": "lognormal128_16src_4grp, time-dependent rays, c dt_P = 32 cells", "steps": steps,
+           "ms_per_step": ms, "segments_per_step": segs, "held_after_last": held,
+           "segments_per_s_late": sum(segs[late]) / (sum(ms[late]) * 1e-3), "dtype": "f32+f64acc"}
+    if oracle:
+        # the oracle's time-dependent step runs on one thread: three steps of two of the sources,
+        # beside the GPU on the same sample
+        from oracle import oracle as O
+        sub = W.subset_sources(W.config1(), [3, 11])
+        t0 = time.perf_counter()
+        rays, osegs = None, 0
+        for _ in range(3):
+            ref, rays = O.trace_td(sub, c_dt, rays, out_cap=1 << 24)
+            osegs += ref["totals"]["segments"]
+        dt = time.perf_counter() - t0
+        dsub = M.problem_to_device(sub)
+        ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+        td = None
+        try:
+            td = M.moray_td_create(ctx, dsub, c_dt, 1 << 24)
+            torch.cuda.synchronize()
+            g0, gsegs = time.perf_counter(), 0
+            for _ in range(3):
+                gsegs += M.moray_td_step(ctx, td, dsub)[0]["segments"]
+            torch.cuda.synchronize()
+            gdt = time.perf_counter() - g0
+        finally:
+            if td:
+                M.moray_td_free(ctx, td)
+            M.moray_free(ctx)
+        out["cpu_oracle"] = {"value": osegs / dt, "unit": "segments/s", "cores": 1, "kind": "oracle",
+                             "sample": f"sources 3 and 11, steps 1-3: {osegs} segments in {dt:.1f} s",
+                             "gpu_same_sample": gsegs / gdt, "gpu_speedup": (gsegs / gdt) / (osegs / dt)}
+    return out
 
 
 def _batched_c2(M, steps):
@@ -634,13 +682,14 @@ def main():
         extras["equilibrium"] = _equilibrium_c1(M)
         print(f"# equilibrium: {extras['equilibrium']['ms_per_trace']:.2f} ms per trace + update", file=sys.stderr,
               flush=True)
-        extras["covering"] = _covering_c1(M, max(2, args.steps // 2))
+        oth = 0 if args.no_cpu_baseline else args.cpu_threads
+        extras["covering"] = _covering_c1(M, max(2, args.steps // 2), oth)
         print(f"# covering factor: {extras['covering']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['covering']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
-        extras["radpres"] = _radpres_c1(M, max(2, args.steps // 2))
+        extras["radpres"] = _radpres_c1(M, max(2, args.steps // 2), oth)
         print(f"# radiation pressure: {extras['radpres']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['radpres']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
-        extras["td_rays"] = _td_c1(M)
+        extras["td_rays"] = _td_c1(M, oracle=not args.no_cpu_baseline)
         print(f"# time-dependent rays: {extras['td_rays']['segments_per_s_late']:.3e} segments/s", file=sys.stderr,
               flush=True)
         extras["evolve_test1"] = _evolve_test1(M)
