@@ -273,10 +273,12 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
 /* Time-dependent rays (section 2.1: a ray halts once it has travelled c dt_P
  * and continues from there in the next step, which keeps the time derivative
  * of the transfer equation; section 3.1 step 3j). A moray_td holds, on the
- * device, the rays in flight between steps of one single-grid problem.
+ * device, the rays in flight between steps of one problem (a root grid and
+ * its children).
  *
- * moray_td_create: state for problems shaped like prob (its grid size, source
- * and group counts and level_init; its fields may change from step to step).
+ * moray_td_create: state for problems shaped like prob (its grid sizes and
+ * offsets, source and group counts and level_init; its fields may change from
+ * step to step).
  * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (1024 to
  * 2^34) bounds the rays in flight and each level's queue; the state holds
  * about 144 bytes of device memory per pool ray (two pools of 32 B, two

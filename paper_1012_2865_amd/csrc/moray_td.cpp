@@ -23,7 +23,9 @@
 using namespace moray;
 
 struct moray_td {
-  int nx = 0, ny = 0, nz = 0, n_src = 0, n_grp = 0, level_init = 0;
+  std::vector<int> shape;               // per grid: nx, ny, nz, offset (children)
+  int n_src = 0, n_grp = 0, level_init = 0;
+  long long n_cells = 0;
   double c_dt = 0.0;
   int slots = 0;
   long long step = 0;
@@ -45,9 +47,18 @@ struct moray_td {
   void* h_stage = nullptr;
 };
 
+static std::vector<int> grid_shape(const moray_problem& P) {
+  std::vector<int> v;
+  for (int q = 0; q < P.n_grids; ++q) {
+    const moray_grid& G = P.grids[q];
+    v.insert(v.end(), {G.nx, G.ny, G.nz, q > 0 ? G.offset[0] : 0, q > 0 ? G.offset[1] : 0, q > 0 ? G.offset[2] : 0});
+  }
+  return v;
+}
+
 static bool same_shape(const moray_td* t, const moray_problem& P) {
-  return P.n_grids == 1 && P.grids[0].nx == t->nx && P.grids[0].ny == t->ny && P.grids[0].nz == t->nz &&
-         P.n_sources == t->n_src && P.spectrum->n_groups == t->n_grp && P.params.level_init == t->level_init;
+  return grid_shape(P) == t->shape && P.n_sources == t->n_src && P.spectrum->n_groups == t->n_grp &&
+         P.params.level_init == t->level_init;
 }
 
 static void td_release(moray_ctx* c, moray_td* t) {
@@ -72,7 +83,6 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
   *out = nullptr;
   if (!(c_dt > 0.0) || !std::isfinite(c_dt)) return fail(c, MORAY_EINVAL, "c_dt must be positive and finite");
   if (pool_rays < 1024 || pool_rays > ((size_t)1 << 34)) return fail(c, MORAY_EINVAL, "pool_rays out of range");
-  if (prob->n_grids != 1) return fail(c, MORAY_EINVAL, "time-dependent rays take a single grid");
   moray_status st = validate(c, *prob, 0);
   if (st != MORAY_OK) return st;
   if (prob->params.covering) return fail(c, MORAY_EINVAL, "time-dependent rays do not take the covering factor");
@@ -82,12 +92,16 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
   const double need_slots = std::ceil(diag / c_dt) + 2.0;
   const long long per = (long long)prob->n_sources * prob->spectrum->n_groups;
   if (need_slots * (double)per >= 2.0e9) return fail(c, MORAY_EINVAL, "c_dt too small for this many trees");
-  if ((double)G.nx * G.ny * G.nz * prob->spectrum->n_groups >= (double)kNoSlot)
-    return fail(c, MORAY_EINVAL, "the grid needs fewer than 2^32 - 1 accumulators (cells x groups)");
+  long long n_cells = 0;
+  for (int q = 0; q < prob->n_grids; ++q)
+    n_cells += (long long)prob->grids[q].nx * prob->grids[q].ny * prob->grids[q].nz;
+  if ((double)n_cells * prob->spectrum->n_groups >= (double)kNoSlot)
+    return fail(c, MORAY_EINVAL, "the grids need fewer than 2^32 - 1 accumulators (cells x groups)");
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
 
   moray_td* t = new moray_td();
-  t->nx = G.nx; t->ny = G.ny; t->nz = G.nz;
+  t->shape = grid_shape(*prob);
+  t->n_cells = n_cells;
   t->n_src = prob->n_sources;
   t->n_grp = prob->spectrum->n_groups;
   t->level_init = prob->params.level_init;
@@ -98,12 +112,14 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
   t->cap = pool_rays;
   t->nseg = queue_segments(pool_rays);
   t->seg_cap = pool_rays / (size_t)t->nseg;
-  const long long n_cells = (long long)G.nx * G.ny * G.nz;
   const int n_sg = (int)(t->slots * per);
   const size_t rsz = c->precision == MORAY_FP32_ACC64 ? sizeof(float) : sizeof(double);
   {
     const long long per_fb = (long long)kFinalBlock * kFinalCellsPerThread;
-    for (long long f = 0; f < n_cells; f += per_fb) t->fb.push_back({0, (int)std::min(per_fb, n_cells - f), f});
+    for (int q = 0; q < prob->n_grids; ++q) {
+      const long long nc = (long long)prob->grids[q].nx * prob->grids[q].ny * prob->grids[q].nz;
+      for (long long f = 0; f < nc; f += per_fb) t->fb.push_back({q, (int)std::min(per_fb, nc - f), f});
+    }
   }
   const size_t stage = sizeof(Counters) + (size_t)n_sg * sizeof(SgStats) + t->fb.size() * 8;
   for (int i = 0; i < 2 && st == MORAY_OK; ++i) {
@@ -116,7 +132,7 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
       break;
   }
   if (st == MORAY_OK) {
-    (void)((st = ensure(c, t->grids, sizeof(GridDev), "grid table")) ||
+    (void)((st = ensure(c, t->grids, (size_t)prob->n_grids * sizeof(GridDev), "grid table")) ||
            (st = ensure(c, t->probs, sizeof(ProblemDev), "problem table")) ||
            (st = ensure(c, t->sgs, (size_t)n_sg * sizeof(SgDev), "source table")) ||
            (st = ensure(c, t->stats, (size_t)n_sg * sizeof(SgStats), "statistics")) ||
@@ -217,7 +233,7 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   const moray_problem& P = *prob;
   const moray_grid& G = P.grids[0];
   const moray_spectrum& Sp = *P.spectrum;
-  const long long n_cells = (long long)G.nx * G.ny * G.nz;
+  const long long n_cells = t->n_cells;
   const int per = t->n_src * t->n_grp;
   const int n_sg = t->slots * per;
   const int cur_slot = (int)(t->step % t->slots);
@@ -231,16 +247,30 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
     t->emit_step[cur_slot] = -1;          // an older batch here has left the box
   }
 
-  // tables
-  GridDev gd{};
-  gd.nx = G.nx; gd.ny = G.ny; gd.nz = G.nz;
-  gd.problem = 0;
-  gd.cell_off = 0;
-  gd.dx_cm = G.dx_cm;
-  gd.n_h = G.n_h;
-  gd.x_hi = G.x_hi;
-  gd.out_kph = out->k_ph;
-  gd.out_heat = out->heating;
+  // tables: the root grid, then its children (cells numbered in grid order)
+  std::vector<GridDev> gds(P.n_grids);
+  long long steps_bound = 16;
+  {
+    long long off = 0;
+    for (int q = 0; q < P.n_grids; ++q) {
+      const moray_grid& Gq = P.grids[q];
+      GridDev& gd = gds[q];
+      gd.nx = Gq.nx; gd.ny = Gq.ny; gd.nz = Gq.nz;
+      gd.is_child = q > 0;
+      gd.ox = q > 0 ? Gq.offset[0] : 0;
+      gd.oy = q > 0 ? Gq.offset[1] : 0;
+      gd.oz = q > 0 ? Gq.offset[2] : 0;
+      gd.problem = 0;
+      gd.cell_off = off;
+      gd.dx_cm = Gq.dx_cm;
+      gd.n_h = Gq.n_h;
+      gd.x_hi = Gq.x_hi;
+      gd.out_kph = out->k_ph + off;
+      gd.out_heat = out->heating + off;
+      off += (long long)Gq.nx * Gq.ny * Gq.nz;
+      steps_bound += 2LL * (Gq.nx + Gq.ny + Gq.nz);
+    }
+  }
   ProblemDev pd{};
   pd.root_grid = 0;
   pd.n_groups = t->n_grp;
@@ -278,7 +308,7 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   auto up = [&](DevBuf& b, const void* src, size_t bytes) {
     return hip_ok(c, hipMemcpyAsync(b.p, src, bytes, hipMemcpyHostToDevice, s), "upload");
   };
-  if (!up(t->grids, &gd, sizeof gd) || !up(t->probs, &pd, sizeof pd) || !up(t->sgs, sgs.data(), sgs.size() * sizeof(SgDev)) ||
+  if (!up(t->grids, gds.data(), gds.size() * sizeof(GridDev)) || !up(t->probs, &pd, sizeof pd) || !up(t->sgs, sgs.data(), sgs.size() * sizeof(SgDev)) ||
       !up(t->eexc, eexc.data(), eexc.size() * 8))
     return MORAY_EDEVICE;
 
@@ -287,7 +317,7 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   int l_lo = emit ? P.params.level_init : kLevels;
   for (int l = 0; l < kLevels; ++l)
     if (t->lev_in[l]) { l_lo = std::min(l_lo, l); break; }
-  unsigned max_steps = (unsigned)std::min<long long>(2 * (16 + 2LL * (G.nx + G.ny + G.nz)), 1LL << 30);
+  unsigned max_steps = (unsigned)std::min<long long>(2 * steps_bound, 1LL << 30);
   const double waves = (double)std::max(1, c->num_cu * c->blocks_per_cu) * (kTraceBlock / kWave);
   unsigned long long reserve =
       (unsigned long long)std::min<double>((double)kReserveMax, (double)t->cap / (8.0 * waves));
@@ -302,9 +332,9 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   };
   hipError_t e = launch_reset(s, ctr, (SgStats*)t->stats.p, n_sg);
   if (e == hipSuccess)
-    e = fp32 ? launch_prep<float>(s, c->num_cu, (GridDev*)t->grids.p, 1, 0, (ProblemDev*)t->probs.p, 0, n_cells,
+    e = fp32 ? launch_prep<float>(s, c->num_cu, (GridDev*)t->grids.p, P.n_grids, 0, (ProblemDev*)t->probs.p, 0, n_cells,
                                   (float*)t->kappa.p, (double*)t->acc.p, ctr)
-             : launch_prep<double>(s, c->num_cu, (GridDev*)t->grids.p, 1, 0, (ProblemDev*)t->probs.p, 0, n_cells,
+             : launch_prep<double>(s, c->num_cu, (GridDev*)t->grids.p, P.n_grids, 0, (ProblemDev*)t->probs.p, 0, n_cells,
                                    (double*)t->kappa.p, (double*)t->acc.p, ctr);
   if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
   int launches = 0;

@@ -6,7 +6,8 @@ oracle's orc_trace_td on the same seeded inputs, through the C ABI:
   flight, escaped and absorbed to the same bar; segment, split, escape and
   truncation counts exact in float64; per-step photon bookkeeping
   emitted + held before = absorbed + escaped + truncated + held after;
-* a pulse (emission in the first step only) against the oracle's pulse;
+* a pulse (emission in the first step only) against the oracle's pulse, and
+  a root grid with a refined child holding a source;
 * c dt_P beyond the box: one step equals moray_trace;
 * a pool too small fails the step with MORAY_EQUEUE and the state refuses
   further steps; bad arguments are rejected.
@@ -37,8 +38,21 @@ def _problem(item=1):
     return W.lognormal_problem(92, item, 20, 2, mean=1e-4)
 
 
-def _compare_steps(precision, emits, cdt=4.0, item=1):
+def _nested_problem(item=6):
+    # a thin root with a 2x-refined child holding one of the sources
     p = _problem(item)
+    rng = W.rng_for(92, 100 + item, 0)
+    child = W.Grid(n_h=(10 ** rng.uniform(-4.5, -3.5, (12, 12, 12))).astype(np.float32),
+                   x_hi=rng.uniform(0.5, 1.0, (12, 12, 12)).astype(np.float32),
+                   dx_cm=p.grids[0].dx_cm / 2, parent=0, offset=(4, 5, 6))
+    p.grids.append(child)
+    p.sources = p.sources.copy()
+    p.sources[0, :3] = [7.25, 8.5, 9.75]
+    return p
+
+
+def _compare_steps(precision, emits, cdt=4.0, item=1, make=None):
+    p = _problem(item) if make is None else make()
     dev = M.problem_to_device(p)
     ctx = M.moray_init(device=0, precision=precision)
     td = None
@@ -51,7 +65,10 @@ def _compare_steps(precision, emits, cdt=4.0, item=1):
             ref, rays = O.trace_td(p, cdt, rays, emit=emit)
             res, held = M.moray_td_step(ctx, td, dev, emit=emit)
             T = ref["totals"]
-            rel, absr = _rel(res["k_ph"][0], ref["k_ph"][0])
+            rel, absr = 0.0, 0.0
+            for q in range(len(p.grids)):
+                rq, aq = _rel(res["k_ph"][q], ref["k_ph"][q])
+                rel, absr = max(rel, rq), max(absr, aq)
             print(f"[td prec {precision} step {step} emit {emit}] k_ph max rel {rel:.2e}, held {held:.4e} "
                   f"(oracle {ref['held']:.4e}), in flight {len(rays)}, segments {res['segments']}/{T['segments']}",
                   flush=True)
@@ -75,6 +92,11 @@ def _compare_steps(precision, emits, cdt=4.0, item=1):
 @pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
 def test_steps_match_the_oracle(precision):
     _compare_steps(precision, [True] * 8)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_nested_grids_match_the_oracle(precision):
+    _compare_steps(precision, [True] * 5, cdt=5.0, make=_nested_problem)
 
 
 @pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
