@@ -33,25 +33,49 @@ def equilibrium_x(k_ph: np.ndarray, n_h: np.ndarray, alpha_b: float = ALPHA_B) -
     return np.where(a > 0.0, x, 1.0)
 
 
-def iterate(problem, tol: float = 1e-6, max_iter: int = 300, damping: float = 0.5, n_threads: int = 1):
-    """Damped fixed-point iteration to ionisation equilibrium (single grid).
+def covered_root_cells(problem) -> np.ndarray:
+    """Root cells that a child grid covers (their radiation field lives in the
+    child; they keep their neutral fraction in the updates)."""
+    root = problem.grids[0]
+    mask = np.zeros(np.asarray(root.n_h).shape, dtype=bool)
+    for g in problem.grids[1:]:
+        ox, oy, oz = (int(v) for v in g.offset)
+        nz, ny, nx = np.asarray(g.n_h).shape
+        mask[oz:oz + nz // 2, oy:oy + ny // 2, ox:ox + nx // 2] = True
+    return mask
 
-    Returns (x_final float64 array, last oracle result, iterations used)."""
+
+def iterate(problem, tol: float = 1e-6, max_iter: int = 300, damping: float = 0.5, n_threads: int = 1):
+    """Damped fixed-point iteration to ionisation equilibrium, from neutral
+    gas, over every grid of the problem (covered root cells excluded).
+
+    Returns (x_final, last oracle result, iterations used): x_final is a
+    float64 array for a single grid, else a list of arrays, one per grid."""
     p = copy.copy(problem)
-    g = copy.copy(problem.grids[0])
-    p.grids = [g]
-    x = np.ones(g.n_h.shape)
+    p.grids = [copy.copy(g) for g in problem.grids]
+    covered = covered_root_cells(problem)
+    xs = [np.ones(np.asarray(g.n_h).shape) for g in p.grids]
     res = None
+    done = max_iter
     for it in range(1, max_iter + 1):
-        g.x_hi = x.astype(np.float32)
-        res = _oracle.trace(p, n_threads=n_threads)
-        x_new = equilibrium_x(res["k_ph"][0], g.n_h)
-        x_next = (1.0 - damping) * x + damping * x_new
-        dx = np.max(np.abs(x_next - x))
-        x = x_next
-        if dx < tol:
+        for g, x in zip(p.grids, xs):
             g.x_hi = x.astype(np.float32)
+        res = _oracle.trace(p, n_threads=n_threads)
+        dx = 0.0
+        for q, g in enumerate(p.grids):
+            x_new = equilibrium_x(res["k_ph"][q], g.n_h)
+            x_next = (1.0 - damping) * xs[q] + damping * x_new
+            if q == 0:
+                x_next[covered] = xs[0][covered]
+            dx = max(dx, float(np.max(np.abs(x_next - xs[q]))))
+            xs[q] = x_next
+        if dx < tol:
+            done = it
+            for g, x in zip(p.grids, xs):
+                g.x_hi = x.astype(np.float32)
             res = _oracle.trace(p, n_threads=n_threads)
-            return x, res, it
-    g.x_hi = x.astype(np.float32)
-    return x, res, max_iter
+            break
+    else:
+        for g, x in zip(p.grids, xs):
+            g.x_hi = x.astype(np.float32)
+    return (xs[0] if len(xs) == 1 else xs), res, done

@@ -33,7 +33,7 @@ import copy
 import numpy as np
 
 from . import oracle as _oracle
-from .equilibrium import ALPHA_B, equilibrium_x
+from .equilibrium import ALPHA_B, covered_root_cells, equilibrium_x
 
 
 def advance(x0, k_ph, n_h, dt, alpha_b: float = ALPHA_B):
@@ -114,26 +114,46 @@ def next_dt(k_ph, x, n_h, dx_cm, sig_bar, eps, tau_front, dt_max, dt_prev, t_lef
 
 def evolve(problem, t_end: float, eps: float = 0.1, tau_front: float = 0.5, dt_max: float | None = None,
            max_steps: int = 100000, alpha_b: float = ALPHA_B, x0=None, n_threads: int = 1):
-    """Evolve a single-grid problem's neutral fraction from x0 (default: its
-    x_hi) for t_end seconds. Returns (x float64, last trace result, steps,
-    time reached, list of steps taken)."""
+    """Evolve a problem's neutral fraction from x0 (default: its x_hi; a
+    list per grid when it has several) for t_end seconds. Every grid takes
+    the same step: the smallest of its own smoothed limits (each grid smoothed
+    on its own), covered root cells excluded (they take dt_max and keep their
+    x). Returns (x, last trace result, steps, time reached, list of steps
+    taken); x is a float64 array for a single grid, else a list per grid."""
     p = copy.copy(problem)
-    g = copy.copy(problem.grids[0])
-    p.grids = [g]
+    p.grids = [copy.copy(g) for g in problem.grids]
     if dt_max is None:
         dt_max = t_end
     sb = sigma_bar(p.spectrum)
-    x = np.asarray(problem.grids[0].x_hi if x0 is None else x0, dtype=np.float64).copy()
+    covered = covered_root_cells(problem)
+    if x0 is None:
+        xs = [np.asarray(g.x_hi, dtype=np.float64).copy() for g in problem.grids]
+    else:
+        xs = [np.asarray(v, dtype=np.float64).copy() for v in (x0 if isinstance(x0, (list, tuple)) else [x0])]
     t, dt_prev, dts = 0.0, None, []
     while t < t_end and len(dts) < max_steps:
-        g.x_hi = x.astype(np.float32)
+        for g, x in zip(p.grids, xs):
+            g.x_hi = x.astype(np.float32)
         res = _oracle.trace(p, n_threads=n_threads)
-        dt = next_dt(res["k_ph"][0], x, g.n_h, g.dx_cm, sb, eps, tau_front, dt_max, dt_prev, t_end - t, alpha_b)
-        x = advance(x, res["k_ph"][0], g.n_h, dt, alpha_b)
+        dt = np.inf
+        for q, g in enumerate(p.grids):
+            lim = cell_limits(res["k_ph"][q], xs[q], g.n_h, g.dx_cm, sb, eps, tau_front, dt_max, alpha_b)
+            if q == 0:
+                lim[covered] = dt_max
+            dt = min(dt, float(np.min(smooth3(lim))))
+        if dt_prev is not None:
+            dt = min(dt, 2.0 * dt_prev)
+        dt = min(dt, dt_max, t_end - t)
+        for q, g in enumerate(p.grids):
+            x_new = advance(xs[q], res["k_ph"][q], g.n_h, dt, alpha_b)
+            if q == 0:
+                x_new[covered] = xs[0][covered]
+            xs[q] = x_new
         t += dt
         dt_prev = dt
         dts.append(dt)
-    g.x_hi = x.astype(np.float32)
+    for g, x in zip(p.grids, xs):
+        g.x_hi = x.astype(np.float32)
     res = _oracle.trace(p, n_threads=n_threads)
-    return x, res, len(dts), t, dts
+    return (xs[0] if len(xs) == 1 else xs), res, len(dts), t, dts
 

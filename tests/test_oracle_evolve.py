@@ -127,3 +127,24 @@ def test_test1_front_follows_the_analytic_radius(n_cells, t_over, dtm, tol):
     print(f"{n_cells}^3 to {t:.2f} t_rec in {steps} steps: r_I / r_s = {ratio:.4f}")
     assert t == pytest.approx(t_over, rel=1e-12)
     assert abs(ratio - 1.0) < tol
+
+
+def test_nested_grids_step_together_and_covered_cells_keep_x():
+    # an optically thick root whose source's photons die in its first cells;
+    # the child far away sees no radiation, so its gas only recombines:
+    # x(t) = 1 - (1 - x0) / (1 + a t (1 - x0)) exactly, with a = alpha n_H
+    n = 16
+    g = W.uniform_grid(n, W.DX_C1, 1.0, 0.5)
+    child = W.Grid(n_h=np.full((8, 8, 8), 2.0, np.float32), x_hi=np.full((8, 8, 8), 0.25, np.float32),
+                   dx_cm=W.DX_C1 / 2, parent=0, offset=(10, 10, 10))
+    p = W.Problem([g, child], np.array([[0.5, 0.5, 0.5, 1e49]]), W.hydrogen_spectrum([13.6]), W.Params())
+    t_end = 3e12
+    xs, res, steps, t, dts = EV.evolve(p, t_end, eps=0.1, dt_max=t_end / 20)
+    assert isinstance(xs, list) and len(xs) == 2 and t == pytest.approx(t_end, rel=1e-12)
+    assert steps >= 20 and np.max(res["k_ph"][1]) == 0.0
+    a = ALPHA * 2.0
+    want = 1.0 - 0.75 / (1.0 + a * t * 0.75)
+    assert np.allclose(xs[1], want, rtol=1e-9, atol=0.0)
+    # the root cells under the child keep their neutral fraction; the others near the source ionise
+    assert np.all(xs[0][10:14, 10:14, 10:14] == 0.5)
+    assert xs[0][0, 0, 0] < 0.5
