@@ -216,14 +216,16 @@ typedef struct {
  * largest change of x is below tol or max_iter updates are done; then trace
  * once more with the final x into `out` (host or device results by flags, as
  * in moray_trace; escaped_sg is filled when given).
- * The problem must have a single grid and device-resident fields (flags must
- * include MORAY_FIELDS_ON_DEVICE). Its x_hi array is updated in place: it
- * holds the float32 neutral fraction of every iterate and, on return, of the
- * last one; the iteration itself keeps x in float64, which x_out (device
- * memory, [cells], or NULL) receives. *iterations (or NULL) receives the
- * number of updates made. Returns MORAY_EINVAL for bad parameters, more than
- * one grid or host fields (nothing is changed then), and the errors of
- * moray_trace (x_hi then holds the last iterate). */
+ * The problem must have device-resident fields (flags must include
+ * MORAY_FIELDS_ON_DEVICE); every grid is updated, except the root cells a
+ * child grid covers, which keep their x (their field lives in the child), and
+ * the largest change is taken over all grids. Its x_hi arrays are updated in
+ * place: they hold the float32 neutral fraction of every iterate and, on
+ * return, of the last one; the iteration itself keeps x in float64, which
+ * x_out (device memory, [total cells] in grid order, or NULL) receives.
+ * *iterations (or NULL) receives the number of updates made. Returns
+ * MORAY_EINVAL for bad parameters or host fields (nothing is changed then),
+ * and the errors of moray_trace (x_hi then holds the last iterate). */
 moray_status moray_equilibrate(moray_ctx* ctx, const moray_problem* prob, unsigned flags,
                                const moray_equilibrium_params* params, double* x_out, moray_result* out,
                                int* iterations);
@@ -258,14 +260,17 @@ typedef struct {
  * until t reaches t_end or max_steps steps are done; then traces once more
  * with the final x into `out` (host or device results by flags, as in
  * moray_trace; escaped_sg is filled when given).
- * The problem must have a single grid and device-resident fields (flags must
- * include MORAY_FIELDS_ON_DEVICE). Its x_hi array is updated in place and
- * holds the float32 neutral fraction of every step; the evolution keeps x in
- * float64, which x_out (device memory, [cells], or NULL) receives. *steps,
- * *t_reached and dt_steps (host memory, [max_steps]) receive, when not NULL,
- * the steps taken, the time reached and each step's dt. Returns MORAY_EINVAL
- * for bad parameters, more than one grid or host fields (nothing is changed
- * then), and the errors of moray_trace (x_hi then holds the last step's x). */
+ * The problem must have device-resident fields (flags must include
+ * MORAY_FIELDS_ON_DEVICE). With child grids, each grid's limits are smoothed
+ * within that grid, the step is the smallest over the grids, and the root
+ * cells a child covers keep their x and take dt_max as their limit. The x_hi
+ * arrays are updated in place and hold the float32 neutral fraction of every
+ * step; the evolution keeps x in float64, which x_out (device memory, [total
+ * cells] in grid order, or NULL) receives. *steps, *t_reached and dt_steps
+ * (host memory, [max_steps]) receive, when not NULL, the steps taken, the
+ * time reached and each step's dt. Returns MORAY_EINVAL for bad parameters or
+ * host fields (nothing is changed then), and the errors of moray_trace (x_hi
+ * then holds the last step's x). */
 moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned flags,
                           const moray_evolve_params* params, double* x_out, moray_result* out, int* steps,
                           double* t_reached, double* dt_steps);

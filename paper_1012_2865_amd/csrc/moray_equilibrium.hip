@@ -38,11 +38,13 @@ __device__ __forceinline__ double block_max(double m) {
   return m;                                   // valid in thread 0
 }
 
+// skip (or NULL): cells that keep their x (root cells under a child grid)
 __global__ __launch_bounds__(kEqBlock) void equilibrium_update_kernel(const double* __restrict__ kph,
                                                                       const float* __restrict__ n_h,
                                                                       double* __restrict__ x64,
                                                                       float* __restrict__ x32, long long n,
                                                                       double alpha_b, double w,
+                                                                      const unsigned char* __restrict__ skip,
                                                                       double* __restrict__ part) {
   const long long stride = (long long)gridDim.x * kEqBlock;
   double dmax = 0.0;
@@ -60,7 +62,7 @@ __global__ __launch_bounds__(kEqBlock) void equilibrium_update_kernel(const doub
 #pragma unroll
     for (int u = 0; u < kEqUnroll; ++u) {
       const long long i = base + u * stride;
-      if (i < n) {
+      if (i < n && !(skip && skip[i])) {
         const double a = alpha_b * (double)nh[u];
         const double root = a > 0.0 ? 2.0 * a / ((2.0 * a + k[u]) + sqrt(k[u] * k[u] + 4.0 * a * k[u])) : 1.0;
         const double xn = (1.0 - w) * x[u] + w * root;
@@ -117,13 +119,14 @@ __global__ __launch_bounds__(kEqBlock) void step_limit_kernel(const double* __re
                                                               const double* __restrict__ x64, long long n,
                                                               double alpha_b, double sigma_bar, double dx_cm,
                                                               double eps, double tau_front, double dt_max,
+                                                              const unsigned char* __restrict__ skip,
                                                               double* __restrict__ lim) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double x = x64[i], nh = (double)n_h[i];
     const double rate = kph[i] + (1.0 - x) * nh * alpha_b;
     const bool front = sigma_bar * nh * x * dx_cm > tau_front;
     double v = dt_max;
-    if (front && rate > 0.0) v = fmin(eps / rate, dt_max);
+    if (front && rate > 0.0 && !(skip && skip[i])) v = fmin(eps / rate, dt_max);
     lim[i] = v;
   }
 }
@@ -173,13 +176,14 @@ __global__ __launch_bounds__(1024) void min_partials_kernel(const double* __rest
 __global__ __launch_bounds__(kEqBlock) void evolve_update_kernel(const double* __restrict__ kph,
                                                                  const float* __restrict__ n_h,
                                                                  double* __restrict__ x64, float* __restrict__ x32,
-                                                                 long long n, double alpha_b, double dt) {
+                                                                 long long n, double alpha_b, double dt,
+                                                                 const unsigned char* __restrict__ skip) {
   for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x) {
     const double a = alpha_b * (double)n_h[i];
     const double k = kph[i];
     const double x0 = x64[i];
     double x = x0;
-    if (a > 0.0) {
+    if (a > 0.0 && !(skip && skip[i])) {
       const double d = sqrt(k * k + 4.0 * a * k);
       const double x1 = 2.0 * a / ((2.0 * a + k) + d);
       const double g = d > 0.0 ? -expm1(-d * dt) / d : dt;
@@ -203,10 +207,10 @@ static int equilibrium_blocks(long long n) {
 }
 
 hipError_t launch_equilibrium_update(hipStream_t s, const double* kph, const float* n_h, double* x64, float* x32,
-                                     long long n, double alpha_b, double w, double* dx) {
+                                     long long n, double alpha_b, double w, const unsigned char* skip, double* dx) {
   const int blocks = equilibrium_blocks(n);
   hipLaunchKernelGGL(equilibrium_update_kernel, dim3(blocks), dim3(kEqBlock), 0, s, kph, n_h, x64, x32, n, alpha_b,
-                     w, dx + 1);
+                     w, skip, dx + 1);
   hipLaunchKernelGGL(max_partials_kernel, dim3(1), dim3(1024), 0, s, (const double*)(dx + 1), blocks, dx);
   return hipGetLastError();
 }
@@ -220,20 +224,20 @@ static int grid_blocks(int num_cu, long long n) {
 
 hipError_t launch_step_limit(hipStream_t s, int num_cu, const double* kph, const float* n_h, const double* x64,
                              int nx, int ny, int nz, double alpha_b, double sigma_bar, double dx_cm, double eps,
-                             double tau_front, double dt_max, double* lim, double* dmin) {
+                             double tau_front, double dt_max, const unsigned char* skip, double* lim, double* dmin) {
   const long long n = (long long)nx * ny * nz;
   const int blocks = grid_blocks(num_cu, n);
   hipLaunchKernelGGL(step_limit_kernel, dim3(blocks), dim3(kEqBlock), 0, s, kph, n_h, x64, n, alpha_b, sigma_bar,
-                     dx_cm, eps, tau_front, dt_max, lim);
+                     dx_cm, eps, tau_front, dt_max, skip, lim);
   hipLaunchKernelGGL(smooth_min_kernel, dim3(blocks), dim3(kEqBlock), 0, s, (const double*)lim, nx, ny, nz, dmin + 1);
   hipLaunchKernelGGL(min_partials_kernel, dim3(1), dim3(1024), 0, s, (const double*)(dmin + 1), blocks, dmin);
   return hipGetLastError();
 }
 
 hipError_t launch_evolve_update(hipStream_t s, int num_cu, const double* kph, const float* n_h, double* x64,
-                                float* x32, long long n, double alpha_b, double dt) {
+                                float* x32, long long n, double alpha_b, double dt, const unsigned char* skip) {
   hipLaunchKernelGGL(evolve_update_kernel, dim3(grid_blocks(num_cu, n)), dim3(kEqBlock), 0, s, kph, n_h, x64, x32, n,
-                     alpha_b, dt);
+                     alpha_b, dt, skip);
   return hipGetLastError();
 }
 

@@ -42,14 +42,14 @@ hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
 // dx: 1 + kEqMaxBlocks doubles; dx[0] receives the largest change of the pass
 constexpr int kEqMaxBlocks = 2048;
 hipError_t launch_equilibrium_update(hipStream_t, const double* kph, const float* n_h, double* x64, float* x32,
-                                     long long n, double alpha_b, double w, double* dx);
+                                     long long n, double alpha_b, double w, const unsigned char* skip, double* dx);
 hipError_t launch_widen(hipStream_t, int num_cu, const float* x32, double* x64, long long n);
 // moray_evolve: lim receives the per-cell limits, dmin (1 + kEqMaxBlocks doubles) their smoothed minimum in dmin[0]
 hipError_t launch_step_limit(hipStream_t, int num_cu, const double* kph, const float* n_h, const double* x64, int nx,
                              int ny, int nz, double alpha_b, double sigma_bar, double dx_cm, double eps,
-                             double tau_front, double dt_max, double* lim, double* dmin);
+                             double tau_front, double dt_max, const unsigned char* skip, double* lim, double* dmin);
 hipError_t launch_evolve_update(hipStream_t, int num_cu, const double* kph, const float* n_h, double* x64, float* x32,
-                                long long n, double alpha_b, double dt);
+                                long long n, double alpha_b, double dt, const unsigned char* skip);
 
 struct DevBuf {
   void* p = nullptr;
@@ -87,6 +87,7 @@ struct moray_ctx {
   moray::DevBuf eq_x, eq_kph, eq_heat, eq_dx;   // moray_equilibrate / moray_evolve: float64 iterate, rates,
                                                  // reduction partials
   moray::DevBuf ev_lim;                          // moray_evolve: per-cell step limits
+  moray::DevBuf eq_skip;                         // both: root cells under a child grid (1) or not (0)
 };
 
 namespace moray {

@@ -362,7 +362,7 @@ void moray_free(moray_ctx* c) {
   else (void)hipDeviceSynchronize();
   DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,
                    &c->acc,     &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
-                   &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx,  &c->ev_lim};
+                   &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx,  &c->ev_lim, &c->eq_skip};
   for (DevBuf* b : all) release(c, *b);
   for (int i = 0; i < 2; ++i) {
     release(c, c->q_pix[i]);
@@ -808,45 +808,85 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   }
 }
 
+// Cells of the ionisation updates: every grid of the problem in order
+// (their offsets in the concatenated results), and a mask of the root cells a
+// child covers, which keep their neutral fraction (their field lives in the
+// child), uploaded to c->eq_skip.
+struct UpdateGrids {
+  std::vector<long long> off;      // first cell of each grid; off.back() = all cells
+};
+
+static moray_status update_grids(moray_ctx* c, const moray_problem& P, UpdateGrids& U) {
+  U.off.assign(1, 0);
+  for (int q = 0; q < P.n_grids; ++q)
+    U.off.push_back(U.off.back() + (long long)P.grids[q].nx * P.grids[q].ny * P.grids[q].nz);
+  if (P.n_grids == 1) return MORAY_OK;
+  const moray_grid& R = P.grids[0];
+  std::vector<unsigned char> skip((size_t)U.off[1], 0);
+  for (int q = 1; q < P.n_grids; ++q) {
+    const moray_grid& G = P.grids[q];
+    for (int k = 0; k < G.nz / 2; ++k)
+      for (int j = 0; j < G.ny / 2; ++j)
+        for (int i = 0; i < G.nx / 2; ++i)
+          skip[(size_t)(G.offset[0] + i) + (size_t)R.nx * ((size_t)(G.offset[1] + j) + (size_t)R.ny * (G.offset[2] + k))] = 1;
+  }
+  moray_status st = ensure(c, c->eq_skip, skip.size(), "covered cells");
+  if (st != MORAY_OK) return st;
+  if (!hip_ok(c, hipMemcpyAsync(c->eq_skip.p, skip.data(), skip.size(), hipMemcpyHostToDevice, c->stream), "upload") ||
+      !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
+    return MORAY_EDEVICE;
+  return MORAY_OK;
+}
+
 moray_status moray_equilibrate(moray_ctx* c, const moray_problem* prob, unsigned flags,
                                const moray_equilibrium_params* ep, double* x_out, moray_result* out, int* iterations) {
   if (!c) return MORAY_EINVAL;
   if (!prob || !ep || !out) return fail(c, MORAY_EINVAL, "NULL problem, parameters or result");
   if (!(ep->alpha_b > 0.0) || !(ep->damping > 0.0 && ep->damping <= 1.0) || !(ep->tol > 0.0) || ep->max_iter < 1)
     return fail(c, MORAY_EINVAL, "alpha_b, damping, tol or max_iter out of range");
-  if (prob->n_grids != 1) return fail(c, MORAY_EINVAL, "the equilibrium iteration takes a single grid");
   if (!(flags & MORAY_FIELDS_ON_DEVICE)) return fail(c, MORAY_EINVAL, "the equilibrium iteration needs device fields");
   if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
   moray_status st = validate(c, *prob, 0);
   if (st != MORAY_OK) return st;
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
-  const moray_grid& G = prob->grids[0];
-  const long long n = (long long)G.nx * G.ny * G.nz;
+  UpdateGrids U;
+  if ((st = update_grids(c, *prob, U)) != MORAY_OK) return st;
+  const int ng = prob->n_grids;
+  const long long n = U.off.back();
+  const size_t stride = 1 + kEqMaxBlocks;      // one reduction area per grid
   if ((st = ensure(c, c->eq_x, (size_t)n * 8, "equilibrium iterate")) ||
       (st = ensure(c, c->eq_kph, (size_t)n * 8, "equilibrium rates")) ||
       (st = ensure(c, c->eq_heat, (size_t)n * 8, "equilibrium rates")) ||
-      (st = ensure(c, c->eq_dx, (size_t)(1 + kEqMaxBlocks) * 8, "equilibrium change")))
+      (st = ensure(c, c->eq_dx, (size_t)ng * stride * 8, "equilibrium change")))
     return st;
-  // the caller's x_hi array is the iterate the trace reads (updated in place, see moray.h)
-  float* x32 = const_cast<float*>(G.x_hi);
+  // the caller's x_hi arrays are the iterate the trace reads (updated in place, see moray.h)
   double* x64 = (double*)c->eq_x.p;
   double* dx = (double*)c->eq_dx.p;
-  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n), "equilibrium start")) return MORAY_EDEVICE;
+  const unsigned char* skip = ng > 1 ? (const unsigned char*)c->eq_skip.p : nullptr;
+  for (int q = 0; q < ng; ++q)
+    if (!hip_ok(c, launch_widen(c->stream, c->num_cu, prob->grids[q].x_hi, x64 + U.off[q], U.off[q + 1] - U.off[q]),
+                "equilibrium start"))
+      return MORAY_EDEVICE;
   moray_result mid{};
   mid.k_ph = (double*)c->eq_kph.p;
   mid.heating = (double*)c->eq_heat.p;
   const unsigned mid_flags = flags | MORAY_OUT_ON_DEVICE;
+  std::vector<double> change(ng);
   int it = 0;
   while (it < ep->max_iter) {
     if ((st = moray_trace(c, prob, 1, mid_flags, &mid)) != MORAY_OK) return st;
     ++it;
-    double change = 0.0;
-    if (!hip_ok(c, launch_equilibrium_update(c->stream, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b, ep->damping, dx),
-                "equilibrium update") ||
-        !hip_ok(c, hipMemcpyAsync(&change, dx, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
-        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
-      return MORAY_EDEVICE;
-    if (change < ep->tol) break;
+    for (int q = 0; q < ng; ++q) {
+      const moray_grid& G = prob->grids[q];
+      if (!hip_ok(c, launch_equilibrium_update(c->stream, mid.k_ph + U.off[q], G.n_h, x64 + U.off[q],
+                                               const_cast<float*>(G.x_hi), U.off[q + 1] - U.off[q], ep->alpha_b,
+                                               ep->damping, q == 0 ? skip : nullptr, dx + q * stride),
+                  "equilibrium update") ||
+          !hip_ok(c, hipMemcpyAsync(&change[q], dx + q * stride, 8, hipMemcpyDeviceToHost, c->stream), "copy"))
+        return MORAY_EDEVICE;
+    }
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")) return MORAY_EDEVICE;
+    if (*std::max_element(change.begin(), change.end()) < ep->tol) break;
   }
   if ((st = moray_trace(c, prob, 1, flags, out)) != MORAY_OK) return st;
   if (x_out && (!hip_ok(c, hipMemcpyAsync(x_out, x64, (size_t)n * 8, hipMemcpyDeviceToDevice, c->stream), "copy") ||
@@ -863,50 +903,66 @@ moray_status moray_evolve(moray_ctx* c, const moray_problem* prob, unsigned flag
   if (!(ep->alpha_b > 0.0) || !(ep->eps_ion > 0.0) || !(ep->tau_front >= 0.0) || !(ep->dt_max > 0.0) ||
       !(ep->t_end > 0.0) || !std::isfinite(ep->t_end) || !std::isfinite(ep->dt_max) || ep->max_steps < 1)
     return fail(c, MORAY_EINVAL, "alpha_b, eps_ion, tau_front, dt_max, t_end or max_steps out of range");
-  if (prob->n_grids != 1) return fail(c, MORAY_EINVAL, "the time-stepped evolution takes a single grid");
   if (!(flags & MORAY_FIELDS_ON_DEVICE)) return fail(c, MORAY_EINVAL, "the time-stepped evolution needs device fields");
   if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
   moray_status st = validate(c, *prob, 0);
   if (st != MORAY_OK) return st;
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
-  const moray_grid& G = prob->grids[0];
-  const long long n = (long long)G.nx * G.ny * G.nz;
+  UpdateGrids U;
+  if ((st = update_grids(c, *prob, U)) != MORAY_OK) return st;
+  const int ng = prob->n_grids;
+  const long long n = U.off.back();
+  const size_t stride = 1 + kEqMaxBlocks;      // one reduction area per grid
   if ((st = ensure(c, c->eq_x, (size_t)n * 8, "evolution iterate")) ||
       (st = ensure(c, c->eq_kph, (size_t)n * 8, "evolution rates")) ||
       (st = ensure(c, c->eq_heat, (size_t)n * 8, "evolution rates")) ||
       (st = ensure(c, c->ev_lim, (size_t)n * 8, "evolution step limits")) ||
-      (st = ensure(c, c->eq_dx, (size_t)(1 + kEqMaxBlocks) * 8, "evolution step")))
+      (st = ensure(c, c->eq_dx, (size_t)ng * stride * 8, "evolution step")))
     return st;
   // photon-weighted cross-section of the spectrum: the front test's sigma
   const moray_spectrum& Sp = *prob->spectrum;
   double sigma_bar = 0.0;
   for (int g = 0; g < Sp.n_groups; ++g) sigma_bar += Sp.photon_frac[g] * Sp.sigma_cm2[g];
-  // the caller's x_hi array is the field the trace reads (updated in place, see moray.h)
-  float* x32 = const_cast<float*>(G.x_hi);
+  // the caller's x_hi arrays are the field the trace reads (updated in place, see moray.h)
   double* x64 = (double*)c->eq_x.p;
   double* dmin = (double*)c->eq_dx.p;
   double* lim = (double*)c->ev_lim.p;
-  if (!hip_ok(c, launch_widen(c->stream, c->num_cu, x32, x64, n), "evolution start")) return MORAY_EDEVICE;
+  const unsigned char* skip = ng > 1 ? (const unsigned char*)c->eq_skip.p : nullptr;
+  for (int q = 0; q < ng; ++q)
+    if (!hip_ok(c, launch_widen(c->stream, c->num_cu, prob->grids[q].x_hi, x64 + U.off[q], U.off[q + 1] - U.off[q]),
+                "evolution start"))
+      return MORAY_EDEVICE;
   moray_result mid{};
   mid.k_ph = (double*)c->eq_kph.p;
   mid.heating = (double*)c->eq_heat.p;
   const unsigned mid_flags = flags | MORAY_OUT_ON_DEVICE;
+  std::vector<double> gmin(ng);
   double t = 0.0, dt_prev = 0.0;
   int k = 0;
   while (t < ep->t_end && k < ep->max_steps) {
     if ((st = moray_trace(c, prob, 1, mid_flags, &mid)) != MORAY_OK) return st;
-    double dt = 0.0;
-    if (!hip_ok(c, launch_step_limit(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, G.nx, G.ny, G.nz, ep->alpha_b,
-                                     sigma_bar, G.dx_cm, ep->eps_ion, ep->tau_front, ep->dt_max, lim, dmin),
-                "evolution step") ||
-        !hip_ok(c, hipMemcpyAsync(&dt, dmin, 8, hipMemcpyDeviceToHost, c->stream), "copy") ||
-        !hip_ok(c, hipStreamSynchronize(c->stream), "synchronize"))
-      return MORAY_EDEVICE;
+    // each grid's limits, smoothed within the grid; the step is the smallest
+    for (int q = 0; q < ng; ++q) {
+      const moray_grid& G = prob->grids[q];
+      if (!hip_ok(c, launch_step_limit(c->stream, c->num_cu, mid.k_ph + U.off[q], G.n_h, x64 + U.off[q], G.nx, G.ny,
+                                       G.nz, ep->alpha_b, sigma_bar, G.dx_cm, ep->eps_ion, ep->tau_front, ep->dt_max,
+                                       q == 0 ? skip : nullptr, lim + U.off[q], dmin + q * stride),
+                  "evolution step") ||
+          !hip_ok(c, hipMemcpyAsync(&gmin[q], dmin + q * stride, 8, hipMemcpyDeviceToHost, c->stream), "copy"))
+        return MORAY_EDEVICE;
+    }
+    if (!hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")) return MORAY_EDEVICE;
+    double dt = *std::min_element(gmin.begin(), gmin.end());
     if (k > 0) dt = std::min(dt, 2.0 * dt_prev);          // Eq. dtchange
     dt = std::min(dt, std::min(ep->dt_max, ep->t_end - t));
-    if (!hip_ok(c, launch_evolve_update(c->stream, c->num_cu, mid.k_ph, G.n_h, x64, x32, n, ep->alpha_b, dt),
-                "evolution update"))
-      return MORAY_EDEVICE;
+    for (int q = 0; q < ng; ++q) {
+      const moray_grid& G = prob->grids[q];
+      if (!hip_ok(c, launch_evolve_update(c->stream, c->num_cu, mid.k_ph + U.off[q], G.n_h, x64 + U.off[q],
+                                          const_cast<float*>(G.x_hi), U.off[q + 1] - U.off[q], ep->alpha_b, dt,
+                                          q == 0 ? skip : nullptr),
+                  "evolution update"))
+        return MORAY_EDEVICE;
+    }
     t += dt;
     dt_prev = dt;
     if (dt_steps) dt_steps[k] = dt;

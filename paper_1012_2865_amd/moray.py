@@ -337,6 +337,24 @@ def moray_autotune(ctx, problems: Sequence, max_trials: int = 0) -> dict:
     return {name: getattr(r, name) for name, _ in TuneResult._fields_}
 
 
+def _x64_buffer(problem):
+    """Flat float64 device buffer for the iterate of every grid, in grid order."""
+    import torch
+    return torch.empty(sum(int(g.n_h.numel()) for g in problem.grids), dtype=torch.float64, device="cuda")
+
+
+def _x64_views(problem, x64):
+    """The iterate shaped like the grid (single grid) or one view per grid."""
+    if x64 is None:
+        return None
+    views, o = [], 0
+    for g in problem.grids:
+        m = int(g.n_h.numel())
+        views.append(x64[o:o + m].view(tuple(g.n_h.shape)))
+        o += m
+    return views[0] if len(views) == 1 else views
+
+
 def moray_equilibrate(ctx, problem, alpha_b: float = ALPHA_B, damping: float = 0.5, tol: float = 1e-6,
                       max_iter: int = 300, out_on_device: bool = True, want_escaped_sg: bool = False,
                       want_x64: bool = False):
@@ -346,17 +364,14 @@ def moray_equilibrate(ctx, problem, alpha_b: float = ALPHA_B, damping: float = 0
     as a torch tensor or None)."""
     lib = load_library()
     cprobs, results, keep, outs, flags = _marshal([problem], out_on_device, want_escaped_sg)
-    x64 = None
-    if want_x64:
-        import torch
-        x64 = torch.empty(problem.grids[0].n_h.shape, dtype=torch.float64, device="cuda")
+    x64 = _x64_buffer(problem) if want_x64 else None
     it = ctypes.c_int(0)
     ep = EquilibriumParams(float(alpha_b), float(damping), float(tol), int(max_iter))
     rc = lib.moray_equilibrate(ctx, cprobs, flags, ctypes.byref(ep), x64.data_ptr() if x64 is not None else None,
                                results, ctypes.byref(it))
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
-    return _unpack(results, outs, want_escaped_sg)[0], it.value, x64
+    return _unpack(results, outs, want_escaped_sg)[0], it.value, _x64_views(problem, x64)
 
 
 def moray_evolve(ctx, problem, t_end: float, eps_ion: float = 0.1, tau_front: float = 0.5,
@@ -370,10 +385,7 @@ def moray_evolve(ctx, problem, t_end: float, eps_ion: float = 0.1, tau_front: fl
     tensor or None, numpy array of the steps' dt or None)."""
     lib = load_library()
     cprobs, results, keep, outs, flags = _marshal([problem], out_on_device, want_escaped_sg)
-    x64 = None
-    if want_x64:
-        import torch
-        x64 = torch.empty(problem.grids[0].n_h.shape, dtype=torch.float64, device="cuda")
+    x64 = _x64_buffer(problem) if want_x64 else None
     dts = np.zeros(max(1, int(max_steps)), dtype=np.float64) if want_dts else None
     steps, t = ctypes.c_int(0), ctypes.c_double(0.0)
     ep = EvolveParams(float(alpha_b), float(eps_ion), float(tau_front), float(t_end if dt_max is None else dt_max),
@@ -383,7 +395,7 @@ def moray_evolve(ctx, problem, t_end: float, eps_ion: float = 0.1, tau_front: fl
                           dts.ctypes.data_as(ctypes.POINTER(ctypes.c_double)) if dts is not None else None)
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
-    return (_unpack(results, outs, want_escaped_sg)[0], steps.value, t.value, x64,
+    return (_unpack(results, outs, want_escaped_sg)[0], steps.value, t.value, _x64_views(problem, x64),
             dts[:steps.value].copy() if dts is not None else None)
 
 

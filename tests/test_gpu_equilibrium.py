@@ -11,8 +11,12 @@ radius (Eq. Rstr), which pins both independently:
 * both: the x = 0.5 front at R_s = (3 Ndot / (4 pi alpha_B n_H^2))^(1/3)
   within a cell, and total recombinations equal to the photons absorbed
   (emitted - escaped - truncated) to 1e-4 in equilibrium;
-* settings out of range, several grids or host fields are rejected and the
-  field is left as it was.
+* a root grid with a refined child around the source: the same comparison
+  with the harness on every grid, the root cells under the child keep their
+  neutral fraction, and the recombination balance holds over the cells that
+  carry the field (the child's and the uncovered root cells);
+* settings out of range or host fields are rejected and the field is left as
+  it was.
 """
 import math
 
@@ -100,15 +104,58 @@ def test_equilibrium_rejects_bad_settings_and_leaves_the_field():
             with pytest.raises(M.MorayError) as e:
                 M.moray_equilibrate(ctx, pd, **kw)
             assert e.value.status == M.MORAY_EINVAL, kw
-        two = W.lognormal_problem(99, 9, 24, 1)
-        two.grids.append(W.Grid(n_h=np.full((8, 8, 8), 1e-2, np.float32), x_hi=np.ones((8, 8, 8), np.float32),
-                                dx_cm=two.grids[0].dx_cm / 2, parent=0, offset=(4, 4, 4)))
-        with pytest.raises(M.MorayError) as e:
-            M.moray_equilibrate(ctx, M.problem_to_device(two))
-        assert e.value.status == M.MORAY_EINVAL
         with pytest.raises(M.MorayError) as e:
             M.moray_equilibrate(ctx, p)                   # host fields
         assert e.value.status == M.MORAY_EINVAL
     finally:
         M.moray_free(ctx)
     assert torch.equal(pd.grids[0].x_hi, before)
+
+
+def _nested_problem():
+    # the Stromgren box with a 2x-refined child holding the source
+    p = _stromgren_problem()
+    g = p.grids[0]
+    p.grids.append(W.Grid(n_h=np.full((16, 16, 16), float(g.n_h[0, 0, 0]), np.float32),
+                          x_hi=np.ones((16, 16, 16), np.float32), dx_cm=g.dx_cm / 2, parent=0, offset=(12, 12, 12)))
+    return p
+
+
+@pytest.fixture(scope="module")
+def nested_harness():
+    p = _nested_problem()
+    xs, res, iters = E.iterate(p, tol=1e-6, max_iter=300)
+    return p, xs, res, iters
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_nested_equilibrium_matches_the_oracle_harness(nested_harness, precision):
+    p, xs_ref, res_ref, it_ref = nested_harness
+    pd = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        res, iters, x64 = M.moray_equilibrate(ctx, pd, tol=1e-6, max_iter=300, want_x64=True)
+    finally:
+        M.moray_free(ctx)
+    xs = [v.cpu().numpy() for v in x64]
+    dx = max(float(np.max(np.abs(a - b))) for a, b in zip(xs, xs_ref))
+    print(f"[nested, precision {precision}] updates {iters} (harness {it_ref}), max |x - x_ref| {dx:.2e}",
+          flush=True)
+    covered = E.covered_root_cells(p)
+    assert np.all(xs[0][covered] == 1.0)
+    rec = 0.0
+    for q, g in enumerate(p.grids):
+        assert np.array_equal(pd.grids[q].x_hi.cpu().numpy(), xs[q].astype(np.float32))
+        r = E.ALPHA_B * g.n_h.astype(np.float64) ** 2 * (1.0 - xs[q]) ** 2 * g.dx_cm ** 3
+        rec += float(np.sum(r[~covered] if q == 0 else r))
+    assert rec == pytest.approx(res["emitted"] - res["escaped"] - res["truncated"], rel=1e-4)
+    if precision == M.MORAY_FP64:
+        assert iters == it_ref
+        assert dx <= 1e-8
+        for q in range(2):
+            k, k_ref = res["k_ph"][q].cpu().numpy(), res_ref["k_ph"][q]
+            m = k_ref > 1e-6 * k_ref.max()
+            assert float(np.max(np.abs(k[m] - k_ref[m]) / k_ref[m])) <= 1e-9
+    else:
+        assert abs(iters - it_ref) <= 3
+        assert dx <= 1e-4

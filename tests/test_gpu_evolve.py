@@ -14,8 +14,11 @@ around the FP64 oracle trace, and against the Test 1 front radius of section
   of R_s (1 - e^{-t/t_rec})^{1/3} at 30 Myr and 4 % at 500 Myr, where the
   partly ionised front cells (fewer recombinations than the sharp front of
   the analytic model) hold it a little outside;
-* settings out of range, several grids or host fields are rejected and the
-  field is left as it was.
+* a root grid with a refined child around the source, the front crossing
+  the child's faces: the same comparison with the harness on every grid, and
+  the root cells under the child keep their neutral fraction;
+* settings out of range or host fields are rejected and the field is left as
+  it was.
 """
 import math
 
@@ -119,15 +122,58 @@ def test_evolution_rejects_bad_settings_and_leaves_the_field():
             with pytest.raises(M.MorayError) as e:
                 M.moray_evolve(ctx, pd, t_end, dt_max=1e13)
             assert e.value.status == M.MORAY_EINVAL
-        two = W.lognormal_problem(99, 9, 24, 1)
-        two.grids.append(W.Grid(n_h=np.full((8, 8, 8), 1e-2, np.float32), x_hi=np.ones((8, 8, 8), np.float32),
-                                dx_cm=two.grids[0].dx_cm / 2, parent=0, offset=(4, 4, 4)))
-        with pytest.raises(M.MorayError) as e:
-            M.moray_evolve(ctx, M.problem_to_device(two), T_REC)
-        assert e.value.status == M.MORAY_EINVAL
         with pytest.raises(M.MorayError) as e:
             M.moray_evolve(ctx, p, T_REC)                        # host fields
         assert e.value.status == M.MORAY_EINVAL
     finally:
         M.moray_free(ctx)
     assert torch.equal(pd.grids[0].x_hi, before)
+
+
+def _nested_test1():
+    # Test 1 gas on 16^3 with the source at the box centre inside a
+    # 2x-refined child of 8^3 cells (4 root cells a side)
+    box = 6.6 * W.KPC_CM
+    g = W.uniform_grid(16, box / 16, 1e-3, 1.0 - 1.2e-3)
+    child = W.Grid(n_h=np.full((8, 8, 8), 1e-3, np.float32), x_hi=np.full((8, 8, 8), 1.0 - 1.2e-3, np.float32),
+                   dx_cm=box / 32, parent=0, offset=(6, 6, 6))
+    return W.Problem([g, child], np.array([[8.0, 8.0, 8.0, 5e48]]), W.hydrogen_spectrum([13.6]), W.Params())
+
+
+@pytest.fixture(scope="module")
+def nested_harness():
+    p = _nested_test1()
+    xs, res, steps, t, dts = EV.evolve(p, 0.05 * T_REC, eps=0.1, dt_max=T_REC / 400)
+    return p, xs, res, steps, t, np.array(dts)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_nested_evolution_matches_the_oracle_harness(nested_harness, precision):
+    p, xs_ref, res_ref, steps_ref, t_ref, dts_ref = nested_harness
+    pd = M.problem_to_device(p)
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        res, steps, t, x64, dts = M.moray_evolve(ctx, pd, 0.05 * T_REC, eps_ion=0.1, dt_max=T_REC / 400,
+                                                  want_x64=True, want_dts=True)
+    finally:
+        M.moray_free(ctx)
+    xs = [v.cpu().numpy() for v in x64]
+    dx = max(float(np.max(np.abs(a - b))) for a, b in zip(xs, xs_ref))
+    m = min(len(dts), len(dts_ref))
+    ddt = float(np.max(np.abs(dts[:m] / dts_ref[:m] - 1.0)))
+    print(f"[nested, precision {precision}] steps {steps} (harness {steps_ref}), max dt rel {ddt:.2e}, "
+          f"max |x - x_ref| {dx:.2e}, child min x {xs[1].min():.3e}", flush=True)
+    assert t == pytest.approx(t_ref, rel=1e-12)
+    covered = EV.covered_root_cells(p)
+    assert np.all(xs[0][covered] == np.float64(np.float32(1.0 - 1.2e-3)))
+    assert xs[1].min() < 0.5 and xs[0][~covered].min() < 0.5        # the front has left the child
+    for q in range(2):
+        assert np.array_equal(pd.grids[q].x_hi.cpu().numpy(), xs[q].astype(np.float32))
+    if precision == M.MORAY_FP64:
+        assert steps == steps_ref
+        assert ddt <= 1e-9
+        assert dx <= 1e-8
+    else:
+        assert abs(steps - steps_ref) <= 2
+        assert ddt <= 1e-3
+        assert dx <= 2e-3
