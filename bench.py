@@ -14,7 +14,8 @@ it, and so are the 64-grid batched workload and a serving run.
   python bench.py [--steps K] [--warmup W] [--workload c1|c2]
   python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
   python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only | --td-only
-  python bench.py --counter-pass            (under rocprofv3 --pmc)
+  python bench.py --counter-pass [--counter-variant plain|radpres|td]   (under rocprofv3 --pmc)
+  python bench.py --read-atomics ATOMIC_DIR LAUNCHES
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
   python bench.py --write-atomics ATOMIC_DIR LAUNCHES
 
@@ -139,18 +140,29 @@ def _traffic(workload, precision):
     return rec["per_launch_bytes"][key]
 
 
-def _counter_pass(workload):
+def _counter_pass(workload, variant="plain"):
     """One warm-up and one measured fp32 trace of the workload, then a 1 GiB
     device-to-device copy whose counter readings calibrate FETCH_SIZE and
-    WRITE_SIZE. Meant to run under `rocprofv3 --pmc`."""
+    WRITE_SIZE. Meant to run under `rocprofv3 --pmc`. The variant "radpres"
+    traces with the radiation-pressure sums; "td" runs six time-dependent
+    steps (c dt_P = 32 cells), the last of which is the measured one."""
     import torch
     from paper_1012_2865_amd import moray as M
     problems, config = _workload(workload)
     dev = [M.problem_to_device(p) for p in problems]
     ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
     try:
-        M.moray_trace(ctx, dev)
-        res = M.moray_trace(ctx, dev)
+        if variant == "td":
+            td = M.moray_td_create(ctx, dev[0], 32.0, 1 << 25)
+            try:
+                for _ in range(6):
+                    res = [M.moray_td_step(ctx, td, dev[0])[0]]
+            finally:
+                M.moray_td_free(ctx, td)
+        else:
+            accel = variant == "radpres"
+            M.moray_trace(ctx, dev, want_accel=accel)
+            res = M.moray_trace(ctx, dev, want_accel=accel)
     finally:
         M.moray_free(ctx)
     a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda")
@@ -159,7 +171,8 @@ def _counter_pass(workload):
     b.copy_(a)
     torch.cuda.synchronize()
     peaks = _device_peaks()     # its scattered-atomics kernel calibrates the atomic counter
-    print(json.dumps({"counter_pass": config["workload"], "segments": sum(r["segments"] for r in res),
+    print(json.dumps({"counter_pass": config["workload"], "variant": variant,
+                      "segments": sum(r["segments"] for r in res),
                       "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES,
                       "peaks": peaks}), flush=True)
 
@@ -205,6 +218,33 @@ def _write_traffic(fetch_dir, write_dir, workload, launches):
     with open(TRAFFIC_FILE, "w") as f:
         json.dump(rec, f, indent=1)
     print(json.dumps(out, indent=1))
+
+
+def _atomic_calibration(atomic_dir):
+    """Atomics per count of TCC_EA0_ATOMIC_sum, from the microbenchmark's
+    scattered-atomics dispatch (64 float64 atomics per thread of its grid)."""
+    import csv
+    import glob
+    scattered = [v for k, v in _read_counter_csv(atomic_dir, "TCC_EA0_ATOMIC_sum") if "atomics_scattered" in k]
+    grid = 0
+    for f in glob.glob(os.path.join(atomic_dir, "**", "*counter_collection.csv"), recursive=True):
+        for r in csv.DictReader(open(f)):
+            if "atomics_scattered" in r["Kernel_Name"]:
+                grid = int(r["Grid_Size"])
+    known = grid * 64
+    return (known / scattered[-1] if (scattered and known) else 1.0), (scattered[-1] if scattered else None), known
+
+
+def _read_atomics(atomic_dir, launches):
+    """Float64 atomics per trace-kernel launch over the last `launches`
+    trace dispatches of a TCC_EA0_ATOMIC_sum pass (no record is written)."""
+    trace = [v for k, v in _read_counter_csv(atomic_dir, "TCC_EA0_ATOMIC_sum") if "trace_level_kernel" in k]
+    if len(trace) < launches:
+        raise SystemExit(f"{atomic_dir}: {len(trace)} trace dispatches, expected at least {launches}")
+    factor, _, _ = _atomic_calibration(atomic_dir)
+    last = trace[len(trace) - launches:]
+    return {"atomics_per_trace": sum(last) * factor, "per_launch": [v * factor for v in last],
+            "atomics_per_count": factor}
 
 
 def _write_atomics(atomic_dir, workload, launches):
@@ -570,6 +610,11 @@ def main():
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
+    ap.add_argument("--counter-variant", choices=("plain", "radpres", "td"), default="plain",
+                    help="with --counter-pass: trace with radiation pressure, or time-dependent steps")
+    ap.add_argument("--read-atomics", nargs=2, metavar=("ATOMIC_DIR", "LAUNCHES"),
+                    help="host only: print the float64 atomics per launch of the last LAUNCHES trace "
+                         "dispatches of a TCC_EA0_ATOMIC_sum pass, calibrated like --write-atomics")
     ap.add_argument("--write-traffic", nargs=3, metavar=("FETCH_DIR", "WRITE_DIR", "LAUNCHES"),
                     help="host only: turn FETCH_SIZE / WRITE_SIZE pass folders into the traffic record")
     ap.add_argument("--write-atomics", nargs=2, metavar=("ATOMIC_DIR", "LAUNCHES"),
@@ -581,13 +626,16 @@ def main():
     if args.write_atomics:
         _write_atomics(args.write_atomics[0], args.workload, int(args.write_atomics[1]))
         return
+    if args.read_atomics:
+        print(json.dumps(_read_atomics(args.read_atomics[0], int(args.read_atomics[1]))))
+        return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only (this tracer shards by request or by source; "
               f"--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
     if args.counter_pass:
-        _counter_pass(args.workload)
+        _counter_pass(args.workload, args.counter_variant)
         return
     import torch
     from paper_1012_2865_amd import moray as M

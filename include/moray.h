@@ -285,7 +285,9 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
  * offsets, source and group counts and level_init; its fields may change from
  * step to step).
  * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (1024 to
- * 2^34) bounds the rays in flight and each level's queue; the state holds
+ * 2^34) bounds the rays in flight, with up to 63 empty records per wave of
+ * each level launch (waves reserve the records of halted rays 64 at a time),
+ * and each level's queue; the state holds
  * about 144 bytes of device memory per pool ray (two pools of 32 B, two
  * level queues of 28 B and the 24 B of sort buffers that order the rays in
  * flight, the latter only below 2^32 rays). The covering factor is

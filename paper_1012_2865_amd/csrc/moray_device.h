@@ -13,6 +13,12 @@ constexpr int kTraceBlock = 256;
 constexpr int kFinalBlock = 256;
 constexpr int kFinalCellsPerThread = 4;
 constexpr unsigned long long kReserveMax = 256;   // next-level queue slots a wave reserves per atomic
+// Time-dependent rays: a wave reserves the halt list's records in blocks of
+// kHaltBlock; the records of its last block that it does not fill are empty,
+// with the level kHaltHole (above every HEALPix level, so they sort last).
+constexpr int kHaltBlock = 64;
+constexpr int kHaltHole = 31;
+static_assert(kLevels <= kHaltHole, "empty halt records need a level above every real one");
 constexpr uint32_t kNoTree = 0xffffffffu;      // tree index of an empty queue slot
 constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries

@@ -945,6 +945,9 @@ void trace_level_kernel(TraceArgs<R> a) {
   unsigned long long w_next = 0, w_end = 0, w_nch = 0, w_slo = 0;
   int w_seg = home;
   bool drained = false;
+  // time-dependent rays: the wave's reserved block [h_next, h_end) of the
+  // halt list, and the rays it halted in this launch
+  unsigned long long h_next = 0, h_end = 0, h_count = 0;
 
   for (;;) {
     if (ended >= 0) {
@@ -1135,17 +1138,22 @@ void trace_level_kernel(TraceArgs<R> a) {
       }
     }
     if constexpr (HALT) {
-      // halted rays of the wave take consecutive records of the halt list
+      // halted rays of the wave take consecutive records of its reserved
+      // block of the halt list, and of a new block (one atomic per
+      // kHaltBlock records) once that is full: a counter every wave of the
+      // device shares is not touched at every halt
       const unsigned long long hm = __ballot(halt);
       if (hm) {
-        unsigned long long base = 0;
-        if (lane == 0) {
-          base = atomicAdd(&a.ctr->halt_count, (unsigned long long)__popcll(hm));
-          atomicAdd(&a.ctr->halt_levels[a.gen], (unsigned long long)__popcll(hm));
+        const unsigned long long n = (unsigned long long)__popcll(hm);
+        const unsigned long long room = h_end - h_next;
+        unsigned long long nb = 0;
+        if (n > room) {
+          if (lane == 0) nb = atomicAdd(&a.ctr->halt_count, (unsigned long long)kHaltBlock);
+          nb = bcast64(nb, 0);
         }
-        base = bcast64(base, 0);
         if (halt) {
-          const unsigned long long i = base + __popcll(hm & below);
+          const unsigned long long rank = (unsigned long long)__popcll(hm & below);
+          const unsigned long long i = rank < room ? h_next + rank : nb + (rank - room);
           if (i < a.halt_cap) {
             a.halt.pix[i] = L.pix;
             a.halt.sg[i] = L.sg;
@@ -1158,6 +1166,13 @@ void trace_level_kernel(TraceArgs<R> a) {
           ended = 3;
           active = false;
         }
+        if (n > room) {
+          h_next = nb + (n - room);
+          h_end = nb + (unsigned long long)kHaltBlock;
+        } else {
+          h_next += n;
+        }
+        h_count += n;
       }
     }
     cache.add(a.acc, dkey, dval, dep, lane);
@@ -1185,6 +1200,19 @@ void trace_level_kernel(TraceArgs<R> a) {
   if (stage.count) stage.write(a, home, lane);
   cache.flush(a.acc, lane);
   if (ended >= 0) tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
+  if constexpr (HALT) {
+    // the unfilled rest of the wave's last block: empty records (no photons,
+    // a level above every real one); the level's count once per wave
+    for (unsigned long long i = h_next + lane; i < h_end; i += kWave)
+      if (i < a.halt_cap) {
+        a.halt.pix[i] = 0;
+        a.halt.sg[i] = 0;
+        a.halt.r[i] = 0.0;
+        a.halt.P[i] = 0.0;
+        a.halt_lev[i] = kHaltHole;
+      }
+    if (lane == 0 && h_count) atomicAdd(&a.ctr->halt_levels[a.gen], h_count);
+  }
   // unused slots of the wave's last reserved block become empty slots
   for (unsigned long long i = stage.o_next + lane; i < stage.o_end; i += 64)
     if (i < a.seg_cap) a.out.sg[(unsigned long long)home * a.seg_cap + i] = kNoTree;

@@ -402,7 +402,9 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   for (size_t b = 0; b < t->fb.size(); ++b) Rr.absorbed += hpart[b];
   // the photons the halted rays hold, summed over the halt list
   double h = 0.0;
-  const unsigned long long n_held = hctr->halt_count;
+  // the halt list's records (empty ones, which waves reserved and did not
+  // fill, hold no photons); records beyond the pool were never written
+  const unsigned long long n_held = std::min<unsigned long long>(hctr->halt_count, t->cap);
   if (n_held) {
     const int nb = (int)std::min<size_t>(t->fb.size(), 1024);
     if (!hip_ok(c, launch_sum_blocks(s, nb, (const double*)t->P[1 - t->cur].p, n_held, (double*)t->partial.p),
@@ -437,7 +439,7 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   Rr.t_admit = Rr.t_done = 0.0;
   Rr.from_graph = 0;
   // the halted rays are the next step's rays in flight
-  t->n_in = hctr->halt_count;
+  t->n_in = n_held;
   std::memcpy(t->lev_in, hctr->halt_levels, sizeof t->lev_in);
   t->cur = 1 - t->cur;
   t->step++;
