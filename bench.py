@@ -17,7 +17,7 @@ it, and so are the 64-grid batched workload and a serving run.
   python bench.py --counter-pass [--counter-variant plain|radpres|td]   (under rocprofv3 --pmc)
   python bench.py --read-atomics ATOMIC_DIR LAUNCHES
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
-  python bench.py --write-atomics ATOMIC_DIR LAUNCHES
+  python bench.py --write-atomics ATOMIC_DIR LAUNCHES [--counter-variant radpres|td]
 
 Prints one JSON line.
 """
@@ -247,7 +247,7 @@ def _read_atomics(atomic_dir, launches):
             "atomics_per_count": factor}
 
 
-def _write_atomics(atomic_dir, workload, launches):
+def _write_atomics(atomic_dir, workload, launches, variant="plain"):
     """Float64 atomics per trace-kernel launch from a TCC_EA0_ATOMIC_sum pass.
     The microbenchmark's timed scattered-atomics dispatch (64 atomics per
     thread of its grid) calibrates the counter."""
@@ -270,7 +270,7 @@ def _write_atomics(atomic_dir, workload, launches):
     sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
     if rec.get("kernel_sha256") != sha:
         raise SystemExit("the traffic record belongs to another kernel source; write the traffic first")
-    key = f"{workload}/fp32"
+    key = f"{workload}/fp32" if variant == "plain" else f"{workload}/fp32/{variant}"
     rec.setdefault("atomics_per_launch", {})[key] = per_launch
     rec.setdefault("detail", {}).setdefault(key, {})["atomics"] = {
         "counter_per_launch": sum(trace[len(trace) - launches:]) / launches,
@@ -624,7 +624,7 @@ def main():
         _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]))
         return
     if args.write_atomics:
-        _write_atomics(args.write_atomics[0], args.workload, int(args.write_atomics[1]))
+        _write_atomics(args.write_atomics[0], args.workload, int(args.write_atomics[1]), args.counter_variant)
         return
     if args.read_atomics:
         print(json.dumps(_read_atomics(args.read_atomics[0], int(args.read_atomics[1]))))
@@ -746,6 +746,21 @@ def main():
         extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
         print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
               file=sys.stderr, flush=True)
+
+    # the radiation-pressure trace and the time-dependent step against the
+    # same scattered-atomic peak (their counts come from their own counter passes)
+    if peaks:
+        for name, variant in (("radpres", "radpres"), ("td_rays", "td")):
+            ob = extras.get(name)
+            apv = _atomics_per_launch(args.workload, "fp32/" + variant)
+            if not ob or not apv:
+                continue
+            ms = ob["ms_per_step"][-1] if isinstance(ob["ms_per_step"], list) else ob["ms_per_step"]
+            segs = ob["segments_per_step"][-1] if name == "td_rays" else ob["segments_per_s"] * ms * 1e-3
+            per_step = apv * launches        # the same ten level launches as the plain trace
+            ob["atomics"] = {"unit": "float64 atomics/s", "per_step": per_step, "per_segment": per_step / segs,
+                             "achieved": per_step / (ms * 1e-3), "peak": peaks["atomics_scattered"],
+                             "frac": per_step / (ms * 1e-3) / peaks["atomics_scattered"]}
 
     out = {"metric": METRIC, "value": seg32 / s32, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": s32 * 1e3, "higher_is_better": True, "scaling": "weak",
