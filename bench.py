@@ -292,10 +292,11 @@ def _atomics_per_launch(workload, precision):
     return rec.get("atomics_per_launch", {}).get(f"{workload}/{precision}")
 
 
-def _equilibrium_c1(M, updates=20):
+def _equilibrium_c1(M, updates=20, oracle_threads=0):
     """Photo-ionisation equilibrium iteration (moray_equilibrate) on the 128^3
     workload from neutral gas: `updates` damped updates, each a full trace plus
-    the per-cell update, then the final trace."""
+    the per-cell update, then the final trace. With oracle_threads, the
+    oracle's harness is timed beside it on the first two updates."""
     import numpy as np
     import torch
     from paper_1012_2865_amd import workloads as W
@@ -307,15 +308,30 @@ def _equilibrium_c1(M, updates=20):
         pd = M.problem_to_device(p)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        M.moray_equilibrate(ctx, pd, tol=1e-30, max_iter=2)
+        torch.cuda.synchronize()
+        dt2 = time.perf_counter() - t0
+        pd = M.problem_to_device(p)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         res, done, _ = M.moray_equilibrate(ctx, pd, tol=1e-30, max_iter=updates)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         x = pd.grids[0].x_hi
     finally:
         M.moray_free(ctx)
-    return {"workload": "lognormal128_16src_4grp from neutral gas", "updates": done, "ms_total": dt * 1e3,
-            "ms_per_trace": dt * 1e3 / (done + 1), "segments_final_trace": res["segments"],
-            "ionised_fraction_final": float(1.0 - x.double().mean()), "dtype": "f32+f64acc"}
+    out = {"workload": "lognormal128_16src_4grp from neutral gas", "updates": done, "ms_total": dt * 1e3,
+           "ms_per_trace": dt * 1e3 / (done + 1), "segments_final_trace": res["segments"],
+           "ionised_fraction_final": float(1.0 - x.double().mean()), "dtype": "f32+f64acc"}
+    if oracle_threads:
+        from oracle import equilibrium as E
+        t0 = time.perf_counter()
+        E.iterate(p, tol=1e-30, max_iter=2, n_threads=oracle_threads)
+        dto = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": dto / 2.0, "unit": "s per update (trace + update)", "cores": oracle_threads,
+                             "kind": "oracle", "sample": f"the first two updates from neutral gas in {dto:.1f} s",
+                             "gpu_same_sample_s_per_update": dt2 / 3.0, "gpu_speedup": dto / 2.0 / (dt2 / 3.0)}
+    return out
 
 
 def _covering_c1(M, steps, oracle_threads=0):
@@ -349,7 +365,7 @@ def _covering_c1(M, steps, oracle_threads=0):
     return out
 
 
-def _evolve_test1(M):
+def _evolve_test1(M, oracle_threads=0):
     """The paper's Test 1 (section 4.1) end to end on the device: a 5e48 ph/s
     source at the corner of a 6.6 kpc, 64^3 box of n_H = 1e-3, evolved for
     500 Myr with moray_evolve (eps_ion = 0.1, steps of at most t_rec / 400),
@@ -372,6 +388,12 @@ def _evolve_test1(M):
         pd = problem()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        _, steps10, _, _, _ = M.moray_evolve(ctx, pd, 10 * myr, dt_max=t_rec / 400)
+        torch.cuda.synchronize()
+        dt10 = time.perf_counter() - t0
+        pd = problem()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
         res, steps, t, x64, _ = M.moray_evolve(ctx, pd, 500 * myr, dt_max=t_rec / 400, want_x64=True)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
@@ -380,8 +402,20 @@ def _evolve_test1(M):
         M.moray_free(ctx)
     r = (6.0 * float(np.sum(1.0 - x)) * (box / n) ** 3 / math.pi) ** (1.0 / 3.0)
     rs = (3.0 * 5e48 / (4.0 * math.pi * alpha * 1e-6)) ** (1.0 / 3.0) * (1.0 - math.exp(-t / t_rec)) ** (1.0 / 3.0)
-    return {"workload": "Test 1 (64^3, 6.6 kpc, 5e48 ph/s) to 500 Myr", "steps": steps, "s_total": dt,
-            "ms_per_step": dt * 1e3 / steps, "front_over_analytic": r / rs, "dtype": "f32+f64acc"}
+    out = {"workload": "Test 1 (64^3, 6.6 kpc, 5e48 ph/s) to 500 Myr", "steps": steps, "s_total": dt,
+           "ms_per_step": dt * 1e3 / steps, "front_over_analytic": r / rs, "dtype": "f32+f64acc"}
+    if oracle_threads:
+        from oracle import evolve as EV
+        g = W.uniform_grid(n, box / n, 1e-3, 1.0 - 1.2e-3)
+        ph = W.Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), W.hydrogen_spectrum([13.6]), W.Params())
+        t0 = time.perf_counter()
+        _, _, osteps, _, _ = EV.evolve(ph, 10 * myr, eps=0.1, dt_max=t_rec / 400, n_threads=oracle_threads)
+        dto = time.perf_counter() - t0
+        out["cpu_oracle"] = {"value": dto * 1e3 / osteps, "unit": "ms per step", "cores": oracle_threads,
+                             "kind": "oracle", "sample": f"the first 10 Myr: {osteps} steps in {dto:.1f} s",
+                             "gpu_same_sample_ms_per_step": dt10 * 1e3 / steps10,
+                             "gpu_speedup": (dto / osteps) / (dt10 / steps10)}
+    return out
 
 
 def _radpres_c1(M, steps, oracle_threads=0):
@@ -727,10 +761,10 @@ def main():
     if not args.no_extras:
         extras["batched_c2"] = _batched_c2(M, max(2, args.steps // 2))
         print(f"# batched c2: {extras['batched_c2']['batched_over_plain']:.2f}x plain fp64", file=sys.stderr, flush=True)
-        extras["equilibrium"] = _equilibrium_c1(M)
+        oth = 0 if args.no_cpu_baseline else args.cpu_threads
+        extras["equilibrium"] = _equilibrium_c1(M, oracle_threads=oth)
         print(f"# equilibrium: {extras['equilibrium']['ms_per_trace']:.2f} ms per trace + update", file=sys.stderr,
               flush=True)
-        oth = 0 if args.no_cpu_baseline else args.cpu_threads
         extras["covering"] = _covering_c1(M, max(2, args.steps // 2), oth)
         print(f"# covering factor: {extras['covering']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['covering']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
@@ -740,7 +774,7 @@ def main():
         extras["td_rays"] = _td_c1(M, oracle=not args.no_cpu_baseline)
         print(f"# time-dependent rays: {extras['td_rays']['segments_per_s_late']:.3e} segments/s", file=sys.stderr,
               flush=True)
-        extras["evolve_test1"] = _evolve_test1(M)
+        extras["evolve_test1"] = _evolve_test1(M, oracle_threads=oth)
         print(f"# Test 1 to 500 Myr: {extras['evolve_test1']['steps']} steps in "
               f"{extras['evolve_test1']['s_total']:.2f} s", file=sys.stderr, flush=True)
         extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
