@@ -6,7 +6,13 @@ its maximum):
 * the covering-factor correction (section 2.3) on the whole workload;
 * the radiation-pressure acceleration (section 2.5.4) on the whole workload;
 * time-dependent rays (section 2.1) on a two-source subset for three steps
-  of c dt_P = 32 cells (the oracle's time-dependent step runs on one thread).
+  of c dt_P = 32 cells (the oracle's time-dependent step runs on one thread);
+* the equilibrium iteration's first two updates from neutral gas on the
+  whole workload, against the oracle's harness: the neutral fraction within
+  1e-4 (mixed) and 1e-8 (float64);
+* Test 1 (section 4.1) at the paper's 64^3 for its first 10 Myr against the
+  oracle's evolution harness: the same steps (float64), every dt within
+  1e-9 (float64) or 1e-3 (mixed), x within 1e-8 or 2e-3.
 """
 import numpy as np
 import pytest
@@ -78,3 +84,49 @@ def test_time_dependent_rays_at_full_size(ctx):
             assert held == pytest.approx(ref["held"], rel=1e-4)
     finally:
         M.moray_td_free(ctx, td)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_equilibrium_updates_at_full_size(precision):
+    from oracle import equilibrium as E
+    p = W.config1()
+    p.grids[0].x_hi = np.ones_like(p.grids[0].x_hi)
+    x_ref, _, _ = E.iterate(p, tol=1e-30, max_iter=2, n_threads=16)
+    pd = M.problem_to_device(p)
+    c = M.moray_init(device=0, precision=precision)
+    try:
+        _, it, x64 = M.moray_equilibrate(c, pd, tol=1e-30, max_iter=2, want_x64=True)
+    finally:
+        M.moray_free(c)
+    dx = float(np.max(np.abs(_np(x64) - x_ref)))
+    print(f"[equilibrium 128^3, precision {precision}] 2 updates: max |x - x_ref| {dx:.2e}", flush=True)
+    assert it == 2
+    assert dx <= (1e-8 if precision == M.MORAY_FP64 else 1e-4)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_test1_first_10_myr_at_full_size(precision):
+    from oracle import evolve as EV
+    n, box = 64, 6.6 * W.KPC_CM
+    t_rec, myr = 1.0 / (M.ALPHA_B * 1e-3), 3.15576e13
+    g = W.uniform_grid(n, box / n, 1e-3, 1.0 - 1.2e-3)
+    p = W.Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), W.hydrogen_spectrum([13.6]), W.Params())
+    x_ref, _, steps_ref, t_ref, dts_ref = EV.evolve(p, 10 * myr, eps=0.1, dt_max=t_rec / 400, n_threads=16)
+    pd = M.problem_to_device(p)
+    c = M.moray_init(device=0, precision=precision)
+    try:
+        _, steps, t, x64, dts = M.moray_evolve(c, pd, 10 * myr, eps_ion=0.1, dt_max=t_rec / 400, want_x64=True,
+                                               want_dts=True)
+    finally:
+        M.moray_free(c)
+    x = _np(x64)
+    m = min(len(dts), len(dts_ref))
+    ddt = float(np.max(np.abs(np.asarray(dts[:m]) / np.asarray(dts_ref[:m]) - 1.0)))
+    dx = float(np.max(np.abs(x - x_ref)))
+    print(f"[Test 1 64^3 10 Myr, precision {precision}] steps {steps} (harness {steps_ref}), max dt rel {ddt:.2e}, "
+          f"max |x - x_ref| {dx:.2e}", flush=True)
+    assert t == pytest.approx(t_ref, rel=1e-12)
+    if precision == M.MORAY_FP64:
+        assert steps == steps_ref and ddt <= 1e-9 and dx <= 1e-8
+    else:
+        assert abs(steps - steps_ref) <= 2 and ddt <= 1e-3 and dx <= 2e-3
