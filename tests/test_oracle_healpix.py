@@ -154,3 +154,64 @@ def test_mirror_symmetries_exact():
     for m in (np.array([-1, 1, 1]), np.array([1, -1, 1]), np.array([1, 1, -1])):
         assert {tuple(x * m) for x in v} == base
     assert {(x[1], x[0], x[2]) for x in v} == base
+
+
+def _ring_of(z: float, ns: int):
+    """Ring index, pixel count and half-step shift of a centre at height z,
+    from the ring heights of the scheme: polar rings i < Ns at
+    z = 1 - i^2 / (3 Ns^2) (mirrored in the south), equatorial rings
+    Ns <= i <= 3 Ns at z = 4/3 - 2 i / (3 Ns). Returns None when z is on no
+    ring."""
+    if abs(z) > 2.0 / 3.0:
+        i = round(math.sqrt(3.0 * ns * ns * (1.0 - abs(z))))
+        if not 1 <= i < ns or abs(1.0 - i * i / (3.0 * ns * ns) - abs(z)) > 4e-16:
+            return None
+        return (i if z > 0 else 4 * ns - i), 4 * i, 1
+    i = round((4.0 / 3.0 - z) * 1.5 * ns)
+    if not ns <= i <= 3 * ns or abs(4.0 / 3.0 - 2.0 * i / (3.0 * ns) - z) > 4e-16:
+        return None
+    return i, 4 * ns, (i - ns + 1) % 2
+
+
+def _sample_pixels(level: int, n: int, seed: int):
+    """Seeded random pixels of a level plus the first and last pixel of every
+    base face and the face's in-face corners."""
+    npface = 4 ** level
+    rng = np.random.default_rng([level, seed])
+    pix = set(int(p) for p in rng.integers(0, 12 * npface, n))
+    ns = 2 ** level
+    for f in range(12):
+        for ix, iy in ((0, 0), (ns - 1, 0), (0, ns - 1), (ns - 1, ns - 1)):
+            pix.add(f * npface + _interleave(ix, iy))
+    return sorted(pix)
+
+
+@pytest.mark.parametrize("level", [10, 11, 12, 13, 14, 15])
+def test_deep_levels_on_rings_and_azimuth_lattice(level):
+    """Sampled pixels of levels 10-15 (where the ring arithmetic needs more
+    than 32 bits from level 14 on): unit length, centre height on a ring of
+    the closed forms, azimuth on that ring's lattice, and the independent
+    angle-to-pixel routine maps every centre back to its pixel."""
+    ns = 2 ** level
+    for p in _sample_pixels(level, 1500, 1):
+        x, y, z = O.pix2vec(level, p)
+        assert abs(math.sqrt(x * x + y * y + z * z) - 1.0) < 4e-16
+        ring = _ring_of(z, ns)
+        assert ring is not None, (level, p, z)
+        _, count, shift = ring
+        phi = math.atan2(y, x) % (2.0 * math.pi)
+        k = phi / ((math.pi / 2.0) / (count // 4)) - 0.5 * shift
+        assert abs(k - round(k)) < 1e-9 * max(1.0, count / 4), (level, p, k)
+        assert ang2pix_nest(ns, z, math.atan2(y, x)) == p
+
+
+@pytest.mark.parametrize("level", [10, 12, 13, 14])
+def test_deep_children_nest_inside_parent(level):
+    npix = 12 * 4 ** level
+    radius = math.sqrt(4 * math.pi / npix)
+    for p in _sample_pixels(level, 300, 2):
+        pv = O.pix2vec(level, p)
+        for k in range(4):
+            cv = O.pix2vec(level + 1, 4 * p + k)
+            assert math.acos(min(1.0, float(np.dot(pv, cv)))) < radius
+            assert ang2pix_nest(2 ** level, cv[2], math.atan2(cv[1], cv[0])) == p
