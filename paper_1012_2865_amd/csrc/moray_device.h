@@ -20,6 +20,7 @@ constexpr int kHaltBlock = 64;
 constexpr int kHaltHole = 31;
 static_assert(kLevels <= kHaltHole, "empty halt records need a level above every real one");
 constexpr uint32_t kNoTree = 0xffffffffu;      // tree index of an empty queue slot
+constexpr int kDropRanges = 16;                // tree ranges one queue filter pass removes (serving)
 constexpr int kSkip = 0, kStarted = 1, kEscaped = 2;
 constexpr int kCacheLog2 = 9;                  // per-wave LDS deposit cache: 512 entries
 constexpr int kCacheEntries = 1 << kCacheLog2;

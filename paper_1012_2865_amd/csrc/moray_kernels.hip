@@ -199,11 +199,14 @@ struct Geom64 {
 // ---------------------------------------------------------------------------
 // Geometry, float32: every plane distance is a pair hi + lo of floats.
 // The source coordinate is split into a 2^-12-lattice part q (so b - q is
-// exact) and a residual e; the reciprocal of the float64 direction into
-// i + j. Then t = (b - q - e)(i + j) = hi + lo, hi = (b-q) i rounded, lo =
-// its exact fma residual + (b-q) j - e i. Chords are differences of such
-// pairs, accurate to ~1e-14 t, so float32 arithmetic places every segment
-// where float64 would.
+// exact) and a residual e, |e| <= 2^-13; the reciprocal of the float64
+// direction into i + j. Then t = (b - q - e)(i + j) = hi + lo, hi = (b-q) i
+// rounded, lo = its exact fma residual + (b-q) j - e i. A pair is within
+// about 2^-36 / |d| cells of the float64 distance (e rounded to float and the
+// dropped e j), so chords, which are differences of pairs, place every
+// segment where float64 would up to that: a plane tie closer than that is a
+// segment of that length in either of two cells. hi alone is not the
+// distance: near the source e i is comparable to it.
 // ---------------------------------------------------------------------------
 // The float path keeps each lane's float64 direction in LDS rather than in
 // registers: it is read only by the rare exact paths (a split test within
@@ -277,7 +280,10 @@ struct Geom32 {
   // a pair resolves distances to ~2^-46 t: anything below 2^-40 t is a plane tie (dr = 0 in float64)
   __device__ bool positive(float dr, int ax) const { return dr > sel3(ax, h0, h1, h2) * 9.094947e-13f; }
   __device__ void advance(int ax) { rh = sel3(ax, h0, h1, h2); rl = sel3(ax, l0, l1, l2); }
-  __device__ float local_u(int ax) const { return sel3(ax, h0, h1, h2) * hloc; }
+  // The split test's distance takes both halves of the pair: the low half
+  // holds the source's off-lattice residual e (t = (b - q - e) / d), which
+  // near the source is not small against the high half.
+  __device__ float local_u(int ax) const { return (sel3(ax, h0, h1, h2) + sel3(ax, l0, l1, l2)) * hloc; }
   __device__ double exit64(int ax) const { return (double)sel3(ax, h0, h1, h2) + (double)sel3(ax, l0, l1, l2); }
   // The exit axis always has a nonzero direction component (an axis with
   // none is at infinity), so its next plane needs no special case; selects
@@ -837,18 +843,24 @@ struct DepositCache<true> {
 };
 
 // Split parents waiting for their children to be written: the children of a
-// stage go to the wave's home segment of the next level's queue in one
-// reservation and coalesced stores (lane c writes child c), four consecutive
-// records per parent.
+// stage go to the wave's current segment of the next level's queue (its home
+// segment at first) through blocks of slots it reserves with one atomic, in
+// coalesced stores (lane c writes child c), four consecutive records per
+// parent. A segment that is full sends the wave on to the next one, so the
+// splits of a few neighbouring pixel ranges (the rays towards a grid's
+// corners, say) can fill one segment without losing children while the
+// queue has room elsewhere; only when every segment is full are children
+// lost (an overflow, which the host answers by tracing in smaller chunks).
 struct SplitStage {
   uint64_t* pix;
   uint32_t* sg;
   double* r;
   double* P;
   int count;                                    // wave-uniform
-  unsigned long long o_next, o_end;             // the wave's reserved slots of its home segment
+  int wseg;                                     // segment of the wave's current reservation
+  unsigned long long o_next, o_end;             // the wave's reserved slots of segment wseg
 
-  __device__ void init() {
+  __device__ void init(int home) {
     __shared__ uint64_t spix[kTraceBlock / kWave][kStageCap];
     __shared__ uint32_t ssg[kTraceBlock / kWave][kStageCap];
     __shared__ double sr[kTraceBlock / kWave][kStageCap];
@@ -856,43 +868,59 @@ struct SplitStage {
     const int wv = threadIdx.x / kWave;
     pix = spix[wv]; sg = ssg[wv]; r = sr[wv]; P = sP[wv];
     count = 0;
+    wseg = home;
     o_next = o_end = 0;
   }
   template <typename R>
-  __device__ void write(const TraceArgs<R>& a, int home, int lane) {
+  __device__ void write(const TraceArgs<R>& a, int lane) {
     __builtin_amdgcn_wave_barrier();
     const unsigned long long need = 4ull * (unsigned long long)count;
-    const unsigned long long rem = o_end - o_next;
-    const unsigned long long grab = need > a.reserve ? need : a.reserve;
-    unsigned long long fresh = 0;
-    if (need > rem) {
-      if (lane == 0) fresh = atomicAdd(&a.ctr->count[a.cout][home], grab);
-      fresh = bcast64(fresh, 0);
-    }
-    const unsigned long long base = (unsigned long long)home * a.seg_cap;
-    for (unsigned long long c = lane; c < need; c += kWave) {
-      const int p = (int)(c >> 2);
-      const unsigned long long d = c < rem ? o_next + c : fresh + (c - rem);
-      const double Pc = 0.25 * P[p];
-      if (d < a.seg_cap) {
-        a.out.pix[base + d] = 4ull * pix[p] + (c & 3);
-        a.out.sg[base + d] = sg[p];
-        a.out.r[base + d] = r[p];
-        a.out.P[base + d] = Pc;
-      } else {
-        atomicOr(&a.ctr->err, kErrOverflow);
-        atomicAdd(&a.ctr->lost_rays, 1ull);
-        unsafeAtomicAdd(&a.ctr->lost_P, Pc);
+    unsigned long long done = 0;
+    int full = 0;                                           // segments found full in this call
+    while (done < need) {
+      if (o_next >= o_end) {
+        const unsigned long long want = need - done;
+        const unsigned long long grab = want > a.reserve ? want : a.reserve;
+        unsigned long long fresh = 0;
+        if (lane == 0) fresh = atomicAdd(&a.ctr->count[a.cout][wseg], grab);
+        fresh = bcast64(fresh, 0);
+        if (fresh >= a.seg_cap) {
+          if (++full >= a.nseg) break;                      // every segment is full
+          wseg = (wseg + 1) & (a.nseg - 1);
+          continue;
+        }
+        o_next = fresh;
+        o_end = fresh + grab < a.seg_cap ? fresh + grab : a.seg_cap;
       }
+      const unsigned long long n = need - done < o_end - o_next ? need - done : o_end - o_next;
+      const unsigned long long base = (unsigned long long)wseg * a.seg_cap + o_next;
+      for (unsigned long long c = lane; c < n; c += kWave) {
+        const unsigned long long k = done + c;
+        const int p = (int)(k >> 2);
+        a.out.pix[base + c] = 4ull * pix[p] + (k & 3);
+        a.out.sg[base + c] = sg[p];
+        a.out.r[base + c] = r[p];
+        a.out.P[base + c] = 0.25 * P[p];
+      }
+      o_next += n;
+      done += n;
     }
-    if (need > rem) {
-      o_next = fresh + (need - rem);
-      o_end = fresh + grab;
-    } else {
-      o_next += need;
+    if (done < need) {
+      for (unsigned long long k = done + lane; k < need; k += kWave) {
+        if (k == done) atomicOr(&a.ctr->err, kErrOverflow);
+        atomicAdd(&a.ctr->lost_rays, 1ull);
+        unsafeAtomicAdd(&a.ctr->lost_P, 0.25 * P[k >> 2]);
+      }
     }
     count = 0;
     __builtin_amdgcn_wave_barrier();
+  }
+  // all lanes of the wave, at its end: the unused slots of its last
+  // reservation become empty slots
+  template <typename R>
+  __device__ void close(const TraceArgs<R>& a, int lane) const {
+    for (unsigned long long i = o_next + lane; i < o_end; i += kWave)
+      a.out.sg[(unsigned long long)wseg * a.seg_cap + i] = kNoTree;
   }
 };
 
@@ -936,7 +964,7 @@ void trace_level_kernel(TraceArgs<R> a) {
   DepositCache<CACHE> cache;
   cache.init(lane);
   SplitStage stage;
-  stage.init();
+  stage.init(home);
   bool active = false;
   unsigned steps = 0;
   L.tree = kNoTree;
@@ -1194,10 +1222,10 @@ void trace_level_kernel(TraceArgs<R> a) {
       }
     }
     // bulk writes, only when a buffer is nearly full
-    if (stage.count >= kStageFlush) stage.write(a, home, lane);
+    if (stage.count >= kStageFlush) stage.write(a, lane);
     if (cache.want_drain()) cache.drain(a.acc, lane);
   }
-  if (stage.count) stage.write(a, home, lane);
+  if (stage.count) stage.write(a, lane);
   cache.flush(a.acc, lane);
   if (ended >= 0) tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
   if constexpr (HALT) {
@@ -1214,8 +1242,7 @@ void trace_level_kernel(TraceArgs<R> a) {
     if (lane == 0 && h_count) atomicAdd(&a.ctr->halt_levels[a.gen], h_count);
   }
   // unused slots of the wave's last reserved block become empty slots
-  for (unsigned long long i = stage.o_next + lane; i < stage.o_end; i += 64)
-    if (i < a.seg_cap) a.out.sg[(unsigned long long)home * a.seg_cap + i] = kNoTree;
+  stage.close(a, lane);
   __syncthreads();
   tally.flush(a.stats);
 }
@@ -1454,6 +1481,29 @@ __global__ __launch_bounds__(256) void prefill_level_kernel(RayQueue pool, const
   }
 }
 
+// Serving: rays of removed problems leave the queue between two launches.
+// Block b walks segment b % nseg (blocks share a segment by their quotient)
+// over its written slots and empties every record whose tree index lies in
+// one of the n ranges [lo[i], hi[i]).
+struct DropRanges {
+  int n;
+  int lo[kDropRanges], hi[kDropRanges];
+};
+
+__global__ __launch_bounds__(256) void drop_trees_kernel(uint32_t* __restrict__ sg, const Counters* __restrict__ ctr,
+                                                         int row, unsigned long long seg_cap, int nseg, DropRanges r) {
+  const int seg = (int)(blockIdx.x % (unsigned)nseg);
+  const unsigned long long part = blockIdx.x / (unsigned)nseg, parts = gridDim.x / (unsigned)nseg;
+  const unsigned long long cnt = ctr->count[row][seg] < seg_cap ? ctr->count[row][seg] : seg_cap;
+  uint32_t* q = sg + (unsigned long long)seg * seg_cap;
+  for (unsigned long long i = part * 256ull + threadIdx.x; i < cnt; i += parts * 256ull) {
+    const uint32_t t = q[i];
+    bool drop = false;
+    for (int k = 0; k < r.n; ++k) drop = drop || ((int)t >= r.lo[k] && (int)t < r.hi[k]);
+    if (t != kNoTree && drop) q[i] = kNoTree;
+  }
+}
+
 // Per-block sums of v[0..n) (the photons the halted rays hold).
 __global__ __launch_bounds__(256) void sum_blocks_kernel(const double* __restrict__ v, unsigned long long n,
                                                          double* __restrict__ part) {
@@ -1473,6 +1523,20 @@ __global__ __launch_bounds__(256) void sum_blocks_kernel(const double* __restric
 
 hipError_t launch_sum_blocks(hipStream_t s, int blocks, const double* v, unsigned long long n, double* part) {
   hipLaunchKernelGGL(sum_blocks_kernel, dim3(blocks), dim3(256), 0, s, v, n, part);
+  return hipGetLastError();
+}
+
+hipError_t launch_drop_trees(hipStream_t s, uint32_t* sg, const Counters* ctr, int row, unsigned long long seg_cap,
+                             int nseg, const int* lo, const int* hi, int n) {
+  if (n <= 0) return hipSuccess;
+  if (n > kDropRanges || nseg < 1) return hipErrorInvalidValue;
+  DropRanges r{};
+  r.n = n;
+  for (int k = 0; k < n; ++k) {
+    r.lo[k] = lo[k];
+    r.hi[k] = hi[k];
+  }
+  hipLaunchKernelGGL(drop_trees_kernel, dim3((unsigned)nseg * 16u), dim3(256), 0, s, sg, ctr, row, seg_cap, nseg, r);
   return hipGetLastError();
 }
 

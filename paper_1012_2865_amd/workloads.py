@@ -11,8 +11,9 @@ Conventions shared by every consumer:
 * A field is a float32 array of shape (nz, ny, nx) in C order, so the linear
   cell index is ``i + nx*(j + ny*k)`` (x fastest).
 * Source positions are in cells of the root grid, measured from the root
-  grid's lower corner, and quantised to multiples of 2**-12 cell so that a
-  cell-plane coordinate minus a source coordinate is exact in float32.
+  grid's lower corner. They are general float64 values drawn uniformly (no
+  lattice): the library accepts any position inside the root grid, and the
+  inputs exercise that.
 * Energies are in eV, cross-sections in cm^2, photon rates in photons/s,
   lengths in cm.
 
@@ -35,7 +36,6 @@ KPC_CM = 1.0e3 * PC_CM
 EV_ERG = 1.602176634e-12           # electron-volt in erg (SI exact value)
 SIGMA_HI_13P6 = 6.3e-18            # HI photo-ionisation cross-section at threshold, cm^2
 E_ION_HI_EV = 13.6                 # hydrogen ionisation energy, eV
-SOURCE_QUANTUM = 2.0 ** -12        # source-coordinate grid, in root cells
 
 
 @dataclass
@@ -100,8 +100,10 @@ def rng_for(cfg: int, item: int, stream: int) -> np.random.Generator:
     return np.random.default_rng(np.random.SeedSequence([cfg, item, stream]))
 
 
-def quantise_positions(x: np.ndarray) -> np.ndarray:
-    return np.floor(np.asarray(x, dtype=np.float64) / SOURCE_QUANTUM) * SOURCE_QUANTUM
+def _below(hi) -> np.ndarray:
+    """The largest float64 below each upper bound (positions stay inside a
+    half-open interval)."""
+    return np.nextafter(np.asarray(hi, dtype=np.float64), -np.inf)
 
 
 def hydrogen_spectrum(energies_ev: Sequence[float], frac: Sequence[float] | None = None) -> Spectrum:
@@ -155,9 +157,8 @@ def random_sources(rng: np.random.Generator, n_src: int, box: Tuple[float, float
     pos = np.empty((n_src, 3))
     for a in range(3):
         pos[:, a] = lo[a] + rng.uniform(0.0, box[a], n_src)
-    pos = quantise_positions(pos)
     for a in range(3):
-        pos[:, a] = np.clip(pos[:, a], lo[a], lo[a] + box[a] - SOURCE_QUANTUM)
+        pos[:, a] = np.clip(pos[:, a], lo[a], _below(lo[a] + box[a]))
     ndot = 10.0 ** rng.uniform(log_ndot[0], log_ndot[1], n_src)
     return np.column_stack([pos, ndot])
 
@@ -297,7 +298,7 @@ def config4(n_clusters: int = 10, per_cluster: int = 100, root_n: int = 256, sub
     inner_lo = lo + sub_root_cells / 4.0
     centres = inner_lo + rng.uniform(0.0, sub_root_cells / 2.0, (n_clusters, 3))
     pos = np.repeat(centres, per_cluster, axis=0) + rng.normal(0.0, 2.0, (n_clusters * per_cluster, 3))
-    pos = quantise_positions(np.clip(pos, lo, lo + sub_root_cells - SOURCE_QUANTUM))
+    pos = np.clip(pos, lo, _below(lo + sub_root_cells))
     ndot = 10.0 ** rng.uniform(48.0, 50.0, n_clusters * per_cluster)
     return Problem([root, sub], np.column_stack([pos, ndot]), hydrogen_spectrum(FOUR_GROUPS_EV),
                    Params(level_max=14), name="nested256+128")

@@ -14,6 +14,7 @@ Bars (written here, derived in the design notes):
 import numpy as np
 import pytest
 
+from checks import check as _check, np_ as _np
 from oracle import oracle as O
 from paper_1012_2865_amd import moray as M
 from paper_1012_2865_amd import workloads as W
@@ -39,48 +40,6 @@ def ctx32():
     c = _ctx(M.MORAY_FP32_ACC64)
     yield c
     M.moray_free(c)
-
-
-def _np(a):
-    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
-
-
-def _field_err(got, want, floor=1e-6):
-    got, want = _np(got).ravel(), np.asarray(want).ravel()
-    mx = want.max()
-    if mx == 0.0:
-        return 0.0, float(np.abs(got).max())
-    m = want > floor * mx
-    rel = float(np.max(np.abs(got[m] - want[m]) / want[m])) if m.any() else 0.0
-    absr = float(np.max(np.abs(got - want)) / mx)
-    return rel, absr
-
-
-def _check(res, ref, rel_tol, name="", fp64=False):
-    T = ref["totals"]
-    worst = 0.0
-    for q in range(len(ref["k_ph"])):
-        for f in ("k_ph", "heating"):
-            rel, absr = _field_err(res[f][q], ref[f][q])
-            worst = max(worst, rel)
-            print(f"[{name}] grid {q} {f}: max rel {rel:.3e} (cells > 1e-6 max), max abs/max {absr:.3e}", flush=True)
-            assert rel <= rel_tol, (name, q, f, rel)
-            assert absr <= max(rel_tol, 1e-6), (name, q, f, absr)
-    bal = res["absorbed"] + res["escaped"] + res["truncated"] - res["emitted"]
-    print(f"[{name}] conservation {bal / res['emitted']:.3e}; segments gpu {res['segments']} oracle {T['segments']}; "
-          f"splits {res['splits']}/{T['splits']}", flush=True)
-    assert abs(bal) <= 1e-9 * res["emitted"]
-    assert res["emitted"] == pytest.approx(T["emitted"], rel=1e-14)
-    assert res["rays_seeded"] + 4 * res["splits"] == res["splits"] + res["rays_escaped"] + res["rays_truncated"]
-    assert res["escaped"] == pytest.approx(T["escaped"], rel=max(rel_tol, 1e-12), abs=1e-12 * T["emitted"])
-    flips = abs(res["splits"] - T["splits"])
-    for k in ("segments", "splits", "rays_escaped", "rays_truncated"):
-        if fp64:
-            assert res[k] == T[k], (k, res[k], T[k])
-        else:
-            # one flipped split decision turns one ray into four
-            assert abs(res[k] - T[k]) <= 1e-5 * T[k] + 2 + 3 * flips, (k, res[k], T[k])
-    return worst
 
 
 def _run(ctx, problems, **kw):

@@ -31,8 +31,10 @@ def test_config1_shape_and_ranges():
     assert g.x_hi.min() >= 0.5 and g.x_hi.max() < 1.0
     assert p.sources.shape == (16, 4)
     assert np.all((p.sources[:, :3] >= 0) & (p.sources[:, :3] < 128))
-    q = p.sources[:, :3] / W.SOURCE_QUANTUM
-    assert np.array_equal(q, np.floor(q))
+    # general float64 positions, not a coarse lattice: no coordinate is a
+    # multiple of 2^-20 cell
+    q = p.sources[:, :3] * 2.0 ** 20
+    assert not np.any(q == np.floor(q))
     assert np.all((p.sources[:, 3] >= 1e48) & (p.sources[:, 3] <= 1e50))
     assert np.allclose(p.spectrum.energy_ev, [13.6, 20, 30, 60])
     np.testing.assert_allclose(p.spectrum.sigma_cm2, 6.3e-18 * (p.spectrum.energy_ev / 13.6) ** -3)
