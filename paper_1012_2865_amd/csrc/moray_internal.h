@@ -26,6 +26,10 @@ hipError_t launch_trace_level_halt(hipStream_t, int, const TraceArgs<R>&, bool c
 hipError_t launch_prefill_level(hipStream_t, int num_cu, const RayQueue& pool, const int* pool_lev,
                                 unsigned long long n_pool, int level, const RayQueue& q, unsigned long long seg_cap,
                                 int nseg, Counters* ctr, int row);
+// Serving: empty the queued rays (counter row `row`, nseg segments) whose
+// tree index lies in one of the n ranges [lo[i], hi[i]) (n <= kDropRanges).
+hipError_t launch_drop_trees(hipStream_t, uint32_t* sg, const Counters* ctr, int row, unsigned long long seg_cap,
+                             int nseg, const int* lo, const int* hi, int n);
 hipError_t launch_sum_blocks(hipStream_t, int blocks, const double* v, unsigned long long n, double* part);
 // moray_td_kernels.hip: the halt list sorted by (level, tree, pixel), and its per-level runs as queue input
 hipError_t td_sort_temp_bytes(unsigned long long cap, size_t* bytes);
@@ -73,6 +77,10 @@ struct moray_ctx {
   int num_cu = 0;
   int blocks_per_cu = 1;
   std::string err = "no error";
+  bool fail_capture_once = false;  // test hook (MORAY_INJECT_CAPTURE_FAILURE=1 at moray_init): the next capture
+                                   // of a launch sequence fails as if HIP had refused it
+  bool overflow_serve_once = false;  // test hook (MORAY_INJECT_SERVE_OVERFLOW=1 at moray_init): the serving
+                                     // engine's first launch with two or more problems reports a queue overflow
   size_t allocated = 0;
   moray::DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial, fields, outs;
   moray::DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];

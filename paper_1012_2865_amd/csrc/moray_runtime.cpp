@@ -13,6 +13,7 @@
 #include <cfloat>
 #include <chrono>
 #include <cmath>
+#include <cstdlib>
 #include <cstdio>
 #include <cstring>
 #include <string>
@@ -323,6 +324,8 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   c->stream = (hipStream_t)p->hip_stream;
   c->queue_cap_user = p->queue_capacity;
   c->profile = p->profile;
+  if (const char* inj = std::getenv("MORAY_INJECT_CAPTURE_FAILURE")) c->fail_capture_once = inj[0] == '1';
+  if (const char* inj = std::getenv("MORAY_INJECT_SERVE_OVERFLOW")) c->overflow_serve_once = inj[0] == '1';
   c->refill = p->refill_lanes ? p->refill_lanes : 64;
   c->chunk = p->chunk_rays ? p->chunk_rays : 256;
   c->reserve_user = p->reserve_rays;
@@ -666,11 +669,27 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     if (!hip_ok(c, hipStreamSynchronize(c->stream), "synchronize")) return MORAY_EDEVICE;
   }
 
+  // A failure while the launch sequence is being captured (or instantiating
+  // or launching the graph) ends the capture, drops the graph and reruns the
+  // solve eagerly on the context's stream: the call still succeeds.
+  auto abandon_capture = [&](hipStream_t s) {
+    hipGraph_t g = nullptr;
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs != hipStreamCaptureStatusNone)
+      (void)hipStreamEndCapture(s, &g);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    drop_graph(c->plan);
+    c->plan->no_graph = true;
+  };
   for (int attempt = 0;; ++attempt) {
-    const bool capturing = capture && attempt == 0;
+    const bool capturing = capture && attempt == 0 && !c->plan->no_graph;
     hipStream_t strm = capturing ? c->gstream : c->stream;
-    if (capturing && !hip_ok(c, hipStreamBeginCapture(strm, hipStreamCaptureModeThreadLocal), "capture"))
-      return MORAY_EDEVICE;
+    if (capturing && (c->fail_capture_once || !hip_ok(c, hipStreamBeginCapture(strm, hipStreamCaptureModeThreadLocal), "capture"))) {
+      c->fail_capture_once = false;
+      abandon_capture(strm);
+      continue;
+    }
     // chunks: consecutive trees whose bounds fit the capacity
     std::vector<ChunkPlan> chunks;
     {
@@ -694,16 +713,26 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
         c->evs.push_back(e);
       }
     }
-    if (!hip_ok(c, launch_reset(strm, ctr, stats, n_sg), "reset")) return MORAY_EDEVICE;
+    if (!hip_ok(c, launch_reset(strm, ctr, stats, n_sg), "reset")) {
+      if (capturing) { abandon_capture(strm); continue; }
+      return MORAY_EDEVICE;
+    }
     hipError_t e = fp32 ? launch_prep<float>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                              (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
                         : launch_prep<double>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                               (ProblemDev*)c->probs.p, 0, n_cells, (double*)c->kappa.p,
                                               (double*)c->acc.p, ctr);
-    if (!hip_ok(c, e, "prep")) return MORAY_EDEVICE;
+    if (!hip_ok(c, e, "prep")) {
+      if (capturing) { abandon_capture(strm); continue; }
+      return MORAY_EDEVICE;
+    }
     int launches = 0;
+    bool launch_failed = false;
     for (const ChunkPlan& ch : chunks) {
-      if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(strm, ctr), "reset levels")) return MORAY_EDEVICE;
+      if (chunks.size() > 1 && !hip_ok(c, launch_reset_levels(strm, ctr), "reset levels")) {
+        launch_failed = true;
+        break;
+      }
       for (int l = min_l0; l <= max_reach; ++l) {
         const int lo = std::max(seed_lo[l], ch.sg_begin), hi = std::min(seed_hi[l], ch.sg_end);
         const RayQueue qin{(uint64_t*)c->q_pix[l & 1].p, (uint32_t*)c->q_sg[l & 1].p, (double*)c->q_r[l & 1].p,
@@ -730,31 +759,42 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp);
         }
-        if (!hip_ok(c, e, "trace")) return MORAY_EDEVICE;
+        if (!hip_ok(c, e, "trace")) {
+          launch_failed = true;
+          break;
+        }
         if (c->profile) (void)hipEventRecord(c->evs[2 * launches + 1], strm);
         ++launches;
       }
+      if (launch_failed) break;
+    }
+    if (launch_failed) {
+      if (capturing) { abandon_capture(strm); continue; }
+      return MORAY_EDEVICE;
     }
     if (!hip_ok(c, launch_finalize(strm, (int)fblocks.size(), (GridDev*)c->grids.p, (ProblemDev*)c->probs.p,
                                    (FinalBlock*)c->fblocks.p, (double*)c->acc.p, (double*)c->eexc.p,
                                    (double*)c->partial.p, ctr),
-                "finalize"))
+                "finalize")) {
+      if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
+    }
 
     // ---- results ----
     if (!hip_ok(c, hipMemcpyAsync(hctr, ctr, sizeof(Counters), hipMemcpyDeviceToHost, strm), "copy") ||
         (n_sg && !hip_ok(c, hipMemcpyAsync(hst, stats, n_sg * sizeof(SgStats), hipMemcpyDeviceToHost, strm), "copy")) ||
         (!fblocks.empty() &&
-         !hip_ok(c, hipMemcpyAsync(hpart, c->partial.p, fblocks.size() * 8, hipMemcpyDeviceToHost, strm), "copy")))
+         !hip_ok(c, hipMemcpyAsync(hpart, c->partial.p, fblocks.size() * 8, hipMemcpyDeviceToHost, strm), "copy"))) {
+      if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
+    }
     if (capturing) {
       PlanHost& ph = *c->plan;
       if (!hip_ok(c, hipStreamEndCapture(strm, &ph.graph), "capture") ||
           !hip_ok(c, hipGraphInstantiate(&ph.exec, ph.graph, nullptr, nullptr, 0), "graph instantiate") ||
           !hip_ok(c, hipGraphLaunch(ph.exec, strm), "graph launch")) {
-        drop_graph(&ph);
-        ph.no_graph = true;
-        return MORAY_EDEVICE;
+        abandon_capture(strm);
+        continue;
       }
     }
     if (!hip_ok(c, hipStreamSynchronize(strm), "synchronize")) return MORAY_EDEVICE;

@@ -86,3 +86,29 @@ def test_autotune_settings_and_results():
     finally:
         M.moray_free(ctx)
         M.moray_free(base)
+
+
+def test_failed_capture_falls_back_to_eager(monkeypatch):
+    """A capture that fails (injected at the second call, where the library
+    would capture) still returns MORAY_OK with the eager results; later calls
+    capture and replay as usual."""
+    p = M.problem_to_device(W.lognormal_problem(97, 3, 32, 2))
+    outs = [(torch.empty(32 ** 3, dtype=torch.float64, device="cuda"),
+             torch.empty(32 ** 3, dtype=torch.float64, device="cuda"))]
+    monkeypatch.setenv("MORAY_INJECT_CAPTURE_FAILURE", "1")
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    monkeypatch.delenv("MORAY_INJECT_CAPTURE_FAILURE")
+    eager = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        want = M.moray_trace(eager, [p])[0]
+        seen = []
+        for call in range(6):
+            got = M.moray_trace(ctx, [p], outputs=outs)[0]
+            seen.append(got["from_graph"])
+            _cmp(got, want, f"injected capture failure, call {call}")
+        print(f"from_graph per call: {seen}", flush=True)
+        assert seen[1] == 0                      # the failed capture ran eagerly
+        assert seen[-1] == 1                     # and graphs work again afterwards
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(eager)
