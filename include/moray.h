@@ -47,7 +47,9 @@ typedef enum {
   MORAY_EDEVICE = -3,    /* no usable GPU, or a HIP runtime call failed */
   MORAY_EQUEUE = -4,     /* ray queue overflowed even after automatic retries */
   MORAY_EBUSY = -5,      /* an asynchronous solve has not finished yet */
-  MORAY_EINTERNAL = -7   /* a device-side consistency check failed */
+  MORAY_ETIMEOUT = -6,   /* an asynchronous solve passed its deadline (moray_set_deadline) */
+  MORAY_EINTERNAL = -7,  /* a device-side consistency check failed */
+  MORAY_ECANCELED = -8   /* an asynchronous solve was cancelled (moray_cancel) */
 } moray_status;
 
 typedef enum {
@@ -343,6 +345,24 @@ moray_status moray_trace_async(moray_ctx* ctx, const moray_problem* probs, int n
  * status (MORAY_OK when every problem's results are written), after which the
  * ticket is forgotten; MORAY_EINVAL for an unknown ticket. */
 moray_status moray_query(moray_ctx* ctx, moray_ticket ticket, int wait_ms);
+
+/* Serving failure handling (not part of the paper's method). Both act at the
+ * serving engine's next launch-generation boundary, so every kernel in
+ * flight finishes normally; the problems of the ticket that have not
+ * finished by then leave the engine (pending ones are dropped, running ones
+ * have their rays removed from the ray queue and their memory returned to
+ * the pools), and moray_query then reports the ticket's status. Problems of
+ * the ticket that finished before keep their results; the outputs of the
+ * others are undefined. Other tickets are not affected.
+ *
+ * moray_set_deadline: the ticket fails with MORAY_ETIMEOUT unless all of its
+ * problems are done `seconds` from now (CLOCK_MONOTONIC; seconds >= 0).
+ * moray_cancel: the ticket fails with MORAY_ECANCELED.
+ * Both return MORAY_EINVAL for an unknown ticket (or a negative time), and
+ * MORAY_OK otherwise, also when the ticket is already done (its status is
+ * then the one it finished with). */
+moray_status moray_set_deadline(moray_ctx* ctx, moray_ticket ticket, double seconds);
+moray_status moray_cancel(moray_ctx* ctx, moray_ticket ticket);
 
 /* Release every device and host resource of the context (NULL is allowed).
  * Queued and running asynchronous solves are finished first. */

@@ -38,6 +38,7 @@ namespace moray {
 namespace {
 
 constexpr int kServeMaxGroups = 64;
+constexpr double kLoadFrac = 0.75;         // share of the ray queue admitted problems may claim
 
 double now_s() {
   timespec ts;
@@ -88,6 +89,8 @@ struct Ticket {
   int remaining = 0;
   moray_status status = MORAY_OK;
   std::string err;
+  double deadline = HUGE_VAL;    // CLOCK_MONOTONIC seconds (moray_set_deadline)
+  bool cancel = false;           // moray_cancel
 };
 
 // One problem of an asynchronous call, with its own copies of the descriptors.
@@ -166,7 +169,8 @@ struct Engine {
   void* hfin = nullptr;                     // finalize blocks out, partial sums back
   size_t hfin_bytes = 0;
   int gen = 0;
-  double load = 0.0, load_frac = 0.75;
+  double load = 0.0, load_frac = 0.75;     // queue share in use, and the admission limit (kLoadFrac when
+                                           // clean; halved by overflows, restored by clean generations)
   std::string err;                          // last engine-side error (engine thread only)
 };
 
@@ -510,7 +514,10 @@ moray_status retire(Engine* E, std::vector<ServeProblem*>& done) {
     finish_ticket(E, p, MORAY_OK, "");
     delete p;
   }
-  if (E->running.empty()) E->load = 0.0;
+  if (E->running.empty()) {
+    E->load = 0.0;
+    E->load_frac = kLoadFrac;
+  }
   return MORAY_OK;
 }
 
@@ -542,6 +549,75 @@ void fail_all(Engine* E, moray_status st, const std::string& msg) {
   }
 }
 
+// Status a problem must leave with at this boundary (MORAY_OK: none), from its
+// ticket's cancel flag and deadline. Under E->mu.
+moray_status leave_status(Engine* E, const ServeProblem* p, double t) {
+  auto it = E->tickets.find(p->ticket);
+  if (it == E->tickets.end()) return MORAY_OK;
+  if (it->second.cancel) return MORAY_ECANCELED;
+  if (t >= it->second.deadline) return MORAY_ETIMEOUT;
+  return MORAY_OK;
+}
+
+const char* leave_message(moray_status st) {
+  return st == MORAY_ECANCELED ? "the solve was cancelled" : "the solve passed its deadline";
+}
+
+// At a generation boundary: pending problems of cancelled or expired tickets
+// are dropped; running ones have their rays removed from the queue that the
+// next launch reads (row `row`), and their memory returns to the pools.
+// Returns false on a device error (the engine then fails everything).
+bool drop_leavers(Engine* E, int row) {
+  const double t = now_s();
+  std::vector<std::pair<ServeProblem*, moray_status>> gone, stop_running;
+  {
+    std::lock_guard<std::mutex> lk(E->mu);
+    for (auto it = E->pending.begin(); it != E->pending.end();) {
+      const moray_status st = leave_status(E, *it, t);
+      if (st != MORAY_OK) {
+        gone.push_back({*it, st});
+        it = E->pending.erase(it);
+      } else {
+        ++it;
+      }
+    }
+    for (ServeProblem* p : E->running) {
+      const moray_status st = leave_status(E, p, t);
+      if (st != MORAY_OK) stop_running.push_back({p, st});
+    }
+  }
+  for (auto& [p, st] : gone) {
+    finish_ticket(E, p, st, leave_message(st));
+    delete p;
+  }
+  if (stop_running.empty()) return true;
+  moray_ctx* c = E->c;
+  for (size_t b = 0; b < stop_running.size(); b += kDropRanges) {
+    int lo[kDropRanges], hi[kDropRanges], n = 0;
+    for (size_t k = b; k < stop_running.size() && n < kDropRanges; ++k, ++n) {
+      lo[n] = stop_running[k].first->tbase;
+      hi[n] = stop_running[k].first->tbase + stop_running[k].first->ntrees;
+    }
+    if (!eok(E, launch_drop_trees(c->stream, (uint32_t*)E->qsg[row].p, (Counters*)E->ctr.p, row, E->seg_cap,
+                                  E->nseg, lo, hi, n),
+             "drop rays"))
+      return false;
+  }
+  if (!eok(E, hipStreamSynchronize(c->stream), "synchronize")) return false;
+  for (auto& [p, st] : stop_running) {
+    E->running.erase(std::find(E->running.begin(), E->running.end(), p));
+    E->load -= p->bound;
+    unplace(E, p);
+    finish_ticket(E, p, st, leave_message(st));
+    delete p;
+  }
+  if (E->running.empty()) {
+    E->load = 0.0;
+    E->load_frac = kLoadFrac;
+  }
+  return true;
+}
+
 // One trip of the launch loop. Returns false when the engine must stop.
 bool trip(Engine* E) {
   moray_ctx* c = E->c;
@@ -551,6 +627,14 @@ bool trip(Engine* E) {
     std::unique_lock<std::mutex> lk(E->mu);
     E->cv_work.wait(lk, [&] { return E->stop || !E->pending.empty() || !E->running.empty(); });
     if (E->stop && E->pending.empty() && E->running.empty()) return false;
+  }
+  // the next launch reads the queue the last one wrote (row E->gen & 1)
+  if (!drop_leavers(E, E->gen & 1)) {
+    fail_all(E, MORAY_EDEVICE, E->err);
+    return true;
+  }
+  {
+    std::unique_lock<std::mutex> lk(E->mu);
     while (!E->pending.empty()) {
       ServeProblem* p = E->pending.front();
       if (!admitted.empty() && p->l0 != admitted[0]->l0) break;
@@ -718,7 +802,9 @@ bool trip(Engine* E) {
     fail_all(E, MORAY_EINTERNAL, "a ray exceeded its step bound");
     return false;
   }
-  if (E->hctr->err & kErrOverflow) {
+  const bool injected = c->overflow_serve_once && E->running.size() > 1;
+  if (injected) c->overflow_serve_once = false;
+  if ((E->hctr->err & kErrOverflow) || injected) {
     // children were lost: every running problem starts again, with a smaller
     // queue share; one that overflowed alone, or again and again, cannot be served
     std::vector<ServeProblem*> again;
@@ -742,6 +828,8 @@ bool trip(Engine* E) {
     requeue(E, again);
     return true;
   }
+  // a clean generation gives back a quarter of what an overflow took
+  E->load_frac = std::min(kLoadFrac, E->load_frac * 1.25);
   unsigned long long pop = 0;
   for (int k = 0; k < E->nseg; ++k) pop += std::min<unsigned long long>(E->hctr->count[cout][k], E->seg_cap);
   std::vector<ServeProblem*> done, still;
@@ -878,6 +966,35 @@ moray_status moray_trace_async(moray_ctx* c, const moray_problem* probs, int n_p
     }
     E->in_flight += n_probs;
     *ticket = t;
+  }
+  E->cv_work.notify_all();
+  return MORAY_OK;
+}
+
+moray_status moray_set_deadline(moray_ctx* c, moray_ticket ticket, double seconds) {
+  if (!c) return MORAY_EINVAL;
+  if (!(seconds >= 0.0)) return fail(c, MORAY_EINVAL, "the deadline must be a time >= 0 from now");
+  Engine* E = c->engine;
+  if (!E) return fail(c, MORAY_EINVAL, "unknown ticket");
+  {
+    std::lock_guard<std::mutex> lk(E->mu);
+    auto it = E->tickets.find(ticket);
+    if (it == E->tickets.end()) return fail(c, MORAY_EINVAL, "unknown ticket");
+    it->second.deadline = now_s() + seconds;
+  }
+  E->cv_work.notify_all();
+  return MORAY_OK;
+}
+
+moray_status moray_cancel(moray_ctx* c, moray_ticket ticket) {
+  if (!c) return MORAY_EINVAL;
+  Engine* E = c->engine;
+  if (!E) return fail(c, MORAY_EINVAL, "unknown ticket");
+  {
+    std::lock_guard<std::mutex> lk(E->mu);
+    auto it = E->tickets.find(ticket);
+    if (it == E->tickets.end()) return fail(c, MORAY_EINVAL, "unknown ticket");
+    it->second.cancel = true;
   }
   E->cv_work.notify_all();
   return MORAY_OK;

@@ -18,9 +18,10 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmoray.so")
 
-MORAY_OK, MORAY_EINVAL, MORAY_ENOMEM, MORAY_EDEVICE, MORAY_EQUEUE, MORAY_EBUSY, MORAY_EINTERNAL = 0, -1, -2, -3, -4, -5, -7
+MORAY_OK, MORAY_EINVAL, MORAY_ENOMEM, MORAY_EDEVICE, MORAY_EQUEUE, MORAY_EBUSY = 0, -1, -2, -3, -4, -5
+MORAY_ETIMEOUT, MORAY_EINTERNAL, MORAY_ECANCELED = -6, -7, -8
 STATUS_NAMES = {0: "MORAY_OK", -1: "MORAY_EINVAL", -2: "MORAY_ENOMEM", -3: "MORAY_EDEVICE", -4: "MORAY_EQUEUE",
-                -5: "MORAY_EBUSY", -7: "MORAY_EINTERNAL"}
+                -5: "MORAY_EBUSY", -6: "MORAY_ETIMEOUT", -7: "MORAY_EINTERNAL", -8: "MORAY_ECANCELED"}
 MORAY_FP64, MORAY_FP32_ACC64 = 0, 1
 MORAY_FIELDS_ON_DEVICE, MORAY_OUT_ON_DEVICE = 1, 2
 
@@ -95,7 +96,7 @@ class TuneResult(ctypes.Structure):
 
 ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_evolve",
                  "moray_td_create", "moray_td_step", "moray_td_free", "moray_trace_async", "moray_query",
-                 "moray_free", "moray_last_error", "moray_version")
+                 "moray_set_deadline", "moray_cancel", "moray_free", "moray_last_error", "moray_version")
 
 _lib = None
 
@@ -136,6 +137,10 @@ def load_library(path: str = LIB_PATH):
         lib.moray_trace_async.restype = ctypes.c_int
         lib.moray_query.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_int]
         lib.moray_query.restype = ctypes.c_int
+        lib.moray_set_deadline.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong, ctypes.c_double]
+        lib.moray_set_deadline.restype = ctypes.c_int
+        lib.moray_cancel.argtypes = [ctypes.c_void_p, ctypes.c_ulonglong]
+        lib.moray_cancel.restype = ctypes.c_int
         lib.moray_free.argtypes = [ctypes.c_void_p]
         lib.moray_free.restype = None
         lib.moray_last_error.argtypes = [ctypes.c_void_p]
@@ -462,6 +467,22 @@ def moray_query(ctx, ticket: Ticket, wait_ms: int = -1):
         raise MorayError(rc, moray_last_error(ctx))
     ticket.results = _unpack(ticket._results, ticket._outs, ticket._want)
     return ticket.results
+
+
+def moray_set_deadline(ctx, ticket: Ticket, seconds: float) -> None:
+    """The ticket fails with MORAY_ETIMEOUT unless done `seconds` from now
+    (checked at the serving engine's next launch boundary)."""
+    rc = load_library().moray_set_deadline(ctx, ticket.handle, float(seconds))
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+
+
+def moray_cancel(ctx, ticket: Ticket) -> None:
+    """The ticket fails with MORAY_ECANCELED at the serving engine's next
+    launch boundary (unless it is done by then)."""
+    rc = load_library().moray_cancel(ctx, ticket.handle)
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
 
 
 def problem_to_device(problem, device: str = "cuda"):

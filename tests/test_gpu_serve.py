@@ -171,3 +171,75 @@ def test_overflow_alone_fails_only_its_ticket():
     finally:
         M.moray_free(ctx)
         M.moray_free(ref)
+
+
+def test_cancel_and_deadline_leave_other_requests_intact():
+    """A long anchor request cancelled from the host, and another that passes
+    its deadline, leave at a launch boundary with MORAY_ECANCELED and
+    MORAY_ETIMEOUT; small requests running beside them complete with their
+    solo results, and the engine serves new requests afterwards (on the tree
+    slots and memory the removed requests gave back)."""
+    anchor = M.problem_to_device(W.lognormal_problem(96, 20, 256, 32))
+    small = [M.problem_to_device(W.lognormal_problem(96, 21 + i, 32, 3)) for i in range(3)]
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    ref = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        alone = [M.moray_trace(ref, [p])[0] for p in small]
+        t_anchor = M.moray_trace_async(ctx, [anchor])
+        t_small = M.moray_trace_async(ctx, [small[0]])
+        time.sleep(0.003)
+        M.moray_cancel(ctx, t_anchor)
+        _same(M.moray_query(ctx, t_small, -1)[0], alone[0], 1e-9, "beside a cancelled request")
+        with pytest.raises(M.MorayError) as e:
+            M.moray_query(ctx, t_anchor, -1)
+        assert e.value.status == M.MORAY_ECANCELED
+        t_anchor = M.moray_trace_async(ctx, [anchor])
+        M.moray_set_deadline(ctx, t_anchor, 0.002)
+        t_small = M.moray_trace_async(ctx, [small[1]])
+        _same(M.moray_query(ctx, t_small, -1)[0], alone[1], 1e-9, "beside a timed-out request")
+        with pytest.raises(M.MorayError) as e:
+            M.moray_query(ctx, t_anchor, -1)
+        assert e.value.status == M.MORAY_ETIMEOUT
+        # a finished ticket keeps its status when cancelled late; unknown tickets are rejected
+        t_small = M.moray_trace_async(ctx, [small[2]])
+        got = M.moray_query(ctx, t_small, -1)
+        _same(got[0], alone[2], 1e-9, "after the removed requests")
+        lib = M.load_library()
+        assert lib.moray_cancel(ctx, ctypes.c_ulonglong(987654321)) == M.MORAY_EINVAL
+        assert lib.moray_set_deadline(ctx, ctypes.c_ulonglong(987654321), 1.0) == M.MORAY_EINVAL
+        t_late = M.moray_trace_async(ctx, [small[0]])
+        time.sleep(0.5)                                   # a 32^3 solve takes a few milliseconds
+        assert lib.moray_cancel(ctx, ctypes.c_ulonglong(t_late.handle)) == M.MORAY_OK
+        _same(M.moray_query(ctx, t_late, -1)[0], alone[0], 1e-9, "cancelled after it finished")
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(ref)
+
+
+def test_admission_share_recovers_after_an_overflow(monkeypatch):
+    """An overflow (injected into the first launch that runs several problems)
+    restarts them with half the queue share, so fewer are admitted at once;
+    clean launches restore the share, and a later burst is admitted together
+    again. Every result equals its solo run."""
+    probs = [M.problem_to_device(W.lognormal_problem(96, 30 + i, 24, 3)) for i in range(8)]
+    # the admission estimate of one such problem is 12006 rays per tree x 12
+    # trees; a queue where four fit in 0.75 of it but not in half of that
+    bound = 12006 * 12
+    monkeypatch.setenv("MORAY_INJECT_SERVE_OVERFLOW", "1")
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64, queue_capacity=int(4 * bound / 0.6))
+    monkeypatch.delenv("MORAY_INJECT_SERVE_OVERFLOW")
+    ref = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        alone = [M.moray_trace(ref, [p])[0] for p in probs]
+        first = M.moray_query(ctx, M.moray_trace_async(ctx, probs[:4]), -1)
+        second = M.moray_query(ctx, M.moray_trace_async(ctx, probs[4:]), -1)
+        for i, r in enumerate(first + second):
+            _same(r, alone[i], 1e-9, f"overflow recovery p{i}")
+        admits1 = sorted({r["t_admit"] for r in first})
+        admits2 = sorted({r["t_admit"] for r in second})
+        print(f"admission times after the overflow: {len(admits1)} distinct; later burst: {len(admits2)}", flush=True)
+        assert len(admits1) >= 2          # the restart admitted them in smaller groups
+        assert len(admits2) == 1          # the later burst went in together
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(ref)
