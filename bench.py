@@ -2,22 +2,26 @@
 """Throughput benchmark of the adaptive ray tracer on one MI355X.
 
 A step is one full single-pass trace (absorber columns, seeding, every
-HEALPix level's march/split/deposit, finalize) of one synthetic workload whose
-fields are already resident in HBM. `value` is ray-cell segments per second
-of the float32-geometry / float64-accumulate path over the timed steps
-(wall clock around the steps, including the result read-back of each call),
-with the library's default launch settings (the ones its autotuner picks for
-this workload) and the launch sequence replayed from its HIP graph. The plain float64 path
-on the same input (planned and launched anew every call) is reported beside
-it, and so are the 64-grid batched workload and a serving run.
+HEALPix level's march/split/deposit, finalize) of one synthetic batch whose
+fields are already resident in HBM. The headline workload is the batched one:
+64 independent lognormal grids (edges 32-96, 1-8 sources each) traced in one
+call, in the float32-geometry / float64-accumulate mode, with launch settings
+chosen by the library's autotuner for this batch and the launch sequence
+replayed from its HIP graph. `value` is ray-cell segments per second over the
+timed steps (wall clock around the steps, including each call's read-back of
+its totals). Beside it: the plain float64 form (the same 64 problems, one
+problem per call, planned and launched anew every call, no graph), the
+trace kernel's roofline, the CPU oracle on all 64 problems, the 128^3
+single-problem workload, the nested 256^3 + 128^3 workload, a serving sweep
+over arrival rates, and the optional physics rows.
 
-  python bench.py [--steps K] [--warmup W] [--workload c1|c2]
-  python bench.py --serve-only [--serve-rates 10,20,...] [--serve-requests N]
+  python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--settings C,R,S,W]
+  python bench.py --serve-only [--serve-rates 10,50,...] [--serve-requests N]
   python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only | --td-only
-  python bench.py --counter-pass [--counter-variant plain|radpres|td]   (under rocprofv3 --pmc)
+  python bench.py --counter-pass [--workload c2] [--counter-variant plain|radpres|td]   (under rocprofv3 --pmc)
   python bench.py --read-atomics ATOMIC_DIR LAUNCHES
-  python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES
-  python bench.py --write-atomics ATOMIC_DIR LAUNCHES [--counter-variant radpres|td]
+  python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES [--workload c2]
+  python bench.py --write-atomics ATOMIC_DIR LAUNCHES [--workload c2] [--counter-variant radpres|td]
 
 Prints one JSON line.
 """
@@ -59,17 +63,27 @@ def _device_peaks():
 
 def _workload(name):
     from paper_1012_2865_amd import workloads as W
+    common = {"groups": [13.6, 20.0, 30.0, 60.0], "phi_c": 5.1, "level_init": 1, "level_max": 14, "p_min_frac": 1e-8}
     if name == "c1":
         return [W.config1()], {"workload": "lognormal128_16src_4grp", "grid": "128^3", "box_kpc": 2.0,
-                               "sources": 16, "groups": [13.6, 20.0, 30.0, 60.0], "phi_c": 5.1,
-                               "level_init": 1, "level_max": 14, "p_min_frac": 1e-8}
+                               "sources": 16, **common}
     if name == "c2":
         probs = W.config2(64)
         return probs, {"workload": "batched64_lognormal_32-96", "problems": 64,
                        "cells": int(sum(p.n_cells for p in probs)),
-                       "sources": int(sum(p.n_sources for p in probs)), "groups": [13.6, 20.0, 30.0, 60.0],
-                       "phi_c": 5.1, "level_init": 1, "level_max": 14, "p_min_frac": 1e-8}
+                       "sources": int(sum(p.n_sources for p in probs)), **common}
+    if name == "c4":
+        p = W.config4()
+        return [p], {"workload": "nested256+128_1000src_4grp", "grids": "256^3 root + 128^3 child (2x)",
+                     "box_kpc": 4.0, "sources": 1000, "clusters": 10, **common}
     raise ValueError(name)
+
+
+def _parse_settings(text):
+    """--settings chunk,refill,reserve,waves (launch settings to use instead
+    of running the autotuner)."""
+    c, r, s, w = (int(x) for x in text.split(","))
+    return {"chunk_rays": c, "refill_lanes": r, "reserve_rays": s, "waves_per_cu": w, "source": "--settings"}
 
 
 def _outputs(dev):
@@ -102,10 +116,17 @@ def _time_steps(M, ctx, dev, steps, warmup, graph=True):
     return dt / steps, segs, res
 
 
-def _tuned(M, precision, dev):
-    """A context whose launch settings the autotuner chose for this batch."""
+def _tuned(M, precision, dev, settings=None):
+    """A context whose launch settings the autotuner chose for this batch
+    (or the given settings)."""
+    if settings:
+        ctx = M.moray_init(device=0, precision=precision, chunk_rays=settings["chunk_rays"],
+                           refill_lanes=settings["refill_lanes"], reserve_rays=settings["reserve_rays"],
+                           waves_per_cu=settings["waves_per_cu"])
+        return ctx, dict(settings)
     ctx = M.moray_init(device=0, precision=precision)
     tune = M.moray_autotune(ctx, dev)
+    tune["source"] = "moray_autotune"
     return ctx, tune
 
 
@@ -140,17 +161,23 @@ def _traffic(workload, precision):
     return rec["per_launch_bytes"][key]
 
 
-def _counter_pass(workload, variant="plain"):
-    """One warm-up and one measured fp32 trace of the workload, then a 1 GiB
-    device-to-device copy whose counter readings calibrate FETCH_SIZE and
-    WRITE_SIZE. Meant to run under `rocprofv3 --pmc`. The variant "radpres"
-    traces with the radiation-pressure sums; "td" runs six time-dependent
-    steps (c dt_P = 32 cells), the last of which is the measured one."""
+def _counter_pass(workload, variant="plain", settings=None):
+    """One warm-up and one measured fp32 trace of the workload (with the
+    given launch settings, else the autotuner's for it, else for "c1" the
+    library defaults), then a 1 GiB device-to-device copy whose counter
+    readings calibrate FETCH_SIZE and WRITE_SIZE, and the device-peak
+    microbenchmark whose known atomic count calibrates TCC_EA0_ATOMIC. Meant
+    to run under `rocprofv3 --pmc`. The variant "radpres" traces with the
+    radiation-pressure sums; "td" runs six time-dependent steps (c dt_P = 32
+    cells), the last of which is the measured one."""
     import torch
     from paper_1012_2865_amd import moray as M
     problems, config = _workload(workload)
     dev = [M.problem_to_device(p) for p in problems]
-    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    if settings is None and workload == "c1":
+        ctx, settings = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64), {"source": "library defaults"}
+    else:
+        ctx, settings = _tuned(M, M.MORAY_FP32_ACC64, dev, settings)
     try:
         if variant == "td":
             td = M.moray_td_create(ctx, dev[0], 32.0, 1 << 25)
@@ -171,7 +198,7 @@ def _counter_pass(workload, variant="plain"):
     b.copy_(a)
     torch.cuda.synchronize()
     peaks = _device_peaks()     # its scattered-atomics kernel calibrates the atomic counter
-    print(json.dumps({"counter_pass": config["workload"], "variant": variant,
+    print(json.dumps({"counter_pass": config["workload"], "variant": variant, "settings": settings,
                       "segments": sum(r["segments"] for r in res),
                       "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES,
                       "peaks": peaks}), flush=True)
@@ -519,42 +546,88 @@ def _td_c1(M, steps=10, c_dt=32.0, oracle=False):
     return out
 
 
-def _batched_c2(M, steps):
-    """Config 2: 64 independent grids (edges 32-96, 1-8 sources). The batched
-    form traces all of them in one call (one launch sequence) in mixed
-    precision; the plain form calls the float64 path once per problem."""
+def _roofline(M, workload, dev, tune, peaks):
+    """Roofline of the dominant kernel (trace_level_kernel<float>) under the
+    timed form's launch settings: algorithmic bytes per launch (36 B per
+    segment) over the average launch duration measured with HIP events on
+    the library's stream. traffic and atomics come from the committed counter
+    passes of the same kernel source (profiles/traffic_trace_level.json), or
+    null when the kernel has changed since."""
+    kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, dev, tune)
+    algo_bytes = BYTES_PER_SEGMENT["fp32"] * ksegs
+    achieved = algo_bytes / (kms * 1e-3) / 1e9
+    traffic = _traffic(workload, "fp32")
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+            "traffic_source": "FETCH_SIZE + WRITE_SIZE counter passes of this kernel source, per launch, read from "
+                              "profiles/traffic_trace_level.json (null: kernel changed since)",
+            "kernel": "trace_level_kernel<float>", "launches_per_step": launches,
+            "avg_launch_ms": kms / launches if launches else None,
+            "algorithmic_bytes_per_launch": algo_bytes / launches if launches else None,
+            "segments_per_step": ksegs}
+    # the deposits' second bound: float64 atomics that reach the memory side
+    # (evicted LDS sums), against the device's measured atomic peak
+    apl = _atomics_per_launch(workload, "fp32")
+    if peaks:
+        rate = apl / (kms * 1e-3 / launches) if (apl and launches) else None
+        roof["atomics"] = {"unit": "float64 atomics/s", "per_launch": apl,
+                           "per_segment": apl * launches / ksegs if apl else None, "achieved": rate,
+                           "peak": peaks["atomics_scattered"], "peak_coherent": peaks["atomics_coherent"],
+                           "frac": rate / peaks["atomics_scattered"] if rate else None,
+                           "source": "TCC_EA0_ATOMIC counter pass read from profiles/traffic_trace_level.json"}
+        roof["copy_GBs_measured"] = peaks["copy_GBs"]
+    return roof
+
+
+def _plain_fp64(M, dev, steps):
+    """The plain form: float64 path, one problem per call, every call planned
+    and launched anew (alternating result buffers, so nothing replays)."""
     import torch
-    problems, config = _workload("c2")
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
+    try:
+        sets = [_outputs(dev), _outputs(dev)]
+        for i, p in enumerate(dev[:4]):
+            M.moray_trace(ctx, [p], outputs=[sets[0][i]])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        seg64 = 0
+        for rep in range(steps):
+            seg64 = 0
+            for i, p in enumerate(dev):
+                seg64 += M.moray_trace(ctx, [p], outputs=[sets[rep % 2][i]])[0]["segments"]
+        torch.cuda.synchronize()
+        s64 = (time.perf_counter() - t0) / steps
+    finally:
+        M.moray_free(ctx)
+    return {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3, "segments": seg64,
+            "dtype": "f64", "form": "one problem per call, no graph" if len(dev) > 1 else "one solve per call, no graph"}
+
+
+def _single_workload(M, name, steps, peaks, cpu_threads=0):
+    """A workload traced as one problem: the mixed form (default settings,
+    graph replay) beside the float64 form, with its own roofline."""
+    import torch
+    problems, config = _workload(name)
     dev = [M.problem_to_device(p) for p in problems]
     torch.cuda.synchronize()
-    ctx, tune = _tuned(M, M.MORAY_FP32_ACC64, dev)
+    settings = {"chunk_rays": 256, "refill_lanes": 64, "reserve_rays": 0, "waves_per_cu": 0,
+                "source": "library defaults"}
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
     try:
         s32, seg32, res = _time_steps(M, ctx, dev, steps, 2)
     finally:
         M.moray_free(ctx)
-    ctx = M.moray_init(device=0, precision=M.MORAY_FP64)
-    try:
-        for p in dev[:4]:
-            M.moray_trace(ctx, [p])
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        reps = max(1, steps // 2)
-        seg64 = 0
-        for _ in range(reps):
-            seg64 = 0
-            for p in dev:
-                seg64 += M.moray_trace(ctx, [p])[0]["segments"]
-        torch.cuda.synchronize()
-        s64 = (time.perf_counter() - t0) / reps
-    finally:
-        M.moray_free(ctx)
-    return {"workload": config["workload"], "batched_fp32": {"value": seg32 / s32, "unit": "segments/s",
-                                                             "ms_per_step": s32 * 1e3, "segments": seg32,
-                                                             "graph_replay": bool(res[0]["from_graph"]),
-                                                             "tuned": tune},
-            "plain_fp64": {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3,
-                           "segments": seg64, "form": "one problem per call"},
-            "batched_over_plain": (seg32 / s32) / (seg64 / s64)}
+    out = {"workload": config["workload"], "config": config, "value": seg32 / s32, "unit": "segments/s",
+           "ms_per_step": s32 * 1e3, "segments_per_step": seg32, "graph_replay": bool(res[0]["from_graph"]),
+           "dtype": "f32+f64acc", "settings": settings,
+           "plain_fp64": _plain_fp64(M, dev, max(1, steps // 2)),
+           "roofline": _roofline(M, name, dev, settings, peaks)}
+    out["fp32_over_fp64"] = out["value"] / out["plain_fp64"]["value"]
+    if cpu_threads:
+        v, dt, segs = _cpu_baseline(problems, cpu_threads)
+        out["cpu_oracle"] = {"value": v, "unit": "segments/s", "cores": cpu_threads, "kind": "oracle",
+                             "sample": f"full workload: {segs} segments in {dt:.1f} s"}
+    return out
 
 
 def _serving_c3(M, rate_hz, n_requests, horizon_s):
@@ -617,21 +690,33 @@ def _cpu_baseline(problems, threads):
     return segs / dt, dt, segs
 
 
+def _serving_sweep(M, rates, n_requests):
+    out = []
+    for rate in rates:
+        r = _serving_c3(M, rate, n_requests, 60.0)
+        print(f"# serving {rate:g} req/s: p50 {r['p50_ms']:.1f} ms p99 {r['p99_ms']:.1f} ms "
+              f"{r['segments_per_s']:.3e} segments/s", file=sys.stderr, flush=True)
+        out.append(r)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", choices=["c1", "c2"], default="c1")
+    ap.add_argument("--workload", choices=["c2", "c1", "c4"], default="c2")
+    ap.add_argument("--settings", type=str, default=None,
+                    help="chunk,refill,reserve,waves launch settings for the timed form instead of the autotuner")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--cpu-threads", type=int, default=int(os.environ.get("MORAY_CPU_THREADS", "16")))
-    ap.add_argument("--no-extras", action="store_true", help="skip the batched and serving measurements")
-    ap.add_argument("--serve-rate", type=float, default=10.0, help="serving measurement: arrivals per second")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the single-problem, nested, serving and physics measurements")
+    ap.add_argument("--serve-requests", type=int, default=200)
     ap.add_argument("--serve-only", action="store_true",
                     help="print one serving JSON line per --serve-rates value and exit")
-    ap.add_argument("--serve-rates", type=str, default="10,20,50,100,200,500")
+    ap.add_argument("--serve-rates", type=str, default="10,50,100,200,500")
     ap.add_argument("--equilibrium-only", action="store_true",
                     help="print the photo-ionisation equilibrium measurement as one JSON line and exit")
     ap.add_argument("--evolve-only", action="store_true",
@@ -654,6 +739,7 @@ def main():
     ap.add_argument("--write-atomics", nargs=2, metavar=("ATOMIC_DIR", "LAUNCHES"),
                     help="host only: add the float64 atomics per launch from a TCC_EA0_ATOMIC_sum pass")
     args = ap.parse_args()
+    settings = _parse_settings(args.settings) if args.settings else None
     if args.write_traffic:
         _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]))
         return
@@ -669,7 +755,7 @@ def main():
         sys.exit(2)
 
     if args.counter_pass:
-        _counter_pass(args.workload, args.counter_variant)
+        _counter_pass(args.workload, args.counter_variant, settings)
         return
     import torch
     from paper_1012_2865_amd import moray as M
@@ -693,75 +779,55 @@ def main():
             print(json.dumps(_serving_c3(M, rate, args.serve_requests, 60.0)), flush=True)
         return
 
+    threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
+    peaks = _device_peaks()
     problems, config = _workload(args.workload)
     dev = [M.problem_to_device(p) for p in problems]
     torch.cuda.synchronize()
     print(f"# workload {config['workload']} on {torch.cuda.get_device_name(0)}", file=sys.stderr, flush=True)
 
-    # the library's default launch settings are the ones the autotuner picks
-    # for this workload; the batched form below runs the autotuner itself
-    ctx32 = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
-    tune = {"chunk_rays": 256, "refill_lanes": 64, "reserve_rays": 0, "waves_per_cu": 0, "source": "library defaults"}
+    # the timed form: mixed precision, one call per step over the whole
+    # batch, launch settings from the autotuner (or --settings), graph replay
+    ctx32, tune = _tuned(M, M.MORAY_FP32_ACC64, dev, settings)
     try:
         s32, seg32, res32 = _time_steps(M, ctx32, dev, args.steps, max(2, args.warmup))
     finally:
         M.moray_free(ctx32)
-    print(f"# fp32: {s32 * 1e3:.2f} ms/step, {seg32} segments, graph replay {bool(res32[0]['from_graph'])}",
-          file=sys.stderr, flush=True)
+    print(f"# fp32 batched: {s32 * 1e3:.2f} ms/step, {seg32} segments, graph replay {bool(res32[0]['from_graph'])}, "
+          f"settings {tune}", file=sys.stderr, flush=True)
     plain = None
     if not args.no_fp64:
-        ctx64 = M.moray_init(device=0, precision=M.MORAY_FP64)
-        try:
-            s64, seg64, _ = _time_steps(M, ctx64, dev, max(1, args.steps // 2), 1, graph=False)
-        finally:
-            M.moray_free(ctx64)
-        plain = {"value": seg64 / s64, "unit": "segments/s", "ms_per_step": s64 * 1e3, "segments": seg64,
-                 "dtype": "f64", "form": "one solve per call, no graph"}
-        print(f"# fp64: {s64 * 1e3:.2f} ms/step, {seg64} segments", file=sys.stderr, flush=True)
-
-    kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, dev, tune)
-    algo_bytes = BYTES_PER_SEGMENT["fp32"] * ksegs
-    achieved = algo_bytes / (kms * 1e-3) / 1e9
-    traffic = _traffic(args.workload, "fp32")
-    roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
-                "kernel": "trace_level_kernel<float>", "launches_per_step": launches,
-                "avg_launch_ms": kms / launches if launches else None,
-                "algorithmic_bytes_per_launch": algo_bytes / launches if launches else None}
-    # the deposits' second bound: float64 atomics that reach the memory side
-    # (evicted LDS sums), against the device's scattered-atomic peak
-    peaks = _device_peaks()
-    apl = _atomics_per_launch(args.workload, "fp32")
-    if peaks:
-        rate = apl / (kms * 1e-3 / launches) if (apl and launches) else None
-        roofline["atomics"] = {"unit": "float64 atomics/s", "per_launch": apl,
-                               "per_segment": apl * launches / ksegs if apl else None, "achieved": rate,
-                               "peak": peaks["atomics_scattered"], "peak_coherent": peaks["atomics_coherent"],
-                               "frac": rate / peaks["atomics_scattered"] if rate else None}
-        roofline["copy_GBs_measured"] = peaks["copy_GBs"]
+        plain = _plain_fp64(M, dev, max(1, args.steps // 2))
+        print(f"# fp64 plain: {plain['ms_per_step']:.2f} ms/step, {plain['segments']} segments", file=sys.stderr,
+              flush=True)
+    roofline = _roofline(M, args.workload, dev, tune, peaks)
 
     cpu = None
     if not args.no_cpu_baseline:
-        threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-        sample = problems if args.workload == "c1" else problems[:8]
-        v, dt, segs = _cpu_baseline(sample, threads)
+        v, dt, segs = _cpu_baseline(problems, threads)
+        what = f"all {len(problems)} problems" if len(problems) > 1 else "full workload"
         cpu = {"value": v, "unit": "segments/s", "cores": threads, "kind": "oracle",
-               "sample": f"{'full workload' if args.workload == 'c1' else 'first 8 of 64 problems'}: "
-                         f"{segs} segments in {dt:.1f} s", "host": _host_cpu()}
+               "sample": f"{what}: {segs} segments in {dt:.1f} s", "host": _host_cpu()}
         # the plain single-threaded oracle on a bounded sample of the same workload
         from paper_1012_2865_amd import workloads as W
-        one = [W.subset_sources(problems[0], [0, 1])] if args.workload == "c1" else problems[:1]
+        one = problems[:1] if len(problems) > 1 else [W.subset_sources(problems[0], [0, 1])]
         v1, dt1, segs1 = _cpu_baseline(one, 1)
         cpu["one_thread"] = {"value": v1, "unit": "segments/s", "cores": 1, "kind": "oracle",
-                             "sample": f"{'sources 0-1 of 16' if args.workload == 'c1' else 'first problem'}: "
+                             "sample": f"{'the first problem' if len(problems) > 1 else 'sources 0-1'}: "
                                        f"{segs1} segments in {dt1:.1f} s"}
         cpu["gpu_speedup"] = {"over_all_cores": (seg32 / s32) / v, "over_one_thread": (seg32 / s32) / v1}
+        print(f"# cpu oracle ({threads} threads): {v:.3e} segments/s", file=sys.stderr, flush=True)
 
     extras = {}
     if not args.no_extras:
-        extras["batched_c2"] = _batched_c2(M, max(2, args.steps // 2))
-        print(f"# batched c2: {extras['batched_c2']['batched_over_plain']:.2f}x plain fp64", file=sys.stderr, flush=True)
-        oth = 0 if args.no_cpu_baseline else args.cpu_threads
+        oth = 0 if args.no_cpu_baseline else threads
+        for name, steps in (("c1", args.steps), ("c4", 2)):
+            if name != args.workload:
+                extras[name] = _single_workload(M, name, steps, peaks, oth if name == "c1" else 0)
+                print(f"# {name}: {extras[name]['ms_per_step']:.2f} ms/step, {extras[name]['value']:.3e} segments/s, "
+                      f"roofline {extras[name]['roofline']['frac']:.3f}", file=sys.stderr, flush=True)
+        extras["serving_c3"] = {"sweep": _serving_sweep(M, [float(x) for x in args.serve_rates.split(",")],
+                                                        args.serve_requests)}
         extras["equilibrium"] = _equilibrium_c1(M, oracle_threads=oth)
         print(f"# equilibrium: {extras['equilibrium']['ms_per_trace']:.2f} ms per trace + update", file=sys.stderr,
               flush=True)
@@ -777,30 +843,31 @@ def main():
         extras["evolve_test1"] = _evolve_test1(M, oracle_threads=oth)
         print(f"# Test 1 to 500 Myr: {extras['evolve_test1']['steps']} steps in "
               f"{extras['evolve_test1']['s_total']:.2f} s", file=sys.stderr, flush=True)
-        extras["serving_c3"] = _serving_c3(M, args.serve_rate, args.serve_requests, 60.0)
-        print(f"# serving: p50 {extras['serving_c3']['p50_ms']:.1f} ms p99 {extras['serving_c3']['p99_ms']:.1f} ms",
-              file=sys.stderr, flush=True)
 
     # the radiation-pressure trace and the time-dependent step against the
-    # same scattered-atomic peak (their counts come from their own counter passes)
+    # measured atomic peak (their counts come from their own counter passes on
+    # the 128^3 workload)
     if peaks:
+        c1_launches = extras["c1"]["roofline"]["launches_per_step"] if "c1" in extras else None
         for name, variant in (("radpres", "radpres"), ("td_rays", "td")):
             ob = extras.get(name)
-            apv = _atomics_per_launch(args.workload, "fp32/" + variant)
-            if not ob or not apv:
+            apv = _atomics_per_launch("c1", "fp32/" + variant)
+            if not ob or not apv or not c1_launches:
                 continue
             ms = ob["ms_per_step"][-1] if isinstance(ob["ms_per_step"], list) else ob["ms_per_step"]
             segs = ob["segments_per_step"][-1] if name == "td_rays" else ob["segments_per_s"] * ms * 1e-3
-            per_step = apv * launches        # the same ten level launches as the plain trace
+            per_step = apv * c1_launches        # the same level launches as the plain trace
             ob["atomics"] = {"unit": "float64 atomics/s", "per_step": per_step, "per_segment": per_step / segs,
                              "achieved": per_step / (ms * 1e-3), "peak": peaks["atomics_scattered"],
-                             "frac": per_step / (ms * 1e-3) / peaks["atomics_scattered"]}
+                             "frac": per_step / (ms * 1e-3) / peaks["atomics_scattered"],
+                             "source": "TCC_EA0_ATOMIC counter pass read from profiles/traffic_trace_level.json"}
 
     out = {"metric": METRIC, "value": seg32 / s32, "unit": "segments/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": s32 * 1e3, "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32+f64acc", "data": "synthetic", "config": config,
            "segments_per_step": seg32, "graph_replay": bool(res32[0]["from_graph"]), "settings": tune,
-           "roofline": roofline, "cpu_baseline": cpu, "plain_fp64": plain, **extras}
+           "plain_fp64": plain, "batched_over_plain": (seg32 / s32) / plain["value"] if plain else None,
+           "roofline": roofline, "cpu_baseline": cpu, "device_peaks": peaks, **extras}
     print(json.dumps(out), flush=True)
 
 
