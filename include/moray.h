@@ -177,6 +177,27 @@ moray_status moray_init(moray_ctx** ctx, const moray_init_params* params);
 moray_status moray_trace(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
                          moray_result* outs);
 
+/* moray_trace for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * the same solve, with every scratch buffer (absorber columns, accumulators,
+ * ray queues, tables, counters, host-field upload and host-result staging)
+ * carved from one fixed array of 256 MiB that the library holds in device
+ * memory on each GPU it runs on, for the life of the process. The call makes
+ * no hipMalloc, hipFree or other device allocation, captures no graph and
+ * does not time its launches (profile is ignored). A batch whose scratch
+ * does not fit the array fails with MORAY_ENOMEM and a message that says so
+ * (the ray queues take what the other buffers leave; a queue too small for
+ * the batch is handled as in moray_trace, by tracing its trees in chunks,
+ * and fails with MORAY_EQUEUE only when one tree does not fit); so does a
+ * batch whose per-tree statistics and finalize partial sums exceed the
+ * context's 1 MiB pinned read-back staging. Every call on one GPU uses that
+ * GPU's one array and leaves its contents behind (each call zeroes what it
+ * needs zeroed): calls that overlap on one GPU, from any contexts or
+ * threads, race and must not be made. Arguments, flags, results and errors
+ * otherwise as moray_trace; the context's own buffers are not touched. */
+moray_status moray_trace_noalloc(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
+                                 moray_result* outs);
+
 /* Launch settings chosen by moray_autotune. */
 typedef struct {
   int chunk_rays;             /* rays a wave claims from a level queue per atomic */

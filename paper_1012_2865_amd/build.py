@@ -43,7 +43,8 @@ def build_library(out: str = LIB) -> str:
     objdir = os.path.join(HERE, "_build")
     os.makedirs(objdir, exist_ok=True)
     objs = []
-    for src in ("moray_kernels.hip", "moray_equilibrium.hip", "moray_runtime.cpp", "moray_serve.cpp", "moray_td.cpp", "moray_td_kernels.hip"):
+    for src in ("moray_kernels.hip", "moray_equilibrium.hip", "moray_runtime.cpp", "moray_serve.cpp", "moray_td.cpp",
+                "moray_td_kernels.hip", "moray_noalloc.hip"):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])

@@ -60,6 +60,11 @@ struct DevBuf {
   size_t bytes = 0;
 };
 
+// moray_noalloc.hip: the fixed scratch array of moray_trace_noalloc and its
+// address on a device (looked up once per device, with that device current)
+size_t scratch_bytes();
+hipError_t scratch_address(int device, void** ptr);
+
 struct Engine;     // serving engine of a context (moray_serve.cpp)
 struct PlanHost;   // last one-shot solve and its captured launch sequence (moray_runtime.cpp)
 
@@ -77,6 +82,13 @@ struct moray_ctx {
   int num_cu = 0;
   int blocks_per_cu = 1;
   std::string err = "no error";
+  // moray_trace_noalloc: the device address of the library's fixed scratch
+  // array on this context's device (null if its lookup failed: scratch_err),
+  // and while such a call runs, the part of it the call has carved so far
+  char* scratch = nullptr;
+  std::string scratch_err;
+  bool arena = false;
+  size_t arena_used = 0;
   bool fail_capture_once = false;  // test hook (MORAY_INJECT_CAPTURE_FAILURE=1 at moray_init): the next capture
                                    // of a launch sequence fails as if HIP had refused it
   bool overflow_serve_once = false;  // test hook (MORAY_INJECT_SERVE_OVERFLOW=1 at moray_init): the serving

@@ -177,8 +177,21 @@ void release(moray_ctx* c, DevBuf& b) {
   b.bytes = 0;
 }
 
-// Grow-only device buffer inside the context's HBM budget.
+// Grow-only device buffer inside the context's HBM budget. During a
+// moray_trace_noalloc call the buffer is carved from the library's fixed
+// scratch array instead (nothing is allocated; too little room is an error).
 moray_status ensure(moray_ctx* c, DevBuf& b, size_t bytes, const char* what) {
+  if (c->arena) {
+    bytes = (bytes + 255) & ~size_t(255);
+    if (bytes > scratch_bytes() - c->arena_used)
+      return fail(c, MORAY_ENOMEM, std::string("moray_trace_noalloc: the ") + what + " do not fit the library's " +
+                                       std::to_string(scratch_bytes() >> 20) + " MiB scratch array (" +
+                                       std::to_string(c->arena_used >> 20) + " MiB already in use by this call)");
+    b.p = c->scratch + c->arena_used;
+    b.bytes = bytes;
+    c->arena_used += bytes;
+    return MORAY_OK;
+  }
   if (bytes <= b.bytes) return MORAY_OK;
   bytes = (bytes + 255) & ~size_t(255);
   if (c->allocated - b.bytes + bytes > c->budget)
@@ -353,6 +366,11 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
     return init_fail(MORAY_EDEVICE, std::string("hipHostMalloc: ") + hipGetErrorString(he));
   }
   c->h_stage_bytes = 1 << 20;
+  // the fixed scratch array of moray_trace_noalloc: its address on this
+  // device, looked up once per device with the device current
+  void* sp = nullptr;
+  if ((he = scratch_address(c->device, &sp)) == hipSuccess) c->scratch = (char*)sp;
+  else c->scratch_err = std::string("hipGetSymbolAddress of the scratch array: ") + hipGetErrorString(he);
   *out = c;
   return MORAY_OK;
 }
@@ -384,7 +402,14 @@ void moray_free(moray_ctx* c) {
   delete c;
 }
 
-moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, moray_result* outs) {
+}  // extern "C"
+
+namespace {
+
+// The one-shot solve behind moray_trace and moray_trace_noalloc (c->arena:
+// buffers carved from the scratch array, no graphs, no profiling, no staging
+// growth).
+moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, moray_result* outs) {
   if (!c) return MORAY_EINVAL;
   if (!probs || n_probs < 1 || !outs) return fail(c, MORAY_EINVAL, "need n_probs >= 1 problems and results");
   if (flags & ~(MORAY_FIELDS_ON_DEVICE | MORAY_OUT_ON_DEVICE)) return fail(c, MORAY_EINVAL, "unknown flags");
@@ -399,7 +424,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   // Repeated solves of the same descriptors with device-resident fields and
   // results: the second call captures its launch sequence in a graph, later
   // calls replay it (fields may change in place between calls).
-  const bool graphable = (flags & MORAY_FIELDS_ON_DEVICE) && (flags & MORAY_OUT_ON_DEVICE) && !c->profile;
+  const bool graphable = (flags & MORAY_FIELDS_ON_DEVICE) && (flags & MORAY_OUT_ON_DEVICE) && !c->profile && !c->arena;
   std::string key;
   bool capture = false;
   if (graphable) {
@@ -415,7 +440,7 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
       }
     }
   }
-  if (c->plan && !(capture && c->plan->key == key)) {
+  if (c->plan && !c->arena && !(capture && c->plan->key == key)) {
     drop_graph(c->plan);
     c->plan->valid = false;
     c->plan->no_graph = false;
@@ -543,7 +568,8 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
   const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
   const size_t out_stage = odev ? 0 : (size_t)n_cells * (radp ? 40 : 16);
   const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
-                       grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) + (64 << 20);
+                       grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) +
+                       (c->arena ? (size_t)(1 << 20) : (size_t)(64 << 20));
   if (!cap) {
     const size_t room = c->budget > c->allocated + fixed ? c->budget - fixed : 0;
     const double fit = (double)room / (double)per_ray;
@@ -648,6 +674,9 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
 
   // pinned staging for the counters, the tree statistics and the partial sums
   const size_t need_stage = sizeof(Counters) + n_sg * sizeof(SgStats) + fblocks.size() * 8;
+  if (need_stage > c->h_stage_bytes && c->arena)
+    return fail(c, MORAY_ENOMEM, "moray_trace_noalloc: the batch has more (source, group) trees and finalize blocks "
+                                 "than the context's 1 MiB read-back staging holds");
   if (need_stage > c->h_stage_bytes) {
     (void)hipHostFree(c->h_stage);
     c->h_stage = nullptr;
@@ -846,6 +875,50 @@ moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, 
     c->err = "no error";
     return MORAY_OK;
   }
+}
+
+}  // namespace
+
+extern "C" {
+
+moray_status moray_trace(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags, moray_result* outs) {
+  return trace_impl(c, probs, n_probs, flags, outs);
+}
+
+moray_status moray_trace_noalloc(moray_ctx* c, const moray_problem* probs, int n_probs, unsigned flags,
+                                 moray_result* outs) {
+  if (!c) return MORAY_EINVAL;
+  if (!c->scratch)
+    return fail(c, MORAY_EDEVICE, c->scratch_err.empty() ? "no scratch array on this device" : c->scratch_err);
+  // The context's own buffers step aside for the call (they stay allocated
+  // for later moray_trace calls); every buffer of this call is carved from
+  // the scratch array, from its start, and graphs and profiling are off.
+  DevBuf* bufs[] = {&c->grids,    &c->probs,    &c->sgs,      &c->stats,    &c->ctr,      &c->kappa,
+                    &c->acc,      &c->eexc,     &c->fblocks,  &c->partial,  &c->fields,   &c->outs,
+                    &c->q_pix[0], &c->q_sg[0],  &c->q_r[0],   &c->q_P[0],   &c->q_pix[1], &c->q_sg[1],
+                    &c->q_r[1],   &c->q_P[1]};
+  constexpr int nb = (int)(sizeof(bufs) / sizeof(bufs[0]));
+  DevBuf saved[nb];
+  for (int i = 0; i < nb; ++i) {
+    saved[i] = *bufs[i];
+    *bufs[i] = DevBuf{};
+  }
+  const size_t budget = c->budget, allocated = c->allocated, q_cap = c->q_cap;
+  const int profile = c->profile;
+  c->budget = scratch_bytes();
+  c->allocated = 0;
+  c->profile = 0;
+  c->arena = true;
+  c->arena_used = 0;
+  const moray_status st = trace_impl(c, probs, n_probs, flags, outs);
+  c->arena = false;
+  c->arena_used = 0;
+  c->profile = profile;
+  c->budget = budget;
+  c->allocated = allocated;
+  c->q_cap = q_cap;
+  for (int i = 0; i < nb; ++i) *bufs[i] = saved[i];
+  return st;
 }
 
 // Cells of the ionisation updates: every grid of the problem in order

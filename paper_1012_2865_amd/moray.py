@@ -96,7 +96,8 @@ class TuneResult(ctypes.Structure):
 
 ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_evolve",
                  "moray_td_create", "moray_td_step", "moray_td_free", "moray_trace_async", "moray_query",
-                 "moray_set_deadline", "moray_cancel", "moray_free", "moray_last_error", "moray_version")
+                 "moray_set_deadline", "moray_cancel", "moray_trace_noalloc", "moray_free", "moray_last_error",
+                 "moray_version")
 
 _lib = None
 
@@ -112,6 +113,9 @@ def load_library(path: str = LIB_PATH):
         lib.moray_trace.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                     ctypes.POINTER(Result)]
         lib.moray_trace.restype = ctypes.c_int
+        lib.moray_trace_noalloc.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
+                                            ctypes.POINTER(Result)]
+        lib.moray_trace_noalloc.restype = ctypes.c_int
         lib.moray_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                        ctypes.c_int, ctypes.POINTER(TuneResult)]
         lib.moray_autotune.restype = ctypes.c_int
@@ -326,6 +330,20 @@ def moray_trace(ctx, problems: Sequence, out_on_device: bool = True, want_escape
     lib = load_library()
     cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg, outputs, want_accel)
     rc = lib.moray_trace(ctx, cprobs, len(problems), flags, results)
+    if rc != MORAY_OK:
+        raise MorayError(rc, moray_last_error(ctx))
+    return _unpack(results, outs, want_escaped_sg)
+
+
+def moray_trace_noalloc(ctx, problems: Sequence, outputs, out_on_device: bool = True,
+                        want_escaped_sg: bool = False) -> List[dict]:
+    """moray_trace through the entry point that allocates no device memory
+    (its scratch comes from the library's fixed array). ``outputs`` names the
+    caller's result buffers, as in moray_trace (required: the call itself
+    must not allocate them)."""
+    lib = load_library()
+    cprobs, results, keep, outs, flags = _marshal(problems, out_on_device, want_escaped_sg, outputs)
+    rc = lib.moray_trace_noalloc(ctx, cprobs, len(problems), flags, results)
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
     return _unpack(results, outs, want_escaped_sg)
