@@ -57,8 +57,11 @@ struct ProblemDev {
   long long acc_off;       // first accumulator slot: group g of cell c is acc_off + g*n_cells + (c - cell_off)
   int eexc_off;            // first of its n_groups (E - E_ion) values in erg
   int pad;
-  long long mom_off = -1;  // first momentum accumulator (component k of cell c at
-                           // mom_off + k*n_cells + (c - cell_off)), or -1 without radiation pressure
+  int acc_stride = 1;      // 1: one float64 sum per (group, cell), group g of cell c at
+                           //   acc_off + g*n_cells + (c - cell_off);
+                           // 4 (radiation pressure asked for): a 32-byte record per (group, cell) at
+                           //   acc_off + 4*(g*n_cells + (c - cell_off)): absorbed rate, then the three
+                           //   components of the absorbed momentum rate
 };
 
 // One (source, group) ray tree, with the shape of its problem's root grid so
@@ -81,8 +84,8 @@ struct SgDev {
   double four_pi_phi_c;    // 4 pi phi_c of its problem
   int problem;
   int covering;            // scale deposits into the accumulators by the covering factor
-  uint32_t mom_slot0;      // radiation pressure: component k of cell c (batch numbering) sums at
-  uint32_t mom_stride;     //   acc[mom_slot0 + k * mom_stride + c]
+  uint32_t acc_stride = 1; // its problem's acc_stride: the deposit into cell c (batch numbering) goes to
+                           //   acc[acc_slot + acc_stride * c], the momentum (stride 4) to the next three
   double mom_scale;        // E_ph / c of the group (erg s/cm), 0 without radiation pressure
   double r_halt = __builtin_huge_val();   // time-dependent rays: radius (root cells) where the
                                           // tree's rays halt in this step
@@ -131,6 +134,7 @@ struct TraceArgs {
   const SgDev* sgs;
   const R* kappa;          // n_H x_HI dx_root per leaf cell; -(child+1) on covered root cells
   double* acc;             // absorbed photons/s per (problem, group, leaf cell)
+  uint32_t rec_base;       // deposit keys >= rec_base start 4-sum radiation-pressure records (32-byte aligned)
   RayQueue in, out;                    // nseg segments of seg_cap slots each
   unsigned long long seg_cap;
   int nseg;                            // segments per level queue: a power of two

@@ -26,6 +26,7 @@
 #include <cfloat>
 #include <cmath>
 #include <cstdint>
+#include <type_traits>
 
 namespace moray {
 
@@ -370,8 +371,8 @@ struct Ray {
   double sx, sy, sz, P0;
   int root, rn0, rn1, rn2, rcell;
   bool cover;             // its deposits are scaled by the covering factor
-  uint32_t mom0, mstride; // radiation pressure: momentum sums of the tree's problem
-  double mscale;          // E_ph / c, 0 when the problem does not ask for them
+  uint32_t astride;       // deposit key of cell lin: slot0 + astride * lin (4: a radiation-pressure record)
+  double mscale;          // E_ph / c, 0 when the problem does not ask for the momentum
   double rhalt;           // time-dependent rays: radius where the tree's rays halt in this step
 };
 
@@ -493,8 +494,7 @@ struct Tracer {
     L.rn0 = S.rnx; L.rn1 = S.rny; L.rn2 = S.rnz;
     L.rcell = (int)S.rcell_off;
     L.cover = S.covering != 0;
-    L.mom0 = S.mom_slot0;
-    L.mstride = S.mom_stride;
+    L.astride = S.acc_stride;
     L.mscale = S.mom_scale;
     L.rhalt = S.r_halt;
     const bool can_split = level < S.level_max;
@@ -842,6 +842,141 @@ struct DepositCache<true> {
   }
 };
 
+// Radiation pressure: a problem that asks for the momentum keeps one 32-byte
+// record per (group, cell), [absorbed rate, momentum x, y, z], so a segment
+// makes one deposit of four sums under one key. Keys at or above rec_base
+// are such records; below it they are the plain one-sum slots of the other
+// problems of the batch. Evicted records are drained with (entry, component)
+// spread over consecutive lanes, so the four float64 atomics of a record go
+// out in one instruction to one 32-byte-aligned piece of a cache line.
+constexpr int kCache4Log2 = 8;                 // entries of the 4-sum table per wave
+constexpr int kCache4Entries = 1 << kCache4Log2;
+
+template <bool CACHE>
+struct DepositCache4;
+
+template <>
+struct DepositCache4<false> {
+  uint32_t rec_base;
+  __device__ void init(int, uint32_t rb) { rec_base = rb; }
+  __device__ void add(double* acc, uint32_t key, const double (&v)[4], bool has, int) {
+    if (!has) return;
+    unsafeAtomicAdd(&acc[key], v[0]);
+    if (key >= rec_base) {
+      unsafeAtomicAdd(&acc[key + 1], v[1]);
+      unsafeAtomicAdd(&acc[key + 2], v[2]);
+      unsafeAtomicAdd(&acc[key + 3], v[3]);
+    }
+  }
+  __device__ bool want_drain() const { return false; }
+  __device__ void drain(double*, int) {}
+  __device__ void flush(double*, int) {}
+};
+
+__device__ __forceinline__ uint32_t cache4_index(uint32_t key) {
+  return (key * 0x9E3779B1u) >> (32 - kCache4Log2);
+}
+
+template <>
+struct DepositCache4<true> {
+  uint32_t* key;
+  double* val;            // [4][kCache4Entries]
+  uint32_t* ekey;
+  double* eval;           // [4][kEvictCap]
+  int ecount;
+  uint32_t rec_base;
+
+  __device__ void init(int lane, uint32_t rb) {
+    __shared__ uint32_t skey[kTraceBlock / kWave][kCache4Entries];
+    __shared__ double sval[kTraceBlock / kWave][4 * kCache4Entries];
+    __shared__ uint32_t sekey[kTraceBlock / kWave][kEvictCap];
+    __shared__ double seval[kTraceBlock / kWave][4 * kEvictCap];
+    const int wv = threadIdx.x / kWave;
+    key = skey[wv];
+    val = sval[wv];
+    ekey = sekey[wv];
+    eval = seval[wv];
+    ecount = 0;
+    rec_base = rb;
+    for (int e = lane; e < kCache4Entries; e += kWave) key[e] = kNoSlot;
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ bool want_drain() const { return ecount >= kEvictCap - kWave; }
+  // (entry, component) pairs over consecutive lanes: a record's four sums in one instruction
+  __device__ void drain(double* acc, int lane) {
+    __builtin_amdgcn_wave_barrier();
+    for (int j = lane; j < 4 * ecount; j += kWave) {
+      const int i = j >> 2, k = j & 3;
+      const uint32_t kk = ekey[i];
+      if (k == 0 || kk >= rec_base) unsafeAtomicAdd(&acc[kk + k], eval[k * kEvictCap + i]);
+    }
+    ecount = 0;
+    __builtin_amdgcn_wave_barrier();
+  }
+  // The protocol of the one-sum table (DepositCache<true>::add) with four
+  // sums per entry.
+  __device__ void add(double* acc, uint32_t k_new, const double (&v)[4], bool has, int lane) {
+    const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    if (!__ballot(has)) return;
+    if (ecount > kEvictCap - kWave) drain(acc, lane);
+    uint32_t h = 0, k = kNoSlot;
+    bool match = false;
+    if (has) {
+      h = cache4_index(k_new);
+      k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      match = k == k_new;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (match) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        __hip_atomic_fetch_add(&val[c * kCache4Entries + h], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool claim = has && !match;
+    bool won = false, join = false;
+    if (claim) {
+      uint32_t seen = k;
+      won = __hip_atomic_compare_exchange_strong(&key[h], &seen, k_new, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_WORKGROUP);
+      join = !won && seen == k_new;
+    }
+    __builtin_amdgcn_wave_barrier();
+    const bool out = claim && !join && (!won || k != kNoSlot);
+    const unsigned long long omask = __ballot(out);
+    uint32_t ok = k_new;
+    double ov[4] = {v[0], v[1], v[2], v[3]};
+    if (won) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        ov[c] = __hip_atomic_exchange(&val[c * kCache4Entries + h], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      ok = k;
+    }
+    __builtin_amdgcn_wave_barrier();
+    if (join) {
+#pragma unroll
+      for (int c = 0; c < 4; ++c)
+        __hip_atomic_fetch_add(&val[c * kCache4Entries + h], v[c], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+    if (out) {
+      const int e = ecount + __popcll(omask & below);
+      ekey[e] = ok;
+#pragma unroll
+      for (int c = 0; c < 4; ++c) eval[c * kEvictCap + e] = ov[c];
+    }
+    ecount += __popcll(omask);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __device__ void flush(double* acc, int lane) {
+    drain(acc, lane);
+    for (int j = lane; j < 4 * kCache4Entries; j += kWave) {
+      const int e = j >> 2, c = j & 3;
+      const uint32_t kk = key[e];
+      if (kk != kNoSlot && (c == 0 || kk >= rec_base)) unsafeAtomicAdd(&acc[kk + c], val[c * kCache4Entries + e]);
+    }
+  }
+};
+
 // Split parents waiting for their children to be written: the children of a
 // stage go to the wave's current segment of the next level's queue (its home
 // segment at first) through blocks of slots it reserves with one atomic, in
@@ -924,10 +1059,6 @@ struct SplitStage {
   }
 };
 
-// Waves per SIMD the register budget is set for: three (at most 168 VGPRs),
-// which the LDS of a block (four waves) also allows.
-template <typename R> struct TraceWaves { static constexpr int n = 3; };
-
 // PHYS selects the optional physics some tree of the launch asks for:
 // kPhysCover scales deposits by the covering factor (section 2.3), kPhysRadp
 // adds the absorbed momentum E_ph dP / c n to three more sums per cell
@@ -938,8 +1069,12 @@ template <typename R> struct TraceWaves { static constexpr int n = 3; };
 // is the plain trace.
 constexpr int kPhysCover = 1, kPhysRadp = 2, kPhysHalt = 4;
 
+// Waves per SIMD the register budget is set for: three (at most 168 VGPRs),
+// which the LDS of a block (four waves) also allows; two for the
+// radiation-pressure variant with its four-sum deposit table, whose LDS
+// leaves room for two blocks per CU.
 template <typename R, bool CACHE, int PHYS>
-__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(TraceWaves<R>::n)))
+__global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(CACHE && (PHYS & kPhysRadp) ? 2 : 3)))
 void trace_level_kernel(TraceArgs<R> a) {
   constexpr bool COVER = (PHYS & kPhysCover) != 0, RADP = (PHYS & kPhysRadp) != 0, HALT = (PHYS & kPhysHalt) != 0;
   const int lane = threadIdx.x & (kWave - 1);
@@ -961,8 +1096,10 @@ void trace_level_kernel(TraceArgs<R> a) {
   const Tracer<R> T(a);
   Ray<R> L;
   int ended = -1;          // kind of the lane's ray that ended and is not yet tallied
-  DepositCache<CACHE> cache;
-  cache.init(lane);
+  // with radiation pressure one deposit carries four sums (one table entry each)
+  std::conditional_t<RADP, DepositCache4<CACHE>, DepositCache<CACHE>> cache;
+  if constexpr (RADP) cache.init(lane, a.rec_base);
+  else cache.init(lane);
   SplitStage stage;
   stage.init(home);
   bool active = false;
@@ -1103,8 +1240,8 @@ void trace_level_kernel(TraceArgs<R> a) {
       }
       stage.count += __popcll(smask);
     }
-    bool dep = false, moved = false, mdep = false;
-    uint32_t dkey = 0, mkey = 0;
+    bool dep = false, moved = false;
+    uint32_t dkey = 0;
     double dval = 0.0, mval = 0.0;
     R knext = (R)0;
     int s_ax = 0, s_dir = 0;
@@ -1125,14 +1262,12 @@ void trace_level_kernel(TraceArgs<R> a) {
         dval = absorb(L.P, tau);
         if constexpr (RADP) {
           // the absorbed radiation itself, before any covering-factor scaling
-          mdep = L.mscale != 0.0;
           mval = dval * L.mscale;
-          mkey = L.mom0 + (uint32_t)L.lin;
         }
         if constexpr (COVER) {
           if (L.cover) dval *= T.covering_factor(L, (double)dr);
         }
-        dkey = L.slot0 + (uint32_t)L.lin;
+        dkey = RADP ? L.slot0 + L.astride * (uint32_t)L.lin : L.slot0 + (uint32_t)L.lin;
         dep = true;
         L.segs++;
         if (HALT && halt) L.g.set_radius(L.rhalt);
@@ -1203,13 +1338,18 @@ void trace_level_kernel(TraceArgs<R> a) {
         h_count += n;
       }
     }
-    cache.add(a.acc, dkey, dval, dep, lane);
     if constexpr (RADP) {
-      if (__ballot(mdep)) {
-#pragma unroll
-        for (int k = 0; k < 3; ++k)
-          cache.add(a.acc, mkey + (uint32_t)k * L.mstride, mdep ? mval * L.g.dir64(k) : 0.0, mdep, lane);
+      // the momentum rate along the ray, from the float64 direction (zero
+      // for a problem that does not ask for it: its key is a one-sum slot)
+      double v[4] = {dval, 0.0, 0.0, 0.0};
+      if (dep && mval != 0.0) {
+        v[1] = mval * L.g.dir64(0);
+        v[2] = mval * L.g.dir64(1);
+        v[3] = mval * L.g.dir64(2);
       }
+      cache.add(a.acc, dkey, v, dep, lane);
+    } else {
+      cache.add(a.acc, dkey, dval, dep, lane);
     }
     if (moved) {
       if (knext < (R)0) {
@@ -1326,10 +1466,9 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
       }
     }
     kappa[c] = k;
-    const long long base = P.acc_off + (c - P.cell_off);
-    for (int gr = 0; gr < P.n_groups; ++gr) acc[base + gr * P.n_cells] = 0.0;
-    if (P.mom_off >= 0)
-      for (int k = 0; k < 3; ++k) acc[P.mom_off + k * P.n_cells + (c - P.cell_off)] = 0.0;
+    const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
+    for (int gr = 0; gr < P.n_groups; ++gr)
+      for (int k = 0; k < P.acc_stride; ++k) acc[base + gr * gstride + k] = 0.0;
   }
 }
 
@@ -1350,12 +1489,15 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
   for (int t = threadIdx.x; t < B.count; t += kFinalBlock) {
     const long long local = B.first + t;
     const long long c = G.cell_off + local;
-    const long long base = P.acc_off + (c - P.cell_off);
+    const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
     double ab = 0.0, he = 0.0;
+    double mom[3] = {0.0, 0.0, 0.0};
     for (int gr = 0; gr < P.n_groups; ++gr) {
-      const double v = acc[base + gr * P.n_cells];
+      const double v = acc[base + gr * gstride];
       ab += v;
       he += v * eexc[P.eexc_off + gr];
+      if (P.acc_stride == 4)
+        for (int d = 0; d < 3; ++d) mom[d] += acc[base + gr * gstride + 1 + d];
     }
     const double nabs = (double)G.n_h[local] * (double)G.x_hi[local];
     double k = 0.0, h = 0.0;
@@ -1365,12 +1507,9 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
     }
     G.out_kph[local] = k;
     G.out_heat[local] = h;
-    if (P.mom_off >= 0 && G.out_acc) {
+    if (P.acc_stride == 4 && G.out_acc) {
       const double rho = kHydrogenMassG * (double)G.n_h[local];
-      for (int d = 0; d < 3; ++d) {
-        const double m = acc[P.mom_off + d * P.n_cells + (c - P.cell_off)];
-        G.out_acc[d * P.n_cells + local] = rho > 0.0 ? m / (rho * vol) : 0.0;
-      }
+      for (int d = 0; d < 3; ++d) G.out_acc[d * P.n_cells + local] = rho > 0.0 ? mom[d] / (rho * vol) : 0.0;
     }
     sum += ab;
   }
@@ -1422,10 +1561,30 @@ hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_gr
   return hipGetLastError();
 }
 
+// Blocks per CU a kernel can keep resident (looked up once per kernel).
+template <typename K>
+static int resident_blocks(K kernel, int& memo) {
+  if (memo <= 0) {
+    int n = 0;
+    memo = (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, kTraceBlock, 0) == hipSuccess && n > 0) ? n : 1;
+  }
+  return memo;
+}
+
+// `blocks` is sized for the plain kernel's residency; a variant that keeps
+// fewer blocks per CU resident (the radiation-pressure table takes more LDS)
+// is launched with proportionally fewer, so its grid stays persistent.
 template <typename R, int PHYS>
 static void launch_phys(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache) {
-  if (cache) hipLaunchKernelGGL((trace_level_kernel<R, true, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
-  else hipLaunchKernelGGL((trace_level_kernel<R, false, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+  if (cache) {
+    static int plain = 0, mine = 0;
+    const int p = resident_blocks(trace_level_kernel<R, true, 0>, plain);
+    const int m = resident_blocks(trace_level_kernel<R, true, PHYS>, mine);
+    if (m < p) blocks = (blocks * m + p - 1) / p;
+    hipLaunchKernelGGL((trace_level_kernel<R, true, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+  } else {
+    hipLaunchKernelGGL((trace_level_kernel<R, false, PHYS>), dim3(blocks), dim3(kTraceBlock), 0, s, args);
+  }
 }
 
 template <typename R>

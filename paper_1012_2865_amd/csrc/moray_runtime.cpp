@@ -489,18 +489,29 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
     min_l0 = std::min(min_l0, P.params.level_init);
   }
   if (n_cells >= (1LL << 31) - 1) return fail(c, MORAY_EINVAL, "batch exceeds 2^31 cells");
-  // radiation-pressure momentum sums (3 per cell) of the problems that ask for them, after the others
-  long long n_mom = 0;
+  // Accumulators: one float64 sum per (group, cell) for the problems that do
+  // not ask for the radiation-pressure acceleration; after them, from the
+  // first 64-byte boundary (rec_base), a 32-byte record per (group, cell)
+  // (absorbed rate and momentum x, y, z) for those that do.
+  long long n_plain = 0, n_rec = 0;
+  for (int i = 0; i < n_probs; ++i)
+    if (!outs[i].accel) {
+      pdev[i].acc_off = n_plain;
+      n_plain += pdev[i].n_cells * pdev[i].n_groups;
+    }
+  const long long rec_base = (n_plain + 7) & ~7LL;
   for (int i = 0; i < n_probs; ++i)
     if (outs[i].accel) {
-      pdev[i].mom_off = n_acc + n_mom;
-      n_mom += 3 * pdev[i].n_cells;
+      pdev[i].acc_stride = 4;
+      pdev[i].acc_off = rec_base + n_rec;
+      n_rec += 4 * pdev[i].n_cells * pdev[i].n_groups;
     }
-  const bool radp = n_mom > 0;
-  const long long n_sums = n_acc + n_mom;
+  const bool radp = n_rec > 0;
+  const long long n_sums = radp ? rec_base + n_rec : n_plain;
+  (void)n_acc;
   // the trace kernel addresses accumulators with 32-bit indices
   if (n_sums >= (long long)kNoSlot)
-    return fail(c, MORAY_EINVAL, "a batch needs fewer than 2^32 - 1 accumulators (cells x groups, + 3 per cell "
+    return fail(c, MORAY_EINVAL, "a batch needs fewer than 2^32 - 1 accumulators (cells x groups, 4 times that "
                                  "with radiation pressure)");
   bool cover = false;                                   // some problem scales its deposits by the covering factor
   for (int i = 0; i < n_probs; ++i) cover = cover || probs[i].params.covering != 0;
@@ -544,14 +555,11 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
     d.sigma32 = (float)Sp.sigma_cm2[K.grp];
     d.four_pi_phi_c = 4.0 * kPiConst * P.params.phi_c;
     d.split_t2_base = P.params.phi_c > 0.0 ? (float)(12.0 / (4.0 * kPiConst * P.params.phi_c)) : FLT_MAX;
-    d.acc_slot = pd.acc_off + (long long)K.grp * pd.n_cells - pd.cell_off;
+    d.acc_stride = (uint32_t)pd.acc_stride;
+    d.acc_slot = pd.acc_off + (long long)pd.acc_stride * ((long long)K.grp * pd.n_cells - pd.cell_off);
     d.problem = K.prob;
     d.covering = P.params.covering != 0;
-    if (pd.mom_off >= 0) {
-      d.mom_slot0 = (uint32_t)(pd.mom_off - pd.cell_off);
-      d.mom_stride = (uint32_t)pd.n_cells;
-      d.mom_scale = Sp.energy_ev[K.grp] * kEvErgConst / kLightCms;
-    }
+    if (pd.acc_stride == 4) d.mom_scale = Sp.energy_ev[K.grp] * kEvErgConst / kLightCms;
     d.root_grid = pd.root_grid;
     d.rnx = grids[pd.root_grid].nx; d.rny = grids[pd.root_grid].ny; d.rnz = grids[pd.root_grid].nz;
     d.rcell_off = grids[pd.root_grid].cell_off;
@@ -772,7 +780,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
         if (fp32) {
           TraceArgs<float> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
-          A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
+          A.kappa = (float*)c->kappa.p; A.acc = (double*)c->acc.p; A.rec_base = (uint32_t)rec_base; A.in = qin; A.out = qout;
           A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.gen = l; A.cin = l; A.cout = l + 1;
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
@@ -781,7 +789,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
-          A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.in = qin; A.out = qout;
+          A.kappa = (double*)c->kappa.p; A.acc = (double*)c->acc.p; A.rec_base = (uint32_t)rec_base; A.in = qin; A.out = qout;
           A.seg_cap = seg_cap; A.nseg = nseg; A.ctr = ctr; A.stats = stats; A.gen = l; A.cin = l; A.cout = l + 1;
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
