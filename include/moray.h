@@ -310,7 +310,7 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
  * c_dt is c dt_P in root cells (c dt_P / dx_cm), > 0; pool_rays (1024 to
  * 2^34) bounds the rays in flight, with up to 63 empty records per wave of
  * each level launch (waves reserve the records of halted rays 64 at a time),
- * and each level's queue; the state holds
+ * and each level's queue (both grow when a step needs more, see moray_td_step); the state holds
  * about 144 bytes of device memory per pool ray (two pools of 32 B, two
  * level queues of 28 B and the 24 B of sort buffers that order the rays in
  * flight, the latter only below 2^32 rays). The covering factor is
@@ -329,8 +329,12 @@ moray_status moray_evolve(moray_ctx* ctx, const moray_problem* prob, unsigned fl
  * this step's k_ph, heating and totals (emitted counts this step's emission;
  * emitted + the previous step's held = absorbed + escaped + truncated + held)
  * and *held (or NULL) the photon rate of the rays in flight after the step.
- * accel must be NULL. MORAY_EQUEUE when the pool or a level queue overflows:
- * the state is then unusable (free it). Not thread-safe per state.
+ * accel must be NULL. When the pool or a level queue overflows, the step
+ * keeps the rays in flight from before it, grows the pools and queues (at
+ * least doubling them, within the context's HBM budget) and runs again;
+ * MORAY_EQUEUE when they cannot grow, with the state as before the step (it
+ * may be retried, e.g. after other buffers were freed). Not thread-safe per
+ * state.
  *
  * moray_td_free: release the state (before its context). */
 typedef struct moray_td moray_td;

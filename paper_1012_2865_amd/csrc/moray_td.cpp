@@ -215,6 +215,91 @@ static hipError_t launch_level(moray_ctx* c, moray_td* t, int l, int seed_lo, in
   return launch_trace_level_halt<R>(c->stream, std::max(1, c->num_cu * c->blocks_per_cu), A, c->cache);
 }
 
+// Doubles the pools, the level queues and the sort buffers of a state whose
+// step overflowed, keeping the rays in flight before the step (pool t->cur,
+// which a step only reads). Fails with MORAY_EQUEUE, the state unchanged,
+// when the doubled buffers do not fit the context's HBM budget.
+static moray_status td_grow(moray_ctx* c, moray_td* t, unsigned long long demand) {
+  // at least double; enough for what the failed step asked for, with room for segment imbalance
+  size_t ncap = t->cap * 2;
+  while ((double)ncap < 1.5 * (double)demand && ncap <= ((size_t)1 << 34)) ncap *= 2;
+  if (ncap > ((size_t)1 << 34)) return fail(c, MORAY_EQUEUE, "the ray pool cannot grow beyond 2^34 rays");
+  const size_t pool_b = 8 + 4 + 8 + 8 + 4, queue_b = 8 + 4 + 8 + 8, sort_b = 8 + 4;
+  size_t sort_tmp = 0;
+  if (ncap < ((size_t)1 << 32) && !hip_ok(c, td_sort_temp_bytes(ncap, &sort_tmp), "sort")) return MORAY_EDEVICE;
+  const size_t nbytes = ncap * (2 * pool_b + 2 * queue_b + (ncap < ((size_t)1 << 32) ? 2 * sort_b : 0)) +
+                        (ncap < ((size_t)1 << 32) ? std::max<size_t>(sort_tmp, 256) : 0);
+  const int a = t->cur;
+  size_t old = t->sort_temp.bytes + t->pix[1 - a].bytes + t->sg[1 - a].bytes + t->r[1 - a].bytes +
+               t->P[1 - a].bytes + t->lev[1 - a].bytes;
+  for (int i = 0; i < 2; ++i)
+    old += t->qpix[i].bytes + t->qsg[i].bytes + t->qr[i].bytes + t->qP[i].bytes + t->keys[i].bytes + t->order[i].bytes;
+  if (c->allocated - old + nbytes + 4096 > c->budget)
+    return fail(c, MORAY_EQUEUE, "the ray pool or a level queue overflowed and cannot double within the HBM budget");
+  // everything but the rays in flight can go first
+  release(c, t->sort_temp);
+  for (int i = 0; i < 2; ++i) {
+    release(c, t->keys[i]);
+    release(c, t->order[i]);
+    release(c, t->qpix[i]); release(c, t->qsg[i]); release(c, t->qr[i]); release(c, t->qP[i]);
+  }
+  release(c, t->pix[1 - a]); release(c, t->sg[1 - a]); release(c, t->r[1 - a]); release(c, t->P[1 - a]);
+  release(c, t->lev[1 - a]);
+  DevBuf np[5];
+  moray_status st;
+  if ((st = ensure(c, np[0], ncap * 8, "ray pool")) || (st = ensure(c, np[1], ncap * 4, "ray pool")) ||
+      (st = ensure(c, np[2], ncap * 8, "ray pool")) || (st = ensure(c, np[3], ncap * 8, "ray pool")) ||
+      (st = ensure(c, np[4], ncap * 4, "ray pool"))) {
+    for (DevBuf& b : np) release(c, b);
+    t->broken = true;
+    return fail(c, MORAY_EQUEUE, "the ray pool overflowed and its doubled buffers could not be allocated");
+  }
+  hipStream_t s = c->stream;
+  const unsigned long long n = t->n_in;
+  if (n && (!hip_ok(c, hipMemcpyAsync(np[0].p, t->pix[a].p, n * 8, hipMemcpyDeviceToDevice, s), "copy") ||
+            !hip_ok(c, hipMemcpyAsync(np[1].p, t->sg[a].p, n * 4, hipMemcpyDeviceToDevice, s), "copy") ||
+            !hip_ok(c, hipMemcpyAsync(np[2].p, t->r[a].p, n * 8, hipMemcpyDeviceToDevice, s), "copy") ||
+            !hip_ok(c, hipMemcpyAsync(np[3].p, t->P[a].p, n * 8, hipMemcpyDeviceToDevice, s), "copy") ||
+            !hip_ok(c, hipMemcpyAsync(np[4].p, t->lev[a].p, n * 4, hipMemcpyDeviceToDevice, s), "copy"))) {
+    t->broken = true;
+    return MORAY_EDEVICE;
+  }
+  if (!hip_ok(c, hipStreamSynchronize(s), "synchronize")) {
+    t->broken = true;
+    return MORAY_EDEVICE;
+  }
+  release(c, t->pix[a]); release(c, t->sg[a]); release(c, t->r[a]); release(c, t->P[a]); release(c, t->lev[a]);
+  t->pix[a] = np[0]; t->sg[a] = np[1]; t->r[a] = np[2]; t->P[a] = np[3]; t->lev[a] = np[4];
+  const int b = 1 - a;
+  for (int i = 0; i < 2; ++i) {
+    if ((i == b && ((st = ensure(c, t->pix[b], ncap * 8, "ray pool")) || (st = ensure(c, t->sg[b], ncap * 4, "ray pool")) ||
+                    (st = ensure(c, t->r[b], ncap * 8, "ray pool")) || (st = ensure(c, t->P[b], ncap * 8, "ray pool")) ||
+                    (st = ensure(c, t->lev[b], ncap * 4, "ray pool")))) ||
+        (st = ensure(c, t->qpix[i], ncap * 8, "ray queue")) || (st = ensure(c, t->qsg[i], ncap * 4, "ray queue")) ||
+        (st = ensure(c, t->qr[i], ncap * 8, "ray queue")) || (st = ensure(c, t->qP[i], ncap * 8, "ray queue"))) {
+      t->broken = true;
+      return fail(c, MORAY_EQUEUE, "the ray pool overflowed and its doubled buffers could not be allocated");
+    }
+  }
+  t->sort_bytes = 0;
+  if (ncap < ((size_t)1 << 32)) {
+    t->sort_bytes = sort_tmp;
+    for (int i = 0; i < 2; ++i)
+      if ((st = ensure(c, t->keys[i], ncap * 8, "sort keys")) || (st = ensure(c, t->order[i], ncap * 4, "sort order"))) {
+        t->broken = true;
+        return st;
+      }
+    if ((st = ensure(c, t->sort_temp, std::max<size_t>(sort_tmp, 256), "sort scratch"))) {
+      t->broken = true;
+      return st;
+    }
+  }
+  t->cap = ncap;
+  t->nseg = queue_segments(ncap);
+  t->seg_cap = ncap / (size_t)t->nseg;
+  return MORAY_OK;
+}
+
 moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob, unsigned flags, int emit,
                            moray_result* out, double* held) {
   if (!c) return MORAY_EINVAL;
@@ -238,6 +323,13 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   const int n_sg = t->slots * per;
   const int cur_slot = (int)(t->step % t->slots);
   const double npix0 = std::ldexp(12.0, 2 * P.params.level_init);
+  // what this step changes in the state before it has run (restored when it fails)
+  const long long saved_emit = t->emit_step[cur_slot];
+  const std::vector<double> saved_P0(t->P0.begin() + (size_t)cur_slot * per, t->P0.begin() + (size_t)(cur_slot + 1) * per);
+  auto restore = [&]() {
+    t->emit_step[cur_slot] = saved_emit;
+    std::copy(saved_P0.begin(), saved_P0.end(), t->P0.begin() + (size_t)cur_slot * per);
+  };
   if (emit) {
     t->emit_step[cur_slot] = t->step;
     for (int s = 0; s < t->n_src; ++s)
@@ -247,6 +339,9 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
     t->emit_step[cur_slot] = -1;          // an older batch here has left the box
   }
 
+  // An overflow leaves the rays in flight before the step untouched: the
+  // buffers double and the step runs again.
+  for (int attempt = 0;; ++attempt) {
   // tables: the root grid, then its children (cells numbered in grid order)
   std::vector<GridDev> gds(P.n_grids);
   long long steps_bound = 16;
@@ -386,11 +481,27 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
       !hip_ok(c, hipMemcpyAsync(hpart, t->partial.p, t->fb.size() * 8, hipMemcpyDeviceToHost, s), "copy") ||
       !hip_ok(c, hipStreamSynchronize(s), "synchronize"))
     return MORAY_EDEVICE;
-  if (hctr->err & kErrBadInput) return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
-  if (hctr->err & (kErrOverflow | kErrInternal)) {
+  if (hctr->err & kErrBadInput) {
+    restore();
+    return fail(c, MORAY_EINVAL, "a density or neutral fraction is negative, non-finite or x_HI > 1");
+  }
+  if (hctr->err & kErrInternal) {
     t->broken = true;
-    if (hctr->err & kErrInternal) return fail(c, MORAY_EINTERNAL, "a ray exceeded its step bound");
-    return fail(c, MORAY_EQUEUE, "the ray pool or a level queue overflowed: create the state with more pool_rays");
+    return fail(c, MORAY_EINTERNAL, "a ray exceeded its step bound");
+  }
+  if (hctr->err & kErrOverflow) {
+    // what the step asked for: the halt list's records and the largest level queue's slots
+    unsigned long long demand = hctr->halt_count;
+    for (int l = 0; l < kLevels; ++l) {
+      unsigned long long n = 0;
+      for (int sgi = 0; sgi < t->nseg; ++sgi) n += hctr->count[l][sgi];
+      demand = std::max(demand, n);
+    }
+    const moray_status gs = attempt < 8 ? td_grow(c, t, demand)
+                                        : fail(c, MORAY_EQUEUE, "the ray pool or a level queue overflowed eight times");
+    if (gs == MORAY_OK) continue;
+    if (!t->broken) restore();
+    return gs;
   }
   // results of the step
   moray_result& Rr = *out;
@@ -446,4 +557,5 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   if (held) *held = h;
   c->err = "no error";
   return MORAY_OK;
+  }  // attempts
 }

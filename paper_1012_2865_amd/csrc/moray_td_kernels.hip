@@ -9,7 +9,7 @@
 #include "moray_internal.h"
 
 #include <hip/hip_runtime.h>
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 namespace moray {
 
@@ -68,9 +68,8 @@ __global__ __launch_bounds__(256) void prefill_sorted_kernel(RayQueue pool, cons
 
 hipError_t td_sort_temp_bytes(unsigned long long cap, size_t* bytes) {
   *bytes = 0;
-  return hipcub::DeviceRadixSort::SortPairs(nullptr, *bytes, (const unsigned long long*)nullptr,
-                                            (unsigned long long*)nullptr, (const uint32_t*)nullptr,
-                                            (uint32_t*)nullptr, cap, 0, 64, (hipStream_t)0);
+  return rocprim::radix_sort_pairs(nullptr, *bytes, (const unsigned long long*)nullptr, (unsigned long long*)nullptr,
+                                   (const uint32_t*)nullptr, (uint32_t*)nullptr, cap, 0u, 64u, (hipStream_t)0);
 }
 
 hipError_t launch_td_sort(hipStream_t s, int num_cu, const RayQueue& pool, const int* lev, unsigned long long n,
@@ -79,9 +78,9 @@ hipError_t launch_td_sort(hipStream_t s, int num_cu, const RayQueue& pool, const
   if (n == 0) return hipSuccess;
   const int end_bit = 5 + tree_bits + pix_bits;
   size_t need = 0;
-  hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, need, (const unsigned long long*)nullptr,
-                                                    (unsigned long long*)nullptr, (const uint32_t*)nullptr,
-                                                    (uint32_t*)nullptr, n, 0, end_bit, s);
+  hipError_t e = rocprim::radix_sort_pairs(nullptr, need, (const unsigned long long*)nullptr,
+                                           (unsigned long long*)nullptr, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                           n, 0u, (unsigned)end_bit, s);
   if (e != hipSuccess) return e;
   if (need > temp_bytes) return hipErrorInvalidValue;
   unsigned long long blocks = (n + 255) / 256;
@@ -91,8 +90,8 @@ hipError_t launch_td_sort(hipStream_t s, int num_cu, const RayQueue& pool, const
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   size_t tb = temp_bytes;
-  return hipcub::DeviceRadixSort::SortPairs(temp, tb, (const unsigned long long*)keys_in, keys_out,
-                                            (const uint32_t*)idx_in, idx_out, n, 0, end_bit, s);
+  return rocprim::radix_sort_pairs(temp, tb, (const unsigned long long*)keys_in, keys_out, (const uint32_t*)idx_in,
+                                   idx_out, n, 0u, (unsigned)end_bit, s);
 }
 
 hipError_t launch_prefill_sorted(hipStream_t s, int num_cu, const RayQueue& pool, const uint32_t* order,

@@ -9,8 +9,12 @@ oracle's orc_trace_td on the same seeded inputs, through the C ABI:
 * a pulse (emission in the first step only) against the oracle's pulse, and
   a root grid with a refined child holding a source;
 * c dt_P beyond the box: one step equals moray_trace;
-* a pool too small fails the step with MORAY_EQUEUE and the state refuses
-  further steps; bad arguments are rejected.
+* a pool too small grows (doubling, within the context's HBM budget) and
+  the step runs again from the rays in flight before it, with the results of
+  a state created large enough; when the budget leaves no room to grow, the
+  step fails with MORAY_EQUEUE and leaves the state as it was (a later step
+  fails the same way rather than on a broken state); bad arguments are
+  rejected.
 """
 import numpy as np
 import pytest
@@ -133,17 +137,18 @@ def test_overflow_and_bad_arguments():
             with pytest.raises(M.MorayError) as e:
                 M.moray_td_create(ctx, dev, c_dt, pool)
             assert e.value.status == M.MORAY_EINVAL
-        td = M.moray_td_create(ctx, dev, 4.0, 1024)        # far too small for this problem's rays
+        # a context whose HBM budget holds the small state but not a doubled one
+        tight = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64, hbm_budget_bytes=2 << 20)
+        td = M.moray_td_create(tight, dev, 4.0, 1024)      # far too small for this problem's rays
         try:
-            with pytest.raises(M.MorayError) as e:
-                for _ in range(4):
-                    M.moray_td_step(ctx, td, dev)
-            assert e.value.status == M.MORAY_EQUEUE
-            with pytest.raises(M.MorayError) as e:
-                M.moray_td_step(ctx, td, dev)
-            assert e.value.status == M.MORAY_EINVAL
+            for _ in range(2):
+                with pytest.raises(M.MorayError) as e:
+                    M.moray_td_step(tight, td, dev)
+                assert e.value.status == M.MORAY_EQUEUE
+                assert "budget" in str(e.value)
         finally:
-            M.moray_td_free(ctx, td)
+            M.moray_td_free(tight, td)
+            M.moray_free(tight)
         td = M.moray_td_create(ctx, dev, 4.0, 1 << 16)
         try:
             other = M.problem_to_device(W.lognormal_problem(92, 5, 16, 2, mean=1e-4))
@@ -153,4 +158,32 @@ def test_overflow_and_bad_arguments():
         finally:
             M.moray_td_free(ctx, td)
     finally:
+        M.moray_free(ctx)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_small_pool_grows_and_matches_a_large_one(precision):
+    """A pool of 1024 rays overflows at once and doubles, step after step, as
+    the rays in flight grow; every step equals the same step of a state
+    created with room for them (counts exactly, fields to summation order)."""
+    dev = M.problem_to_device(_problem(4))
+    ctx = M.moray_init(device=0, precision=precision)
+    big = small = None
+    try:
+        big = M.moray_td_create(ctx, dev, 4.0, 1 << 21)
+        small = M.moray_td_create(ctx, dev, 4.0, 1024)
+        for step in range(6):
+            want, hw = M.moray_td_step(ctx, big, dev)
+            got, hg = M.moray_td_step(ctx, small, dev)
+            for k in ("segments", "splits", "rays_escaped", "rays_truncated", "rays_seeded"):
+                assert got[k] == want[k], (step, k, got[k], want[k])
+            rel, _ = _rel(got["k_ph"][0], _np(want["k_ph"][0]))
+            print(f"[td grow p{precision} step {step}] k_ph max rel vs large pool {rel:.2e}, held {hg:.4e}/{hw:.4e}",
+                  flush=True)
+            assert rel <= 1e-9
+            assert hg == pytest.approx(hw, rel=1e-12)
+    finally:
+        for td in (big, small):
+            if td:
+                M.moray_td_free(ctx, td)
         M.moray_free(ctx)
