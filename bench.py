@@ -46,19 +46,133 @@ COPY_BYTES = 1 << 30                              # calibration copy of the coun
 MICROBENCH_LIB = os.path.join(ROOT, "paper_1012_2865_amd", "libmoray_microbench.so")
 
 
-def _device_peaks():
-    """Scattered and coherent float64 atomic rates and copy bandwidth measured
-    on the device by the project's microbenchmark (None when it is not built)."""
+MB_KINDS = {"atomics": 0, "copy": 1, "copy_nt": 2, "read": 3, "read_nt": 4}
+MB_MIB = 1 << 20
+
+
+def _microbench():
     import ctypes
     if not os.path.exists(MICROBENCH_LIB):
         return None
     lib = ctypes.CDLL(MICROBENCH_LIB)
     lib.moray_microbench.argtypes = [ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
     lib.moray_microbench.restype = ctypes.c_int
+    lib.moray_microbench_case.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_ulonglong, ctypes.c_int, ctypes.c_int,
+                                          ctypes.c_int, ctypes.POINTER(ctypes.c_double)]
+    lib.moray_microbench_case.restype = ctypes.c_int
+    return lib
+
+
+def _microbench_sweep(lib):
+    """Every point of the device-peak sweep: float64 atomics over array sizes
+    128 MiB - 1 GiB, 2-32 blocks per CU, 16-256 adds per thread, with every
+    lane scattered (runs of 1) and with each wave one run of 64 cells, then
+    the run length 1-64 at the best scattered shape; streaming copies and
+    reads of 512 MiB - 4 GiB (beyond the 256 MiB last-level cache) with 1-16
+    blocks per CU and 1-8 16-byte loads in flight per lane, plain and
+    non-temporal. Returns a list of dicts."""
+    import ctypes
+    rows = []
+
+    def one(kind, size, bpc, per, group=1):
+        r = ctypes.c_double(0.0)
+        rc = lib.moray_microbench_case(0, MB_KINDS[kind], size, bpc, per, group, ctypes.byref(r))
+        if rc != 0:
+            raise RuntimeError(f"microbenchmark case {kind} {size} {bpc} {per} {group}: error {rc}")
+        rows.append({"kind": kind, "MiB": size // MB_MIB, "blocks_per_cu": bpc, "per_thread": per,
+                     "group": group, "rate": r.value})
+        return r.value
+
+    for group in (1, 64):
+        for size in (128, 256, 512, 1024):
+            for bpc in (2, 4, 8, 16, 32):
+                for per in (16, 64, 256):
+                    one("atomics", size * MB_MIB, bpc, per, group)
+    best = max((r for r in rows if r["group"] == 1), key=lambda r: r["rate"])
+    for group in (2, 4, 8, 16, 32):
+        one("atomics", best["MiB"] * MB_MIB, best["blocks_per_cu"], best["per_thread"], group)
+    for kind in ("copy", "copy_nt", "read", "read_nt"):
+        for size in (512, 1024, 2048, 4096):
+            for bpc in (1, 2, 4, 8, 16):
+                for per in (1, 2, 4, 8):
+                    one(kind, size * MB_MIB, bpc, per)
+    return rows
+
+
+def _device_peaks(sweep=True):
+    """Float64 atomic rates and streaming bandwidths measured on the device
+    by the project's microbenchmark: with `sweep`, the maximum of every
+    pattern over the sweep and the shape that reached it (the fixed shape of
+    `moray_microbench` is reported beside it); None when it is not built."""
+    import ctypes
+    lib = _microbench()
+    if lib is None:
+        return None
     out = (ctypes.c_double * 3)()
     if lib.moray_microbench(0, out) != 0:
         return None
-    return {"atomics_scattered": out[0], "atomics_coherent": out[1], "copy_GBs": out[2]}
+    fixed = {"atomics_scattered": out[0], "atomics_coherent": out[1], "copy_GBs": out[2]}
+    if not sweep:
+        return fixed
+    rows = _microbench_sweep(lib)
+
+    def top(pred):
+        r = max((r for r in rows if pred(r)), key=lambda r: r["rate"])
+        return r["rate"], {k: r[k] for k in ("MiB", "blocks_per_cu", "per_thread", "group")}
+
+    sc, sc_at = top(lambda r: r["kind"] == "atomics" and r["group"] == 1)
+    co, co_at = top(lambda r: r["kind"] == "atomics")
+    cp, cp_at = top(lambda r: r["kind"] in ("copy", "copy_nt"))
+    rd, rd_at = top(lambda r: r["kind"] in ("read", "read_nt"))
+    return {"atomics_scattered": sc, "atomics_coherent": co, "copy_GBs": cp, "read_GBs": rd,
+            "at": {"atomics_scattered": sc_at, "atomics_coherent": co_at, "copy_GBs": cp_at, "read_GBs": rd_at},
+            "fixed_shape": fixed, "sweep_points": len(rows),
+            "source": "maxima of the microbenchmark sweep run in this process"}
+
+
+def _microbench_table():
+    """The sweep condensed to markdown (what profiles/ keeps): the best rate of
+    every pattern and the shape that reached it, the scattered-atomic rate by
+    array size and blocks per CU, and each streaming pattern by blocks per CU
+    and loads in flight."""
+    lib = _microbench()
+    if lib is None:
+        raise SystemExit("libmoray_microbench.so is not built")
+    rows = _microbench_sweep(lib)
+
+    def best(pred):
+        sel = [r for r in rows if pred(r)]
+        return max(sel, key=lambda r: r["rate"]) if sel else None
+
+    out = [f"{len(rows)} sweep points.", "", "| pattern | best rate | MiB | blocks/CU | per thread | run |",
+           "|---|---:|---:|---:|---:|---:|"]
+    for run in (1, 2, 4, 8, 16, 32, 64):
+        b = best(lambda r: r["kind"] == "atomics" and r["group"] == run)
+        if b:
+            out.append(f"| float64 atomics, runs of {run} | {b['rate']:.3e}/s | {b['MiB']} | {b['blocks_per_cu']} | "
+                       f"{b['per_thread']} | {run} |")
+    for kind in ("copy", "copy_nt", "read", "read_nt"):
+        b = best(lambda r: r["kind"] == kind)
+        out.append(f"| {kind} | {b['rate']:.0f} GB/s | {b['MiB']} | {b['blocks_per_cu']} | {b['per_thread']} | |")
+    sizes = sorted({r["MiB"] for r in rows if r["kind"] == "atomics"})
+    bpcs = sorted({r["blocks_per_cu"] for r in rows if r["kind"] == "atomics"})
+    out += ["", "Scattered float64 atomics (runs of 1), best over adds per thread, 1e10/s:", "",
+            "| MiB \\ blocks/CU | " + " | ".join(str(b) for b in bpcs) + " |", "|---|" + "---:|" * len(bpcs)]
+    for m in sizes:
+        cells = [best(lambda r: r["kind"] == "atomics" and r["group"] == 1 and r["MiB"] == m and
+                      r["blocks_per_cu"] == b) for b in bpcs]
+        out.append(f"| {m} | " + " | ".join(f"{c['rate'] / 1e10:.2f}" if c else "" for c in cells) + " |")
+    for kind in ("copy", "copy_nt", "read", "read_nt"):
+        pers = sorted({r["per_thread"] for r in rows if r["kind"] == kind})
+        bp = sorted({r["blocks_per_cu"] for r in rows if r["kind"] == kind})
+        out += ["", f"{kind}, best over array sizes, GB/s (rows: blocks per CU; columns: 16-byte loads in flight "
+                    f"per lane):", "", "| blocks/CU \\ loads | " + " | ".join(str(p) for p in pers) + " |",
+                "|---|" + "---:|" * len(pers)]
+        for b in bp:
+            cells = [best(lambda r: r["kind"] == kind and r["blocks_per_cu"] == b and r["per_thread"] == p)
+                     for p in pers]
+            out.append(f"| {b} | " + " | ".join(f"{c['rate']:.0f}" for c in cells) + " |")
+    print("\n".join(out))
 
 
 def _workload(name):
@@ -197,7 +311,7 @@ def _counter_pass(workload, variant="plain", settings=None):
     b = torch.empty_like(a)
     b.copy_(a)
     torch.cuda.synchronize()
-    peaks = _device_peaks()     # its scattered-atomics kernel calibrates the atomic counter
+    peaks = _device_peaks(sweep=False)     # its scattered-atomics kernel calibrates the atomic counter
     print(json.dumps({"counter_pass": config["workload"], "variant": variant, "settings": settings,
                       "segments": sum(r["segments"] for r in res),
                       "launches_per_trace": res[0]["trace_launches"], "copy_bytes": COPY_BYTES,
@@ -727,6 +841,8 @@ def main():
                     help="print the radiation-pressure measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
+    ap.add_argument("--microbench-table", action="store_true",
+                    help="run the device-peak microbenchmark sweep, print its summary as markdown and exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
     ap.add_argument("--counter-variant", choices=("plain", "radpres", "td"), default="plain",
@@ -754,6 +870,9 @@ def main():
               f"--gpus {args.gpus} is not supported)", file=sys.stderr)
         sys.exit(2)
 
+    if args.microbench_table:
+        _microbench_table()
+        return
     if args.counter_pass:
         _counter_pass(args.workload, args.counter_variant, settings)
         return

@@ -144,3 +144,4 @@ def test_microbenchmark_library_exports_its_entry_point():
         pytest.skip("libmoray_microbench.so is not built (run __graft_entry__.build())")
     out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
     assert re.search(r" T moray_microbench$", out, flags=re.M)
+    assert re.search(r" T moray_microbench_case$", out, flags=re.M)
