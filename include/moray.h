@@ -220,6 +220,25 @@ typedef struct {
 moray_status moray_autotune(moray_ctx* ctx, const moray_problem* probs, int n_probs, unsigned flags,
                             int max_trials, moray_tune_result* out);
 
+/* Persistent autotune cache (not part of the paper's method): moray_autotune
+ * whose outcome is kept in the text file `path` (host path, NUL-terminated).
+ * The key is the library version, the device's architecture name and compute
+ * units, the context's precision and deposit-table setting, and a hash of the
+ * batch's shape (grid sizes and nesting, source and group counts, the trace
+ * parameters; not the field values, source positions or photon rates). On a
+ * hit (the last valid line with this key) the context takes the recorded
+ * settings without timing anything, `out` receives them with the recorded
+ * timings, and *from_cache is set to 1. On a miss the file is opened for
+ * appending first (MORAY_EINVAL, nothing changed, when it cannot be), the
+ * batch is tuned as by moray_autotune, and one line is appended; if that
+ * line cannot be written the context keeps the new settings and the call
+ * returns MORAY_EINVAL. Lines that do not parse or whose settings are out of
+ * range for the device are ignored. Concurrent processes may share a file:
+ * each appends whole lines. from_cache may be NULL. Other errors as in
+ * moray_autotune. */
+moray_status moray_autotune_cached(moray_ctx* ctx, const char* path, const moray_problem* probs, int n_probs,
+                                   unsigned flags, int max_trials, moray_tune_result* out, int* from_cache);
+
 /* Settings of moray_equilibrate. */
 typedef struct {
   double alpha_b;             /* case-B recombination coefficient, cm^3/s (2.59e-13 at 1e4 K), > 0 */

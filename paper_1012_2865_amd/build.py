@@ -44,7 +44,7 @@ def build_library(out: str = LIB) -> str:
     os.makedirs(objdir, exist_ok=True)
     objs = []
     for src in ("moray_kernels.hip", "moray_equilibrium.hip", "moray_runtime.cpp", "moray_serve.cpp", "moray_td.cpp",
-                "moray_td_kernels.hip", "moray_noalloc.hip"):
+                "moray_td_kernels.hip", "moray_noalloc.hip", "moray_tune_cache.cpp"):
         obj = os.path.join(objdir, src.rsplit(".", 1)[0] + ".o")
         lang = ["-x", "hip"] if src.endswith(".hip") else []
         _run([HIPCC] + COMMON + lang + ["-c", os.path.join(CSRC, src), "-o", obj])

@@ -303,7 +303,7 @@ double level_rays_bound(const moray_problem& P) {
 
 extern "C" {
 
-const char* moray_version(void) { return "0.1.0"; }
+const char* moray_version(void) { return "0.2.0"; }
 
 namespace {
 // why the last moray_init on this thread returned no context
@@ -327,7 +327,10 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   int n = 0;
   hipError_t he = hipGetDeviceCount(&n);
   if (he != hipSuccess || n < 1)
-    return init_fail(MORAY_EDEVICE, std::string("no usable GPU: hipGetDeviceCount: ") + hipGetErrorString(he));
+    return init_fail(MORAY_EDEVICE, std::string("no usable GPU: hipGetDeviceCount: ") + hipGetErrorString(he) +
+                                        " (if this process ran a many-threaded OpenMP region before its first HIP "
+                                        "call, create the context before that region: such a first HIP "
+                                        "initialisation has been seen to report no device)");
   if (p->device < 0 || p->device >= n) return init_fail(MORAY_EINVAL, "device ordinal out of range");
   if ((he = hipSetDevice(p->device)) != hipSuccess)
     return init_fail(MORAY_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he));

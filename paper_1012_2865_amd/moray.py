@@ -11,7 +11,7 @@ from __future__ import annotations
 
 import ctypes
 import os
-from typing import List, Sequence
+from typing import List, Optional, Sequence
 
 import numpy as np
 
@@ -94,7 +94,8 @@ class TuneResult(ctypes.Structure):
                 ("trials", ctypes.c_int)]
 
 
-ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_equilibrate", "moray_evolve",
+ABI_FUNCTIONS = ("moray_init", "moray_trace", "moray_autotune", "moray_autotune_cached", "moray_equilibrate",
+                 "moray_evolve",
                  "moray_td_create", "moray_td_step", "moray_td_free", "moray_trace_async", "moray_query",
                  "moray_set_deadline", "moray_cancel", "moray_trace_noalloc", "moray_free", "moray_last_error",
                  "moray_version")
@@ -119,6 +120,10 @@ def load_library(path: str = LIB_PATH):
         lib.moray_autotune.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_int, ctypes.c_uint,
                                        ctypes.c_int, ctypes.POINTER(TuneResult)]
         lib.moray_autotune.restype = ctypes.c_int
+        lib.moray_autotune_cached.argtypes = [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(Problem), ctypes.c_int,
+                                              ctypes.c_uint, ctypes.c_int, ctypes.POINTER(TuneResult),
+                                              ctypes.POINTER(ctypes.c_int)]
+        lib.moray_autotune_cached.restype = ctypes.c_int
         lib.moray_equilibrate.argtypes = [ctypes.c_void_p, ctypes.POINTER(Problem), ctypes.c_uint,
                                           ctypes.POINTER(EquilibriumParams), ctypes.c_void_p, ctypes.POINTER(Result),
                                           ctypes.POINTER(ctypes.c_int)]
@@ -349,15 +354,27 @@ def moray_trace_noalloc(ctx, problems: Sequence, outputs, out_on_device: bool = 
     return _unpack(results, outs, want_escaped_sg)
 
 
-def moray_autotune(ctx, problems: Sequence, max_trials: int = 0) -> dict:
-    """Pick the fastest launch settings for this batch and keep them in the context."""
+def moray_autotune(ctx, problems: Sequence, max_trials: int = 0, cache_path: Optional[str] = None) -> dict:
+    """Pick the fastest launch settings for this batch and keep them in the
+    context. With `cache_path`, through the persistent cache file
+    (moray_autotune_cached): the result then has "from_cache"."""
     lib = load_library()
     cprobs, results, keep, outs, flags = _marshal(problems, True, False)
     r = TuneResult()
-    rc = lib.moray_autotune(ctx, cprobs, len(problems), flags, int(max_trials), ctypes.byref(r))
+    if cache_path is None:
+        rc = lib.moray_autotune(ctx, cprobs, len(problems), flags, int(max_trials), ctypes.byref(r))
+        hit = None
+    else:
+        h = ctypes.c_int(0)
+        rc = lib.moray_autotune_cached(ctx, os.fsencode(cache_path), cprobs, len(problems), flags, int(max_trials),
+                                       ctypes.byref(r), ctypes.byref(h))
+        hit = bool(h.value)
     if rc != MORAY_OK:
         raise MorayError(rc, moray_last_error(ctx))
-    return {name: getattr(r, name) for name, _ in TuneResult._fields_}
+    out = {name: getattr(r, name) for name, _ in TuneResult._fields_}
+    if hit is not None:
+        out["from_cache"] = hit
+    return out
 
 
 def _x64_buffer(problem):

@@ -49,6 +49,7 @@ int main() {
   CHECK(moray_cancel(nullptr, 1) == MORAY_EINVAL);
   CHECK(moray_set_deadline(nullptr, 1, 1.0) == MORAY_EINVAL);
   CHECK(moray_autotune(nullptr, nullptr, 1, 0, 0, nullptr) == MORAY_EINVAL);
+  CHECK(moray_autotune_cached(nullptr, "x", nullptr, 1, 0, 0, nullptr, nullptr) == MORAY_EINVAL);
   CHECK(moray_td_create(nullptr, nullptr, 1.0, 4096, nullptr) == MORAY_EINVAL);
   moray_free(nullptr);
 

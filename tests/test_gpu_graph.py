@@ -8,6 +8,10 @@
   changed in place between replays.
 * moray_autotune picks settings from its candidate lists, and solves with
   them still match the oracle-checked default settings exactly in counts.
+* moray_autotune_cached: a miss tunes and appends one line; a new context
+  (a later process) takes the same settings from the file without timing;
+  another batch shape misses; malformed or out-of-range lines are ignored;
+  an unwritable path fails before anything changes.
 """
 import numpy as np
 import pytest
@@ -86,6 +90,46 @@ def test_autotune_settings_and_results():
     finally:
         M.moray_free(ctx)
         M.moray_free(base)
+
+
+def test_autotune_cache_file(tmp_path):
+    probs = [M.problem_to_device(W.lognormal_problem(97, 2 + i, n, s))
+             for i, (n, s) in enumerate([(48, 3), (32, 2)])]
+    other = [M.problem_to_device(W.lognormal_problem(97, 9, 40, 1))]
+    path = tmp_path / "tune.txt"
+    path.write_text("not a tuning line\n")
+    ctxs = [M.moray_init(device=0, precision=M.MORAY_FP32_ACC64) for _ in range(3)]
+    try:
+        a = M.moray_autotune(ctxs[0], probs, max_trials=4, cache_path=str(path))
+        assert a["from_cache"] is False and 1 <= a["trials"] <= 4
+        lines = path.read_text().splitlines()
+        assert len(lines) == 2 and lines[1].startswith("moray-tune-1 ")
+        b = M.moray_autotune(ctxs[1], probs, cache_path=str(path))
+        assert b["from_cache"] is True
+        for k in ("chunk_rays", "refill_lanes", "reserve_rays", "waves_per_cu", "trials"):
+            assert b[k] == a[k], k
+        assert b["best_ms"] == pytest.approx(a["best_ms"], rel=1e-5)
+        # the cached settings are the ones the context now runs with: same counts as the tuned context
+        want, got = M.moray_trace(ctxs[0], probs), M.moray_trace(ctxs[1], probs)
+        for i in range(len(probs)):
+            _cmp(got[i], want[i], f"cached p{i}")
+        # an out-of-range line with the same key appended later is ignored
+        f = lines[1].split(" ")
+        bad = " ".join(f[:7] + ["512", "99", "0", "12"] + f[11:])
+        with open(path, "a") as fh:
+            fh.write(bad + "\n")
+        c = M.moray_autotune(ctxs[1], probs, cache_path=str(path))
+        assert c["from_cache"] is True and c["refill_lanes"] == a["refill_lanes"]
+        # another shape misses and appends its own line
+        d = M.moray_autotune(ctxs[2], other, max_trials=2, cache_path=str(path))
+        assert d["from_cache"] is False
+        assert len(path.read_text().splitlines()) == 4
+        with pytest.raises(M.MorayError) as e:
+            M.moray_autotune(ctxs[2], other, cache_path=str(tmp_path / "no_such_dir" / "t.txt"))
+        assert e.value.status == M.MORAY_EINVAL
+    finally:
+        for c in ctxs:
+            M.moray_free(c)
 
 
 def test_failed_capture_falls_back_to_eager(monkeypatch):

@@ -59,7 +59,8 @@ def test_library_host_code_under_sanitizers():
     with tempfile.TemporaryDirectory() as d:
         built = []
         for src in (os.path.join(CSRC, "moray_runtime.cpp"), os.path.join(CSRC, "moray_serve.cpp"),
-                    os.path.join(CSRC, "moray_td.cpp"), os.path.join(ROOT, "tests", "sanitize_runtime.cpp")):
+                    os.path.join(CSRC, "moray_td.cpp"), os.path.join(CSRC, "moray_tune_cache.cpp"),
+                    os.path.join(ROOT, "tests", "sanitize_runtime.cpp")):
             o = os.path.join(d, os.path.basename(src) + ".o")
             rc, _, err = _run([HIPCC] + common + ["-c", src, "-o", o])
             assert rc == 0, err
