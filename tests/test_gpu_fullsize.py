@@ -1,10 +1,15 @@
-"""Parity at the benchmark sizes, where the oracle cannot trace everything.
+"""Properties that hold at any size, checked at the benchmark sizes (the
+element-wise oracle comparisons of the same workloads are in
+test_gpu_bench_configs.py: the whole 128^3 workload, all 64 batched problems,
+10-source subsets of the nested workload).
 
 * Nested 256^3 root + 128^3 child, 1000 clustered sources, 4 groups: a
   2-source subset against the FP64 oracle (per-cell bars as elsewhere), and
   at full size photon conservation, the integer ray ledger and linearity in
   the sources -- k_ph of all sources equals the sum over two disjoint halves
-  (each cell receives the same deposits, summed in another order).
+  (each cell receives the same deposits, summed in another order). The
+  oracle would take minutes on all 1000 sources, so the whole workload is
+  checked through these properties.
 * Lognormal 128^3, 16 sources: linearity over four disjoint quarters at full
   size, in both precisions.
 """

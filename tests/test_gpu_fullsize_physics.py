@@ -6,7 +6,9 @@ its maximum):
 * the covering-factor correction (section 2.3) on the whole workload;
 * the radiation-pressure acceleration (section 2.5.4) on the whole workload;
 * time-dependent rays (section 2.1) on a two-source subset for three steps
-  of c dt_P = 32 cells (the oracle's time-dependent step runs on one thread);
+  of c dt_P = 32 cells (the oracle's time-dependent step runs on one thread),
+  and on all 16 sources at c dt_P = 16 cells from a pool of 2^22 rays, which
+  overflows and grows, against a state created with room for every ray;
 * the equilibrium iteration's first two updates from neutral gas on the
   whole workload, against the oracle's harness: the neutral fraction within
   1e-4 (mixed) and 1e-8 (float64);
@@ -84,6 +86,28 @@ def test_time_dependent_rays_at_full_size(ctx):
             assert held == pytest.approx(ref["held"], rel=1e-4)
     finally:
         M.moray_td_free(ctx, td)
+
+
+def test_time_dependent_pool_grows_at_full_size(ctx):
+    dev = M.problem_to_device(W.config1())
+    small = big = None
+    try:
+        big = M.moray_td_create(ctx, dev, 16.0, 1 << 27)
+        small = M.moray_td_create(ctx, dev, 16.0, 1 << 22)
+        for step in range(4):
+            want, hw = M.moray_td_step(ctx, big, dev)
+            got, hg = M.moray_td_step(ctx, small, dev)
+            for k in ("segments", "splits", "rays_escaped", "rays_truncated", "rays_seeded"):
+                assert got[k] == want[k], (step, k, got[k], want[k])
+            rel, absr = _rel(got["k_ph"][0], _np(want["k_ph"][0]))
+            print(f"[td 128^3 all sources, c dt = 16 cells, step {step}] k_ph vs large pool: max rel {rel:.2e}; "
+                  f"held {hg:.4e} / {hw:.4e}", flush=True)
+            assert rel <= 1e-9 and absr <= 1e-9
+            assert hg == pytest.approx(hw, rel=1e-12)
+    finally:
+        for td in (small, big):
+            if td:
+                M.moray_td_free(ctx, td)
 
 
 @pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
