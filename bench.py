@@ -841,6 +841,8 @@ def main():
                     help="print the radiation-pressure measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
+    ap.add_argument("--no-microbench", action="store_true",
+                    help="skip the device-peak sweep (no atomic or copy peaks in the line)")
     ap.add_argument("--microbench-table", action="store_true",
                     help="run the device-peak microbenchmark sweep, print its summary as markdown and exit")
     ap.add_argument("--counter-pass", action="store_true",
@@ -899,7 +901,7 @@ def main():
         return
 
     threads = max(1, min(args.cpu_threads, os.cpu_count() or 1))
-    peaks = _device_peaks()
+    peaks = None if args.no_microbench else _device_peaks()
     problems, config = _workload(args.workload)
     dev = [M.problem_to_device(p) for p in problems]
     torch.cuda.synchronize()
