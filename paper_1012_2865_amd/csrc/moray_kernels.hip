@@ -148,6 +148,13 @@ __device__ __forceinline__ int cell_rule(double x, double d) { return d >= 0.0 ?
 __device__ __forceinline__ int floor_half(int c) { return c >= 0 ? c / 2 : -((-c + 1) / 2); }
 template <typename T> __device__ __forceinline__ T sel3(int k, T a, T b, T c) { return k == 0 ? a : (k == 1 ? b : c); }
 
+// One in-order counter covers a wave's vector loads, stores and atomics. A
+// load still in flight where a rare path (a ray start, a grid change, a
+// float64 split re-check) rejoins the hot loop makes the compiler wait at the
+// join for that counter to reach zero, which includes every deposit atomic
+// issued since; those paths therefore finish their own loads before rejoining.
+__device__ __forceinline__ void finish_vector_loads() { __builtin_amdgcn_s_waitcnt(0x0F70); }  // vmcnt(0) alone
+
 // ---------------------------------------------------------------------------
 // Geometry, float64: the definition's expressions (true division, no
 // contraction), so every decision equals the reference's.
@@ -429,6 +436,11 @@ struct Tracer {
   // cell covered by a child: find the new leaf cell. Returns false when the
   // ray left the root grid.
   __device__ bool settle(Ray<R>& L, int ax, int dir) const {
+    const bool inside = find_cell(L, ax, dir);
+    finish_vector_loads();
+    return inside;
+  }
+  __device__ bool find_cell(Ray<R>& L, int ax, int dir) const {
     if (L.q == L.root) {
       if ((unsigned)L.c0 >= (unsigned)L.n0 || (unsigned)L.c1 >= (unsigned)L.n1 || (unsigned)L.c2 >= (unsigned)L.n2)
         return false;
@@ -556,6 +568,11 @@ struct Tracer {
   // Float64 re-evaluation of the split test for the current cell, in the
   // canonical form 12 * 4^l < (4 pi phi_c) * u^2, u = t_exit in local cells.
   __device__ bool split_exact(const Ray<R>& L) const {
+    const bool sp = split_exact64(L);
+    finish_vector_loads();
+    return sp;
+  }
+  __device__ bool split_exact64(const Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
     const bool child = L.q != L.root;
     int o[3] = {0, 0, 0};
@@ -1113,6 +1130,14 @@ void trace_level_kernel(TraceArgs<R> a) {
   // time-dependent rays: the wave's reserved block [h_next, h_end) of the
   // halt list, and the rays it halted in this launch
   unsigned long long h_next = 0, h_end = 0, h_count = 0;
+  // the step's two uniform operands, held in vector registers in the float
+  // kernels: their scalar registers are full, and from there the operands
+  // were reloaded (a kernel-argument load and lane reads of spilled scalars)
+  // at every step; the float64 kernels have no vector registers to spare
+  uint64_t kappa_v = (uint64_t)a.kappa;
+  unsigned max_steps_v = a.max_steps;
+  if constexpr (sizeof(R) == 4) asm volatile("" : "+v"(kappa_v), "+v"(max_steps_v));
+  const __attribute__((address_space(1))) R* const kappa_step = (const __attribute__((address_space(1))) R*)kappa_v;
 
   for (;;) {
     if (ended >= 0) {
@@ -1215,6 +1240,7 @@ void trace_level_kernel(TraceArgs<R> a) {
           }
         }
       }
+      finish_vector_loads();
     }
     if (!__ballot(active)) {
       if (drained) break;
@@ -1287,14 +1313,14 @@ void trace_level_kernel(TraceArgs<R> a) {
       if (L.P < L.pmin) {
         ended = 1;
         active = false;
-      } else if (++steps > a.max_steps) {
+      } else if (++steps > max_steps_v) {
         // cell indices move monotonically, so this bound is never reached by a correct trace
         atomicOr(&a.ctr->err, kErrInternal);
         ended = 0;
         active = false;
       } else {
         // the next cell's absorber column is gathered while the deposit is combined
-        knext = ((unsigned)cnew < (unsigned)nax) ? a.kappa[L.lin] : (R)-1;
+        knext = ((unsigned)cnew < (unsigned)nax) ? kappa_step[L.lin] : (R)-1;
         s_ax = ax;
         s_dir = dir;
         moved = true;
@@ -1351,15 +1377,13 @@ void trace_level_kernel(TraceArgs<R> a) {
     } else {
       cache.add(a.acc, dkey, dval, dep, lane);
     }
-    if (moved) {
-      if (knext < (R)0) {
-        if (!T.settle(L, s_ax, s_dir)) {
-          ended = 0;
-          active = false;
-        }
-      } else {
-        L.kap = knext;
-      }
+    // the gathered column is taken on every path, so that no load is in
+    // flight across the loop's back edge
+    const bool kneg = moved && knext < (R)0;
+    L.kap = (moved && !kneg) ? knext : L.kap;
+    if (kneg && !T.settle(L, s_ax, s_dir)) {
+      ended = 0;
+      active = false;
     }
     // bulk writes, only when a buffer is nearly full
     if (stage.count >= kStageFlush) stage.write(a, lane);
