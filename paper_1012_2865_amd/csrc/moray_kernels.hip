@@ -1249,8 +1249,19 @@ void trace_level_kernel(TraceArgs<R> a) {
     // ---- one cell: exit plane, split test, deposit, step ----
     int ax = 0;
     bool split = false;
+    int e_dir = 0, e_cnew = 0, e_lin = 0;
+    bool e_in = false;
+    R kpre = (R)0;
     if (active) {
       ax = L.g.exit_axis();
+      // the next cell is known from the exit axis alone: its column is
+      // gathered now, under the split test, the deposit and its combining
+      // (an index outside the grid reads cell 0 of the batch, unused)
+      e_dir = L.g.dirf(ax) > 0.0f ? 1 : -1;
+      e_cnew = sel3(ax, L.c0, L.c1, L.c2) + e_dir;
+      e_in = (unsigned)e_cnew < (unsigned)sel3(ax, L.n0, L.n1, L.n2);
+      e_lin = L.lin + e_dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
+      kpre = kappa_step[e_in ? e_lin : 0];
       split = T.split_test(L, ax);
     }
     const unsigned long long smask = __ballot(split);
@@ -1269,7 +1280,6 @@ void trace_level_kernel(TraceArgs<R> a) {
     bool dep = false, moved = false;
     uint32_t dkey = 0;
     double dval = 0.0, mval = 0.0;
-    R knext = (R)0;
     int s_ax = 0, s_dir = 0;
     bool halt = false;
     if (active) {
@@ -1302,13 +1312,12 @@ void trace_level_kernel(TraceArgs<R> a) {
     }
     if (active && !(HALT && halt)) {
       // step across the exit face
-      const int dir = L.g.dirf(ax) > 0.0f ? 1 : -1;
-      const int cnew = sel3(ax, L.c0, L.c1, L.c2) + dir;
-      const int nax = sel3(ax, L.n0, L.n1, L.n2);
+      const int dir = e_dir;
+      const int cnew = e_cnew;
       L.c0 = ax == 0 ? cnew : L.c0;
       L.c1 = ax == 1 ? cnew : L.c1;
       L.c2 = ax == 2 ? cnew : L.c2;
-      L.lin += dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
+      L.lin = e_lin;
       L.g.step(ax, cnew);
       if (L.P < L.pmin) {
         ended = 1;
@@ -1319,8 +1328,6 @@ void trace_level_kernel(TraceArgs<R> a) {
         ended = 0;
         active = false;
       } else {
-        // the next cell's absorber column is gathered while the deposit is combined
-        knext = ((unsigned)cnew < (unsigned)nax) ? kappa_step[L.lin] : (R)-1;
         s_ax = ax;
         s_dir = dir;
         moved = true;
@@ -1379,8 +1386,11 @@ void trace_level_kernel(TraceArgs<R> a) {
     }
     // the gathered column is taken on every path, so that no load is in
     // flight across the loop's back edge
-    const bool kneg = moved && knext < (R)0;
-    L.kap = (moved && !kneg) ? knext : L.kap;
+    // the gather completes here, on every path: left in flight across the
+    // loop's back edge it would make the compiler drain the whole counter
+    asm volatile("" ::"v"(kpre));
+    const bool kneg = moved && (!e_in || kpre < (R)0);
+    L.kap = (moved && !kneg) ? kpre : L.kap;
     if (kneg && !T.settle(L, s_ax, s_dir)) {
       ended = 0;
       active = false;
