@@ -1159,7 +1159,7 @@ moray_status moray_autotune(moray_ctx* c, const moray_problem* probs, int n_prob
   };
   std::vector<int> bpcs;
   for (int b = 1; b <= bpc_max; ++b) bpcs.push_back(b);
-  std::vector<Knob> knobs = {{&c->chunk, {128, 256, 512}},
+  std::vector<Knob> knobs = {{&c->chunk, {128, 256, 512, 1024}},
                              {&c->refill, {8, 16, 24, 64}},
                              {&c->reserve_user, {64, 128, 256}},
                              {&c->blocks_per_cu, bpcs}};

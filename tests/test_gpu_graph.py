@@ -79,7 +79,7 @@ def test_autotune_settings_and_results():
         want = M.moray_trace(base, probs)
         r = M.moray_autotune(ctx, probs)
         print(f"autotune: {r}", flush=True)
-        assert r["chunk_rays"] in (128, 256, 512)
+        assert r["chunk_rays"] in (128, 256, 512, 1024)
         assert r["refill_lanes"] in (8, 16, 24, 64)
         assert r["reserve_rays"] in (0, 64, 128, 256)
         assert r["waves_per_cu"] % 4 == 0 and r["waves_per_cu"] >= 4
