@@ -145,3 +145,27 @@ def test_microbenchmark_library_exports_its_entry_point():
     out = subprocess.run(["nm", "-D", "--defined-only", path], capture_output=True, text=True).stdout
     assert re.search(r" T moray_microbench$", out, flags=re.M)
     assert re.search(r" T moray_microbench_case$", out, flags=re.M)
+
+
+def test_prepared_batch_descriptors_match_a_fresh_marshal():
+    """The descriptors a PreparedBatch keeps are those moray_trace builds for
+    the same host problems and buffers (pointers, shapes, sources, spectrum),
+    and its per-grid result views alias the caller's buffers."""
+    import numpy as np
+    from paper_1012_2865_amd import workloads as W
+    probs = [W.config0(), W.lognormal_problem(97, 1, 16, 2)]
+    outs = [(np.zeros(p.grids[0].n_h.size), np.zeros(p.grids[0].n_h.size)) for p in probs]
+    b = M.PreparedBatch(probs, outputs=outs, out_on_device=False)
+    cp, res, keep, o, flags = M._marshal(probs, False, False, outs)
+    assert b.n == 2 and b.flags == flags == 0
+    for i in range(2):
+        P, Q = b.cprobs[i], cp[i]
+        assert (P.n_grids, P.n_sources) == (Q.n_grids, Q.n_sources)
+        assert (P.grids[0].nx, P.grids[0].ny, P.grids[0].nz) == (Q.grids[0].nx, Q.grids[0].ny, Q.grids[0].nz)
+        assert ctypes.cast(P.grids[0].n_h, ctypes.c_void_p).value == ctypes.cast(Q.grids[0].n_h, ctypes.c_void_p).value
+        for k in range(P.n_sources):
+            assert (P.sources[k].x, P.sources[k].ndot) == (Q.sources[k].x, Q.sources[k].ndot)
+        assert P.spectrum[0].n_groups == Q.spectrum[0].n_groups
+        assert b.results[i].k_ph == res[i].k_ph == outs[i][0].ctypes.data
+        view = b.views[i]["k_ph"][0]
+        assert view.shape == probs[i].grids[0].n_h.shape and np.shares_memory(view, outs[i][0])

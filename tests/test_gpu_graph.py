@@ -8,6 +8,8 @@
   changed in place between replays.
 * moray_autotune picks settings from its candidate lists, and solves with
   them still match the oracle-checked default settings exactly in counts.
+* a PreparedBatch (descriptors built once) replays the captured sequence
+  and returns what moray_trace returns for the same inputs.
 * moray_autotune_cached: a miss tunes and appends one line; a new context
   (a later process) takes the same settings from the file without timing;
   another batch shape misses; malformed or out-of-range lines are ignored;
@@ -90,6 +92,26 @@ def test_autotune_settings_and_results():
     finally:
         M.moray_free(ctx)
         M.moray_free(base)
+
+
+def test_prepared_batch_equals_moray_trace():
+    probs = [M.problem_to_device(W.lognormal_problem(97, 20 + i, n, s)) for i, (n, s) in enumerate([(32, 2), (24, 1)])]
+    outs = [(torch.empty(int(p.grids[0].n_h.numel()), dtype=torch.float64, device="cuda"),
+             torch.empty(int(p.grids[0].n_h.numel()), dtype=torch.float64, device="cuda")) for p in probs]
+    eager = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        want = M.moray_trace(eager, probs)
+        batch = M.PreparedBatch(probs, outputs=outs)
+        for call in range(3):
+            got = M.moray_trace_prepared(ctx, batch)
+            assert got[0]["from_graph"] == (1 if call == 2 else 0)
+            for i in range(len(probs)):
+                _cmp(got[i], want[i], f"prepared call {call} p{i}")
+                assert got[i]["k_ph"][0].data_ptr() == outs[i][0].data_ptr()
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(eager)
 
 
 def test_autotune_cache_file(tmp_path):
