@@ -1490,7 +1490,8 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
     if (!(nh >= 0.0f) || !(xh >= 0.0f) || !(xh <= 1.0f) || !isfinite(nh)) atomicOr(&ctr->err, kErrBadInput);
     const double dx_root = G.is_child ? 2.0 * G.dx_cm : G.dx_cm;
     R k = (R)((double)nh * (double)xh * dx_root);
-    if (!G.is_child) {
+    // children follow their root in the grid table
+    if (!G.is_child && g + 1 < n_grids && grids[g + 1].is_child && grids[g + 1].problem == G.problem) {
       // a root cell under a child grid carries -(child + 1)
       const int i = (int)(local % G.nx), j = (int)((local / G.nx) % G.ny), kk = (int)(local / ((long long)G.nx * G.ny));
       for (int q = g + 1; q < n_grids && grids[q].is_child && grids[q].problem == G.problem; ++q) {
