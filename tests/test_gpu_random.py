@@ -6,7 +6,9 @@ plane, edge or vertex, some inside the child; 1-4 groups; seed levels 0-2;
 split thresholds from 1.1 to 25.1 rays per face; level caps 6 or 14;
 truncation at 1e-8 or 1e-3 of the seed rate; media from optically thin to
 thick. Every problem alone in both precisions, and all of them in one
-batched call (mixed precision), each per cell against the oracle. Bars as
+batched call (mixed precision), each per cell against the oracle; the
+covering-factor correction, the radiation-pressure acceleration and
+time-dependent rays on subsets of them. Bars as
 in the other parity tests (tests/checks.py); the mixed-precision counts of
 sources on planes may differ by sub-resolution segments (2e-3 of the
 segments, as for the off-lattice cases).
@@ -94,5 +96,108 @@ def test_random_problems_in_one_batch(cases):
         res = M.moray_trace(ctx, [M.problem_to_device(p) for p, _ in cases])
         for (p, ref), r in zip(cases, res):
             check(r, ref, 1e-4, name=f"{p.name} batched", count_rtol=2e-3)
+    finally:
+        M.moray_free(ctx)
+
+
+def _np(a):
+    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+
+
+def _field_rel(got, want):
+    got, want = _np(got).ravel(), np.asarray(want).ravel()
+    mx = want.max()
+    if mx == 0.0:
+        return 0.0, float(np.abs(got).max())
+    m = want > 1e-6 * mx
+    return float(np.max(np.abs(got[m] - want[m]) / want[m])), float(np.max(np.abs(got - want)) / mx)
+
+
+PRECISIONS = [(M.MORAY_FP32_ACC64, 1e-4, False), (M.MORAY_FP64, 1e-9, True)]
+
+
+@pytest.mark.parametrize("precision,tol,fp64", PRECISIONS)
+def test_random_problems_with_covering_factor(precision, tol, fp64):
+    """The covering-factor correction (section 2.3) on the first 12 random
+    problems: k_ph and heating per cell, escaped photons and (float64)
+    every count; the corrected deposit is not photon-conserving, so the
+    ledger is not held."""
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        for k in range(12):
+            p = _problem(k)
+            p.params = W.Params(**{**p.params.__dict__, "covering": True})
+            ref = O.trace(p, n_threads=THREADS)
+            res = M.moray_trace(ctx, [M.problem_to_device(p)])[0]
+            for q in range(len(p.grids)):
+                for f in ("k_ph", "heating"):
+                    rel, absr = _field_rel(res[f][q], ref[f][q])
+                    assert rel <= tol and absr <= max(tol, 1e-6), (p.name, q, f, rel, absr)
+            T = ref["totals"]
+            assert res["absorbed"] == pytest.approx(T["absorbed"], rel=tol)
+            assert res["escaped"] == pytest.approx(T["escaped"], rel=max(tol, 1e-12), abs=1e-12 * T["emitted"])
+            if fp64:
+                for c in ("segments", "splits", "rays_escaped", "rays_truncated"):
+                    assert res[c] == T[c], (p.name, c)
+    finally:
+        M.moray_free(ctx)
+
+
+@pytest.mark.parametrize("precision,tol,fp64", PRECISIONS)
+def test_random_problems_with_radiation_pressure(precision, tol, fp64):
+    """The radiation-pressure acceleration (section 2.5.4) on the first 12
+    random problems: per cell the vector against the oracle's."""
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        for k in range(12):
+            p = _problem(k)
+            ref = O.trace(p, n_threads=THREADS, want_accel=True)
+            res = M.moray_trace(ctx, [M.problem_to_device(p)], want_accel=True)[0]
+            for q in range(len(p.grids)):
+                a, b = _np(res["accel"][q]), np.asarray(ref["accel"][q])
+                norm = np.linalg.norm(b, axis=0)
+                if norm.max() == 0.0:
+                    assert np.abs(a).max() == 0.0
+                    continue
+                diff = np.linalg.norm(a - b, axis=0)
+                m = norm > 1e-6 * norm.max()
+                rel, absr = float(np.max(diff[m] / norm[m])), float(diff.max() / norm.max())
+                assert rel <= tol and absr <= max(tol, 1e-6), (p.name, q, rel, absr)
+    finally:
+        M.moray_free(ctx)
+
+
+@pytest.mark.parametrize("precision,tol,fp64", PRECISIONS)
+def test_random_problems_time_dependent(precision, tol, fp64):
+    """Time-dependent rays (section 2.1, c dt_P of 1.5-8 root cells) on six
+    random problems, four steps each with a random emission pattern (a
+    pulsed source emits in some steps only): k_ph per cell, the photons
+    held by the rays in flight, and (float64) every count."""
+    ctx = M.moray_init(device=0, precision=precision)
+    try:
+        for k in range(6):
+            p = _problem(k)
+            rng = W.rng_for(90, k, 1)
+            cdt = float(rng.uniform(1.5, 8.0))
+            emits = [True] + [bool(rng.random() < 0.6) for _ in range(3)]
+            dev = M.problem_to_device(p)
+            td = M.moray_td_create(ctx, dev, cdt, 1 << 20)
+            try:
+                rays, held_prev = None, 0.0
+                for step, emit in enumerate(emits):
+                    ref, rays = O.trace_td(p, cdt, rays, emit=emit)
+                    res, held = M.moray_td_step(ctx, td, dev, emit=emit)
+                    T = ref["totals"]
+                    for q in range(len(p.grids)):
+                        rel, absr = _field_rel(res["k_ph"][q], ref["k_ph"][q])
+                        assert rel <= tol and absr <= max(tol, 1e-6), (p.name, step, q, rel, absr)
+                    scale = max(T["emitted"], held_prev, 1.0)
+                    assert held == pytest.approx(ref["held"], rel=tol, abs=1e-12 * scale), (p.name, step)
+                    if fp64:
+                        for c in ("segments", "splits", "rays_escaped", "rays_truncated", "rays_seeded"):
+                            assert res[c] == T[c], (p.name, step, c, res[c], T[c])
+                    held_prev = held
+            finally:
+                M.moray_td_free(ctx, td)
     finally:
         M.moray_free(ctx)
