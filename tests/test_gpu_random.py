@@ -8,7 +8,8 @@ truncation at 1e-8 or 1e-3 of the seed rate; media from optically thin to
 thick. Every problem alone in both precisions, and all of them in one
 batched call (mixed precision), each per cell against the oracle; the
 covering-factor correction, the radiation-pressure acceleration and
-time-dependent rays on subsets of them. Bars as
+time-dependent rays on subsets of them; all of them through the serving
+engine in staggered groups. Bars as
 in the other parity tests (tests/checks.py); the mixed-precision counts of
 sources on planes may differ by sub-resolution segments (2e-3 of the
 segments, as for the off-lattice cases).
@@ -199,5 +200,29 @@ def test_random_problems_time_dependent(precision, tol, fp64):
                     held_prev = held
             finally:
                 M.moray_td_free(ctx, td)
+    finally:
+        M.moray_free(ctx)
+
+
+def test_random_problems_served(cases):
+    """All 24 random problems submitted to the serving engine (continuous
+    batching) in staggered groups of one to four while earlier ones run;
+    every result against the oracle, mixed precision."""
+    import time
+    ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+    try:
+        dev = [M.problem_to_device(p) for p, _ in cases]
+        rng = np.random.default_rng(91)
+        tickets, i = [], 0
+        while i < len(dev):
+            n = int(rng.integers(1, 5))
+            tickets.append((i, M.moray_trace_async(ctx, dev[i:i + n])))
+            i += n
+            time.sleep(float(rng.uniform(0.0, 0.004)))
+        for first, t in tickets:
+            res = M.moray_query(ctx, t, -1)
+            for j, r in enumerate(res):
+                p, ref = cases[first + j]
+                check(r, ref, 1e-4, name=f"{p.name} served", count_rtol=2e-3)
     finally:
         M.moray_free(ctx)
