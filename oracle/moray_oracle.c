@@ -39,6 +39,38 @@
  * exit-axis ties go to the lowest axis; dr = max(0, t_exit - r) and r never
  * decreases; the residual of a ray cut off by p_min_frac is tallied as
  * "truncated" so that absorbed + escaped + truncated = emitted.
+ *
+ * Optically-thin approximation (section 2.4, Eq. optthin; params.tau_thin >
+ * 0). Every ray carries its optical depth tau from the source. In each cell
+ * the ray is thin when tau + tau_cell < tau_thin (tau once it leaves the
+ * cell; strict <). A thin ray
+ *   - is split against phi_thin = min(1, phi_c) rays per cell face instead
+ *     of phi_c: one ray per cell suffices where the gas is thin;
+ *   - removes no photons, so its P stays its unattenuated share P0;
+ *   - sets the cell's rate once per (source, group): the first thin ray of
+ *     that item to leave the cell adds k = sigma P / (Omega_ray r_cell^2) to
+ *     k_ph and k (E - E_ion) to the heating, where Omega_ray = 4 pi / N_pix(l)
+ *     is the ray's solid angle and r_cell the distance (cm) from the source
+ *     to the cell centre, and marks the cell for that item (a byte per cell
+ *     here, one bit per item of a 32-bit field in the paper);
+ *   - in a cell that holds the source (inside or on its boundary, where
+ *     r_cell can vanish), adds the general deposit P (1 - e^-tau_cell) to the
+ *     cell's rate instead, still removing no photons, and marks nothing. (A
+ *     child ray starts at its parent's radius along its own direction, so it
+ *     can enter such a cell at r > 0.)
+ * A ray that is not thin in its cell deposits and attenuates as above and is
+ * never thin again (tau only grows). The thin rates enter k_ph and heating
+ * but not `absorbed`, `energy` or the totals, as no photons are removed for
+ * them; k_ph and heating of a cell without absorbers keep the thin rate.
+ * Readings: the printed Eq. optthin divides by a linear angle and multiplies
+ * by r_cell / r_ray, which does not give a rate; the text says the factor
+ * moves the ray's flux from its exit point to the cell centre, and the flux of
+ * a ray of solid angle Omega at radius r is P / (Omega r^2), so the rate at
+ * the centre is sigma P / (Omega r_cell^2) (dt_P cancels, P being a rate).
+ * Because a thin ray has lost no photons, P / Omega is the same for every thin
+ * ray of one item, so the rate does not depend on which ray reaches the cell
+ * first. The source's own cell and phi_thin are readings of points the paper
+ * leaves open.
  */
 #include "moray_oracle.h"
 
@@ -197,6 +229,13 @@ typedef struct {
   double* energy;
   double* mom;         /* NULL, or 3 planes of n_cells: momentum rate absorbed per cell (dyn) */
   uint64_t segments, splits, seeded, n_escaped, n_truncated;
+  /* optically-thin approximation (NULL when off): rates per absorber set from
+     Eq. optthin, deposits of thin rays in their source's cell (photons/s and
+     erg/s, nothing removed), and the current item's marks, a byte per cell */
+  double *k_thin, *h_thin, *thin_dep, *thin_energy;
+  unsigned char* mark;
+  uint64_t thin_segments, thin_marked;
+  double thin_margin;
 } acc;
 
 typedef struct {
@@ -205,12 +244,14 @@ typedef struct {
   const orc_spectrum* spec;
   const orc_params* par;
   double four_pi_phi_c;
+  double four_pi_phi_thin;   /* 4 pi min(1, phi_c): the split threshold of thin rays */
 } job;
 
 /* a ray: HEALPix level and pixel, radius, photon rate, its unattenuated
    share P0, the radius where it halts in this step (infinite in a single
-   pass) and the steps since its emission */
-typedef struct { int level; uint64_t pix; double r, P, P0, rh; int age; } oray;
+   pass), the steps since its emission, its optical depth from the source and
+   whether it is still optically thin */
+typedef struct { int level; uint64_t pix; double r, P, P0, rh; int age; double tau; int thin; } oray;
 
 /* rays halted in this step (time-dependent rays) */
 typedef struct {
@@ -286,14 +327,27 @@ static void march(const job* J, int si, int gi, oray first, acc* A, csum* esc, c
           const double ta = (((double)b - sl[a]) / n[a]) / h;
           if (ta < t_exit) { t_exit = ta; ax = a; }
         }
+        const size_t cell = (size_t)c[0] + (size_t)G->nx * ((size_t)c[1] + (size_t)G->ny * (size_t)c[2]);
+        const double nabs = (double)G->n_h[cell] * (double)G->x_hi[cell];
+        /* optically-thin approximation: is the ray still thin once it leaves
+           this cell? (the decision also picks its split threshold) */
+        int thin = 0;
+        if (R.thin) {
+          const double dr0 = t_exit - R.r;
+          const double tau_exit = R.tau + (dr0 > 0.0 ? sigma * nabs * ((dr0 * h) * G->dx_cm) : 0.0);
+          thin = tau_exit < J->par->tau_thin;
+          const double margin = fabs(tau_exit - J->par->tau_thin) / J->par->tau_thin;
+          if (margin < A->thin_margin) A->thin_margin = margin;
+        }
         /* split test at the exit radius, in units of the local cell */
         if (R.level < lmax) {
           const double u = t_exit * h;
-          if (ldexp(12.0, 2 * R.level) < J->four_pi_phi_c * (u * u)) {
+          if (ldexp(12.0, 2 * R.level) < (thin ? J->four_pi_phi_thin : J->four_pi_phi_c) * (u * u)) {
             A->splits++;
             for (int k = 3; k >= 1; --k)
-              stack[sp++] = (oray){R.level + 1, 4 * R.pix + (uint64_t)k, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age};
-            R = (oray){R.level + 1, 4 * R.pix, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age};
+              stack[sp++] = (oray){R.level + 1, 4 * R.pix + (uint64_t)k, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age,
+                                   R.tau, R.thin};
+            R = (oray){R.level + 1, 4 * R.pix, R.r, 0.25 * R.P, 0.25 * R.P0, R.rh, R.age, R.tau, R.thin};
             goto new_ray;
           }
         }
@@ -301,9 +355,41 @@ static void march(const job* J, int si, int gi, oray first, acc* A, csum* esc, c
         const int halt = t_exit > R.rh;
         const double t_end = halt ? R.rh : t_exit;
         const double dr = t_end - R.r;
-        if (dr > 0.0) {
-          const size_t cell = (size_t)c[0] + (size_t)G->nx * ((size_t)c[1] + (size_t)G->ny * (size_t)c[2]);
-          const double nabs = (double)G->n_h[cell] * (double)G->x_hi[cell];
+        if (dr > 0.0 && thin) {
+          /* a thin ray removes no photons (section 2.4) */
+          const double tau = sigma * nabs * ((dr * h) * G->dx_cm);
+          const size_t o = H->cell_off[q] + cell;
+          int holds = 1;
+          for (int a = 0; a < 3; ++a) holds = holds && (double)c[a] <= sl[a] && sl[a] <= (double)c[a] + 1.0;
+          if (holds) {
+            /* a cell that holds the source (on its boundary too): the
+               general deposit, kept apart */
+            const double dP = R.P * (-expm1(-tau));
+            const double fc = J->par->covering ? covering_factor(sl, n, c, R.r, dr, h, R.level) : 1.0;
+            A->thin_dep[o] += dP * fc;
+            A->thin_energy[o] += dP * fc * eexc;
+          } else if (!A->mark[o]) {
+            /* Eq. optthin: the ray's flux P / (Omega_ray r^2) taken at the
+               cell centre, once per cell for this (source, group) */
+            double r2 = 0.0;
+            for (int a = 0; a < 3; ++a) {
+              const double centre = (q == 0) ? (double)c[a] + 0.5 : (double)G->offset[a] + 0.5 * ((double)c[a] + 0.5);
+              const double d = (centre - s[a]) * H->g[0].dx_cm;
+              r2 += d * d;
+            }
+            const double omega = 4.0 * PI_D / ldexp(12.0, 2 * R.level);
+            const double k = sigma * R.P / (omega * r2);
+            A->mark[o] = 1;
+            A->thin_marked++;
+            A->k_thin[o] += k;
+            A->h_thin[o] += k * eexc;
+          }
+          R.tau += tau;
+          A->thin_segments++;
+          A->segments++;
+          R.r = t_end;
+        } else if (dr > 0.0) {
+          R.thin = 0;
           const double tau = sigma * nabs * ((dr * h) * G->dx_cm);
           const double dP = R.P * (-expm1(-tau));
           const double fc = J->par->covering ? covering_factor(sl, n, c, R.r, dr, h, R.level) : 1.0;
@@ -381,10 +467,12 @@ static void trace_item(const job* J, int si, int gi, acc* A, csum* esc, csum* tr
   const int l0 = J->par->level_init;
   const uint64_t npix0 = (uint64_t)12 << (2 * l0);
   const double P0 = J->spec->frac[gi] * S->ndot / (double)npix0;
+  const int thin = J->par->tau_thin > 0.0;
+  if (thin) memset(A->mark, 0, J->H->n_cells);     /* marks are per (source, group) */
   halted none = {NULL, 0, 0, 0, {0.0, 0.0}};
   for (uint64_t p0 = 0; p0 < npix0; ++p0) {
     A->seeded++;
-    march(J, si, gi, (oray){l0, p0, 0.0, P0, P0, INFINITY, 0}, A, esc, trunc, &none);
+    march(J, si, gi, (oray){l0, p0, 0.0, P0, P0, INFINITY, 0, 0.0, thin}, A, esc, trunc, &none);
   }
 }
 
@@ -426,7 +514,7 @@ static int validate(const orc_grid* g, int ng, const orc_source* src, int ns, co
   }
   if (fabs(fsum - 1.0) > 1e-12) return -1;
   if (!finite_nonneg(p->phi_c) || p->level_init < 0 || p->level_init > p->level_max ||
-      p->level_max > MAX_LEVEL || !(p->p_min_frac >= 0.0 && p->p_min_frac < 1.0))
+      p->level_max > MAX_LEVEL || !(p->p_min_frac >= 0.0 && p->p_min_frac < 1.0) || !finite_nonneg(p->tau_thin))
     return -1;
   return 0;
 }
@@ -452,6 +540,8 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
   if (!absorbed || !energy || !k_ph || !heating || !tot) return -1;
   const int td = in != NULL || out != NULL;
   if (td && (!(cdt > 0.0) || (n_in > 0 && !in) || !n_out || !held)) return -1;
+  const int thin = par->tau_thin > 0.0;
+  if (thin && (td || accel)) return -1;   /* the thin approximation is a single-pass option */
   for (size_t i = 0; i < n_in; ++i)
     if (in[i].src < 0 || in[i].src >= n_src || in[i].grp < 0 || in[i].grp >= spec->n_groups || in[i].level < 0 ||
         in[i].level > par->level_max || in[i].age < 0)
@@ -480,7 +570,7 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
         }
   }
 
-  job J = {&H, src, spec, par, 4.0 * PI_D * par->phi_c};
+  job J = {&H, src, spec, par, 4.0 * PI_D * par->phi_c, 4.0 * PI_D * (par->phi_c < 1.0 ? par->phi_c : 1.0)};
   const int n_items = n_src * spec->n_groups;
   int T = n_threads < 1 || td ? 1 : n_threads;
   if (T > n_items && n_items > 0) T = n_items;
@@ -489,6 +579,14 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
     A[t].absorbed = (double*)calloc(H.n_cells, sizeof(double));
     A[t].energy = (double*)calloc(H.n_cells, sizeof(double));
     A[t].mom = accel ? (double*)calloc(3 * H.n_cells, sizeof(double)) : NULL;
+    A[t].thin_margin = INFINITY;
+    if (thin) {
+      A[t].k_thin = (double*)calloc(H.n_cells, sizeof(double));
+      A[t].h_thin = (double*)calloc(H.n_cells, sizeof(double));
+      A[t].thin_dep = (double*)calloc(H.n_cells, sizeof(double));
+      A[t].thin_energy = (double*)calloc(H.n_cells, sizeof(double));
+      A[t].mark = (unsigned char*)calloc(H.n_cells, 1);
+    }
   }
   csum* esc = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
   csum* trn = (csum*)calloc((size_t)(n_items > 0 ? n_items : 1), sizeof(csum));
@@ -510,7 +608,7 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
     for (size_t i = 0; i < n_in; ++i) {
       const orc_tray* T0 = &in[i];
       const int age = T0->age + 1;
-      march(&J, T0->src, T0->grp, (oray){T0->level, T0->pix, T0->r, T0->P, T0->P0, (double)(age + 1) * cdt, age},
+      march(&J, T0->src, T0->grp, (oray){T0->level, T0->pix, T0->r, T0->P, T0->P0, (double)(age + 1) * cdt, age, 0.0, 0},
             &A[0], &esc[T0->src * spec->n_groups + T0->grp], &trn[T0->src * spec->n_groups + T0->grp], &hl);
     }
     if (emit) {
@@ -521,7 +619,7 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
         const double P0 = spec->frac[gi] * src[si].ndot / (double)npix0;
         for (uint64_t p0 = 0; p0 < npix0; ++p0) {
           A[0].seeded++;
-          march(&J, si, gi, (oray){l0, p0, 0.0, P0, P0, cdt, 0}, &A[0], &esc[it], &trn[it], &hl);
+          march(&J, si, gi, (oray){l0, p0, 0.0, P0, P0, cdt, 0, 0.0, 0}, &A[0], &esc[it], &trn[it], &hl);
         }
       }
     }
@@ -546,14 +644,16 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
     energy[i] = e;
     cs_add(&cab, a);
   }
+  tot->thin_margin = INFINITY;
   for (int t = 0; t < T; ++t) {
     tot->segments += A[t].segments;
     tot->splits += A[t].splits;
     tot->rays_seeded += A[t].seeded;
     tot->rays_escaped += A[t].n_escaped;
     tot->rays_truncated += A[t].n_truncated;
-    free(A[t].absorbed);
-    free(A[t].energy);
+    tot->thin_segments += A[t].thin_segments;
+    tot->thin_marked += A[t].thin_marked;
+    if (A[t].thin_margin < tot->thin_margin) tot->thin_margin = A[t].thin_margin;
   }
   tot->emitted = cs_get(&cem);
   tot->absorbed = cs_get(&cab);
@@ -568,14 +668,31 @@ static int run_trace(const orc_grid* grids, int n_grids, const orc_source* src, 
     for (size_t i = 0; i < nc; ++i) {
       const double nabs = (double)G->n_h[i] * (double)G->x_hi[i];
       const size_t o = H.cell_off[q] + i;
+      double a = absorbed[o], e = energy[o], kt = 0.0, ht = 0.0;
+      if (thin)
+        for (int t = 0; t < T; ++t) {
+          a += A[t].thin_dep[o];
+          e += A[t].thin_energy[o];
+          kt += A[t].k_thin[o];
+          ht += A[t].h_thin[o];
+        }
       if (nabs > 0.0) {
-        k_ph[o] = absorbed[o] / (nabs * vol);
-        heating[o] = energy[o] / (nabs * vol);
+        k_ph[o] = a / (nabs * vol) + kt;
+        heating[o] = e / (nabs * vol) + ht;
       } else {
-        k_ph[o] = 0.0;
-        heating[o] = 0.0;
+        k_ph[o] = kt;
+        heating[o] = ht;
       }
     }
+  }
+  for (int t = 0; t < T; ++t) {
+    free(A[t].absorbed);
+    free(A[t].energy);
+    free(A[t].k_thin);
+    free(A[t].h_thin);
+    free(A[t].thin_dep);
+    free(A[t].thin_energy);
+    free(A[t].mark);
   }
   /* radiation-pressure acceleration a = dp / (rho V) with rho = m_H n_H
      (section 2.5.4; dt_P cancels as P is a rate) */

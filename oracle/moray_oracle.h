@@ -47,17 +47,29 @@ typedef struct {
   int covering;            /* nonzero: scale each segment's contribution to the absorbed
                               and energy rates (not its attenuation) by the covering
                               factor f_c of section 2.3 (Eqs. midpoint, fc) */
+  double tau_thin;         /* > 0: the optically-thin approximation of section 2.4 (Eq.
+                              optthin) for rays whose optical depth from the source is
+                              below tau_thin when they leave a cell; 0: off. Single pass
+                              only (orc_trace_td and accel reject it). */
 } orc_params;
 
 typedef struct {
   double emitted, absorbed, escaped, truncated;       /* photons/s, compensated sums */
   uint64_t segments, rays_seeded, splits, rays_escaped, rays_truncated;
+  /* optically-thin approximation (tau_thin > 0; zero otherwise): segments of
+     rays that were thin in their cell, the (cell, source, group) rates set
+     from Eq. optthin, and the smallest |tau_exit - tau_thin| / tau_thin of
+     any thin-or-thick decision (INFINITY when none was taken) */
+  uint64_t thin_segments, thin_marked;
+  double thin_margin;
 } orc_totals;
 
 /* Trace every (source, group, seed pixel) ray tree of one problem.
  * Outputs (caller-allocated, concatenated over grids in grid order, every one
  * overwritten): absorbed [photons/s per cell], energy [erg/s per cell], k_ph
- * [1/s per absorber], heating [erg/s per absorber]; escaped_sg
+ * [1/s per absorber], heating [erg/s per absorber] (with tau_thin > 0 these
+ * include the optically-thin rates, which `absorbed` and `energy` do not: see
+ * the notes in moray_oracle.c); escaped_sg
  * [n_src*n_groups] escaped photons/s per (source, group) (may be NULL).
  * n_threads > 1 splits (source, group) items cyclically over OpenMP threads,
  * each with private accumulators summed in thread order.

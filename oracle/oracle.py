@@ -6,7 +6,8 @@ imports it. It imports nothing from the GPU package: a problem is any object
 with the attributes ``grids`` (each with ``n_h``, ``x_hi``, ``dx_cm``,
 ``parent``, ``offset``), ``sources`` (S x 4: x, y, z in root cells, ndot),
 ``spectrum`` (``energy_ev``, ``sigma_cm2``, ``frac``, ``e_ion_ev``) and
-``params`` (``phi_c``, ``level_init``, ``level_max``, ``p_min_frac``).
+``params`` (``phi_c``, ``level_init``, ``level_max``, ``p_min_frac``, and
+optionally ``covering`` and ``tau_thin``).
 """
 from __future__ import annotations
 
@@ -49,13 +50,19 @@ class _Spectrum(ctypes.Structure):
 
 class _Params(ctypes.Structure):
     _fields_ = [("phi_c", ctypes.c_double), ("level_init", ctypes.c_int), ("level_max", ctypes.c_int),
-                ("p_min_frac", ctypes.c_double), ("covering", ctypes.c_int)]
+                ("p_min_frac", ctypes.c_double), ("covering", ctypes.c_int), ("tau_thin", ctypes.c_double)]
 
 
 class _Totals(ctypes.Structure):
     _fields_ = [("emitted", ctypes.c_double), ("absorbed", ctypes.c_double), ("escaped", ctypes.c_double),
                 ("truncated", ctypes.c_double), ("segments", ctypes.c_uint64), ("rays_seeded", ctypes.c_uint64),
-                ("splits", ctypes.c_uint64), ("rays_escaped", ctypes.c_uint64), ("rays_truncated", ctypes.c_uint64)]
+                ("splits", ctypes.c_uint64), ("rays_escaped", ctypes.c_uint64), ("rays_truncated", ctypes.c_uint64),
+                ("thin_segments", ctypes.c_uint64), ("thin_marked", ctypes.c_uint64), ("thin_margin", ctypes.c_double)]
+
+
+def _params(pr) -> _Params:
+    return _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
+                   1 if getattr(pr, "covering", False) else 0, float(getattr(pr, "tau_thin", 0.0)))
 
 
 _lib = None
@@ -182,8 +189,7 @@ def _c_problem(problem):
     dp = ctypes.POINTER(ctypes.c_double)
     spec = _Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
     pr = problem.params
-    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
-                  1 if getattr(pr, "covering", False) else 0)
+    par = _params(pr)
     keep += [spec, par]
     n_cells = sum(int(np.prod(shp)) for shp in shapes)
     return (grids, len(problem.grids), srcs, len(S), spec, par), keep, n_cells, shapes
@@ -220,8 +226,7 @@ def trace(problem, n_threads: int = 1, want_accel: bool = False) -> dict:
     dp = ctypes.POINTER(ctypes.c_double)
     spec = _Spectrum(len(e), e.ctypes.data_as(dp), sg.ctypes.data_as(dp), fr.ctypes.data_as(dp), float(sp.e_ion_ev))
     pr = problem.params
-    par = _Params(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
-                  1 if getattr(pr, "covering", False) else 0)
+    par = _params(pr)
     n_cells = sum(int(np.asarray(g.n_h).size) for g in problem.grids)
     absorbed = np.zeros(n_cells)
     energy = np.zeros(n_cells)

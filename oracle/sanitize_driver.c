@@ -3,8 +3,9 @@
  * -fsanitize=address,undefined together with moray_oracle.c, it runs small
  * problems through every entry point -- a uniform box with a vertex source, a
  * pseudo-random medium with several sources, a 2x-refined child grid holding
- * a source, the covering factor, the radiation-pressure acceleration,
- * time-dependent steps (including an out-list that is too small) and the
+ * a source, the covering factor, the optically-thin approximation, the
+ * radiation-pressure acceleration, time-dependent steps (including an
+ * out-list that is too small) and the
  * rejected inputs -- and checks photon conservation, so that an
  * out-of-bounds access, an overflow or undefined arithmetic anywhere on those
  * paths stops the run with a report. Exit status 0 when every case passed.
@@ -74,6 +75,22 @@ int main(void) {
   ok &= orc_trace(g, 2, src, 3, &sp, &par, 1, ab, en, kp, he, esc, &tot) == 0;
   printf("%-28s segments %10llu\n", "covering factor", (unsigned long long)tot.segments);
   par.covering = 0;
+
+  /* the optically-thin approximation, two threads; it is refused with
+     radiation pressure and with time-dependent rays */
+  par.tau_thin = 0.1;
+  ok &= orc_trace(g, 2, src, 3, &sp, &par, 2, ab, en, kp, he, esc, &tot) == 0 && conserved("optically thin", &tot, 1e-12);
+  printf("%-28s thin segments %10llu marked %8llu margin %.2e\n", "optically thin",
+         (unsigned long long)tot.thin_segments, (unsigned long long)tot.thin_marked, tot.thin_margin);
+  ok &= tot.thin_segments > 0 && tot.thin_marked > 0;
+  ok &= orc_trace_accel(g, 2, src, 3, &sp, &par, 1, ab, en, kp, he, esc, acc, &tot) == -1;
+  {
+    size_t n0 = 0;
+    double h0 = 0.0;
+    orc_tray one;
+    ok &= orc_trace_td(g, 2, src, 3, &sp, &par, 3.0, 1, NULL, 0, &one, 1, &n0, &h0, ab, en, kp, he, &tot) == -1;
+  }
+  par.tau_thin = 0.0;
 
   /* radiation pressure */
   ok &= orc_trace_accel(g, 2, src, 3, &sp, &par, 1, ab, en, kp, he, esc, acc, &tot) == 0 &&

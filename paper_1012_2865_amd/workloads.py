@@ -76,6 +76,7 @@ class Params:
     level_max: int = 14         # rays at this level never split
     p_min_frac: float = 1e-8    # a ray ends when P < p_min_frac * P0
     covering: bool = False      # scale k_ph and heating by the covering factor (section 2.3)
+    tau_thin: float = 0.0       # > 0: optically-thin approximation below this optical depth (section 2.4)
 
 
 @dataclass
