@@ -113,6 +113,22 @@ typedef struct {
                                  its attenuation) by the covering factor of section 2.3 (Eqs.
                                  midpoint, fc); the results are then not photon-conserving, and
                                  `absorbed` reports the scaled sum */
+  double tau_thin;            /* > 0: the optically-thin approximation of section 2.4 (Eq. optthin,
+                                 the per-source marker field); 0 (or a zero-initialised struct):
+                                 off. Finite and >= 0. A ray whose optical depth from its source
+                                 is still below tau_thin where it leaves a cell is thin there: it
+                                 removes no photons, is split against min(1, phi_c) rays per cell
+                                 face instead of phi_c, and gives the cell, once per (source,
+                                 group), the rate sigma P / (Omega_ray r_cell^2) of its flux moved
+                                 to the cell centre (Omega_ray = 4 pi / N_pix(l), r_cell in cm), and
+                                 heating that rate times (E - E_ion); in a cell that holds the
+                                 source (inside or on its boundary) it adds its general deposit
+                                 P (1 - e^-tau) to the rate instead. A ray that is not thin in a
+                                 cell deposits and attenuates as usual and stays thick. The thin
+                                 rates are in k_ph and heating (also where n_H x_HI = 0) but not in
+                                 `absorbed` or the other totals, which count removed photons only.
+                                 Not with radiation pressure (`accel`) in the same batch, the
+                                 serving engine or time-dependent rays (MORAY_EINVAL). */
 } moray_trace_params;
 
 typedef struct {

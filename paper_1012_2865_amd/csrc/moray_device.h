@@ -59,9 +59,17 @@ struct ProblemDev {
   int pad;
   int acc_stride = 1;      // 1: one float64 sum per (group, cell), group g of cell c at
                            //   acc_off + g*n_cells + (c - cell_off);
+                           // 2 (optically-thin approximation): a 16-byte record per (group, cell) at
+                           //   acc_off + 2*(g*n_cells + (c - cell_off)): absorbed rate, then the
+                           //   deposits of thin rays in cells that hold their source (nothing removed);
                            // 4 (radiation pressure asked for): a 32-byte record per (group, cell) at
                            //   acc_off + 4*(g*n_cells + (c - cell_off)): absorbed rate, then the three
                            //   components of the absorbed momentum rate
+  // optically-thin approximation: the marks of (source, group) tree t = sg_first + w*32 + b of the
+  // problem on cell c are bit b of mark[mark_off + w*n_cells + (c - cell_off)], w < mark_words
+  int mark_words = 0;      // 0: the problem does not use the approximation
+  int sg_first = 0;        // its first tree in the tree table (its trees are consecutive)
+  long long mark_off = 0;
 };
 
 // One (source, group) ray tree, with the shape of its problem's root grid so
@@ -89,6 +97,13 @@ struct SgDev {
   double mom_scale;        // E_ph / c of the group (erg s/cm), 0 without radiation pressure
   double r_halt = __builtin_huge_val();   // time-dependent rays: radius (root cells) where the
                                           // tree's rays halt in this step
+  // optically-thin approximation (tau_thin > 0)
+  double tau_thin = 0.0;   // a ray is thin in a cell while its optical depth on leaving it is below this
+  double four_pi_phi_thin; // 4 pi min(1, phi_c): the split threshold of thin rays
+  float split_t2_thin;     // 12 / (4 pi min(1, phi_c)), float; FLT_MAX when the problem never splits
+  uint32_t mark_bit;       // its bit in the marker words
+  long long mark_base;     // its marker word of cell c (batch numbering) is mark[mark_base + c]
+  double thin_coef;        // sigma Ndot_g / (4 pi dx_root^2): the thin rate at r root cells is thin_coef / r^2
 };
 
 struct SgStats {
@@ -154,6 +169,7 @@ struct TraceArgs {
   unsigned long long halt_cap;
   uint32_t tree_fold;                  // statistics of tree k are kept under k % tree_fold (the trees
                                        // of one batch), so the block tables hold one batch's trees
+  uint32_t* mark;                      // optically-thin marker words (see ProblemDev), or NULL
 };
 
 // One finalize block: cells [first, first + count) of one grid.

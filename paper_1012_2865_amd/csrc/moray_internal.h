@@ -16,11 +16,13 @@ hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
 hipError_t launch_reset_levels(hipStream_t, Counters*);
 hipError_t launch_reset_generation(hipStream_t, Counters*, int cin, int cout);
 hipError_t launch_reset_stats(hipStream_t, SgStats*, int first, int count);
+// mark: the optically-thin marker words the prep pass clears (NULL: none)
 template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
-                       Counters*);
+                       Counters*, uint32_t* mark = nullptr);
 template <typename R>
-hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp);
+hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp,
+                              bool thin = false);
 template <typename R>
 hipError_t launch_trace_level_halt(hipStream_t, int, const TraceArgs<R>&, bool cache);
 hipError_t launch_prefill_level(hipStream_t, int num_cu, const RayQueue& pool, const int* pool_lev,
@@ -39,8 +41,10 @@ hipError_t launch_td_sort(hipStream_t, int num_cu, const RayQueue& pool, const i
 hipError_t launch_prefill_sorted(hipStream_t, int num_cu, const RayQueue& pool, const uint32_t* order,
                                  unsigned long long first, unsigned long long count, const RayQueue& q,
                                  unsigned long long seg_cap, int nseg, Counters* ctr, int row);
+// sgs, mark: the tree table and the optically-thin marker words (NULL when no problem uses them)
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
-                           const double*, double*, const Counters*);
+                           const double*, double*, const Counters*, const SgDev* sgs = nullptr,
+                           const uint32_t* mark = nullptr);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
 // photo-ionisation equilibrium (moray_equilibrium.hip)
 // dx: 1 + kEqMaxBlocks doubles; dx[0] receives the largest change of the pass
@@ -94,7 +98,7 @@ struct moray_ctx {
   bool overflow_serve_once = false;  // test hook (MORAY_INJECT_SERVE_OVERFLOW=1 at moray_init): the serving
                                      // engine's first launch with two or more problems reports a queue overflow
   size_t allocated = 0;
-  moray::DevBuf grids, probs, sgs, stats, ctr, kappa, acc, eexc, fblocks, partial, fields, outs;
+  moray::DevBuf grids, probs, sgs, stats, ctr, kappa, acc, mark, eexc, fblocks, partial, fields, outs;
   moray::DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
   size_t q_cap = 0;
   void* h_stage = nullptr;

@@ -381,6 +381,17 @@ struct Ray {
   uint32_t astride;       // deposit key of cell lin: slot0 + astride * lin (4: a radiation-pressure record)
   double mscale;          // E_ph / c, 0 when the problem does not ask for the momentum
   double rhalt;           // time-dependent rays: radius where the tree's rays halt in this step
+  // optically-thin approximation (section 2.4): the ray's optical depth from
+  // its source while it is thin, and the tree's constants for it
+  bool thin;
+  double tau;
+  double tau_thin;        // 0: the tree does not use it
+  double sig64;           // cross-section, float64 (the thin decision's optical depth)
+  double pthin;           // photon rate of a thin ray at this launch's level (nothing removed)
+  R split_t_thin;         // split thresholds of thin rays, as split_t and fpp
+  double fpp_thin;
+  long long mark_base;
+  uint32_t mark_bit;
 };
 
 template <typename R>
@@ -489,7 +500,7 @@ struct Tracer {
       L.sg = (uint32_t)(a.seed_sg_begin + idx / npix);
       L.pix = idx % npix;
       r64 = 0.0;
-      L.P = -1.0;                          // the tree's seed rate, set in locate
+      L.P = -__builtin_huge_val();         // the tree's seed rate, set in locate
     }
   }
 
@@ -519,6 +530,62 @@ struct Tracer {
       L.split_t = can_split ? ldexp(12.0, 2 * level) : __builtin_huge_val();
       L.fpp = S.four_pi_phi_c;
     }
+  }
+
+  // The optically-thin constants of the lane's tree (after load_tree).
+  __device__ void load_thin(Ray<R>& L) const {
+    const SgDev& S = a.sgs[L.sg];
+    L.tau_thin = S.tau_thin;
+    L.sig64 = S.sigma64;
+    L.pthin = ldexp(S.P0, -2 * (L.level - S.level_init));
+    L.mark_base = S.mark_base;
+    L.mark_bit = S.mark_bit;
+    const bool can_split = L.level < S.level_max;
+    if constexpr (sizeof(R) == 4) {
+      L.split_t_thin = can_split ? ldexpf(S.split_t2_thin, 2 * L.level) : FLT_MAX;
+      L.fpp_thin = 0.0;
+    } else {
+      L.split_t_thin = L.split_t;
+      L.fpp_thin = S.four_pi_phi_thin;
+    }
+  }
+
+  // Thin state of a fetched ray (before locate). A thin ray has removed no
+  // photons, so its rate is pthin; its queue record holds -(1 + tau) in
+  // place of the rate (its parent staged -4 (1 + tau), which the child
+  // writer quarters like any rate). A seed is thin when its tree uses the
+  // approximation.
+  __device__ void thin_start(Ray<R>& L) const {
+    L.tau = 0.0;
+    if (L.P == -__builtin_huge_val()) {
+      L.thin = L.tau_thin > 0.0;
+    } else if (L.P < 0.0) {
+      L.thin = true;
+      L.tau = -L.P - 1.0;
+      L.P = L.pthin;
+    } else {
+      L.thin = false;
+    }
+  }
+
+  // Does the ray's current cell hold its source (inside or on its boundary)?
+  // Only a cell within sqrt(3) local cells of the source can: nearer than 2
+  // the test is taken exactly, on the source's float64 local coordinates.
+  __device__ bool holds_source(const Ray<R>& L) const {
+    const bool child = L.q != L.root;
+    if (L.g.radius64() * (child ? 2.0 : 1.0) >= 2.0) return false;
+    double sl[3] = {L.sx, L.sy, L.sz};
+    if (child) {
+      const GridDev& G = a.grids[L.q];
+      sl[0] = 2.0 * (L.sx - (double)G.ox);
+      sl[1] = 2.0 * (L.sy - (double)G.oy);
+      sl[2] = 2.0 * (L.sz - (double)G.oz);
+    }
+    const int c[3] = {L.c0, L.c1, L.c2};
+    bool in = true;
+#pragma unroll
+    for (int k = 0; k < 3; ++k) in = in && (double)c[k] <= sl[k] && sl[k] <= (double)c[k] + 1.0;
+    return in;
   }
 
   // Start cell of a fetched ray whose tree constants are loaded. Returns false
@@ -567,12 +634,12 @@ struct Tracer {
 
   // Float64 re-evaluation of the split test for the current cell, in the
   // canonical form 12 * 4^l < (4 pi phi_c) * u^2, u = t_exit in local cells.
-  __device__ bool split_exact(const Ray<R>& L) const {
-    const bool sp = split_exact64(L);
+  __device__ bool split_exact(const Ray<R>& L, bool thin) const {
+    const bool sp = split_exact64(L, thin);
     finish_vector_loads();
     return sp;
   }
-  __device__ bool split_exact64(const Ray<R>& L) const {
+  __device__ bool split_exact64(const Ray<R>& L, bool thin) const {
     const SgDev& S = a.sgs[L.sg];
     const bool child = L.q != L.root;
     int o[3] = {0, 0, 0};
@@ -594,20 +661,23 @@ struct Tracer {
       te = t < te ? t : te;
     }
     const double u = te * h;
-    return ldexp(12.0, 2 * L.level) < S.four_pi_phi_c * (u * u);
+    return ldexp(12.0, 2 * L.level) < (thin ? S.four_pi_phi_thin : S.four_pi_phi_c) * (u * u);
   }
 
-  __device__ bool split_test(const Ray<R>& L, int ax) const {
+  // thin: the ray is optically thin in this cell and is split against
+  // min(1, phi_c) rays per cell face (section 2.4)
+  __device__ bool split_test(const Ray<R>& L, int ax, bool thin = false) const {
     if constexpr (sizeof(R) == 4) {
       const float u = L.g.local_u(ax);
-      const float gap = u * u - L.split_t;
-      const float tol = L.split_t * 9.6e-7f;   // 16 float ulp: beyond every rounding of u^2
+      const float t = thin ? L.split_t_thin : L.split_t;
+      const float gap = u * u - t;
+      const float tol = t * 9.6e-7f;           // 16 float ulp: beyond every rounding of u^2
       if (gap > tol) return true;
       if (gap < -tol) return false;
-      return split_exact(L);
+      return split_exact(L, thin);
     } else {
       const double u = L.g.local_u(ax);
-      return L.split_t < L.fpp * (u * u);
+      return L.split_t < (thin ? L.fpp_thin : L.fpp) * (u * u);
     }
   }
 
@@ -1082,9 +1152,16 @@ struct SplitStage {
 // (radiation pressure, section 2.5.4), kPhysHalt halts every ray at its
 // tree's radius r_halt (time-dependent rays, section 2.1 and section 3.1
 // step 3j): the segment in that cell ends there and the ray, with the
-// photons it still carries, goes to the halt list for the next step. PHYS = 0
-// is the plain trace.
-constexpr int kPhysCover = 1, kPhysRadp = 2, kPhysHalt = 4;
+// photons it still carries, goes to the halt list for the next step.
+// kPhysThin applies the optically-thin approximation (section 2.4, Eq.
+// optthin): a ray whose optical depth from its source stays below tau_thin
+// through a cell removes no photons there, is split against min(1, phi_c)
+// rays per cell face, and sets its tree's bit in the cell's marker word (the
+// rate sigma P / (Omega_ray r_cell^2) is the same for every thin ray of a
+// tree, so finalize adds it once per set bit); in a cell that holds the
+// source it adds its general deposit to the cell's second sum instead.
+// PHYS = 0 is the plain trace.
+constexpr int kPhysCover = 1, kPhysRadp = 2, kPhysHalt = 4, kPhysThin = 8;
 
 // Waves per SIMD the register budget is set for: three (at most 168 VGPRs),
 // which the LDS of a block (four waves) also allows; two for the
@@ -1094,6 +1171,8 @@ template <typename R, bool CACHE, int PHYS>
 __global__ __launch_bounds__(kTraceBlock) __attribute__((amdgpu_waves_per_eu(CACHE && (PHYS & kPhysRadp) ? 2 : 3)))
 void trace_level_kernel(TraceArgs<R> a) {
   constexpr bool COVER = (PHYS & kPhysCover) != 0, RADP = (PHYS & kPhysRadp) != 0, HALT = (PHYS & kPhysHalt) != 0;
+  constexpr bool THIN = (PHYS & kPhysThin) != 0;
+  static_assert(!(THIN && (RADP || HALT)), "the optically-thin approximation is a single-pass option");
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ int s_bad;
@@ -1229,7 +1308,11 @@ void trace_level_kernel(TraceArgs<R> a) {
         double r64;
         T.fetch(L, child, q, r64);
         if (L.sg != kNoTree) {
-          if (L.sg != L.tree) T.load_tree(L);
+          if (L.sg != L.tree) {
+            T.load_tree(L);
+            if constexpr (THIN) T.load_thin(L);
+          }
+          if constexpr (THIN) T.thin_start(L);
           R k;
           if (T.locate(L, r64, k)) {
             T.begin(L, k);
@@ -1252,6 +1335,8 @@ void trace_level_kernel(TraceArgs<R> a) {
     int e_dir = 0, e_cnew = 0, e_lin = 0;
     bool e_in = false;
     R kpre = (R)0;
+    bool thin_here = false;
+    double tc64 = 0.0;
     if (active) {
       ax = L.g.exit_axis();
       // the next cell is known from the exit axis alone: its column is
@@ -1262,7 +1347,18 @@ void trace_level_kernel(TraceArgs<R> a) {
       e_in = (unsigned)e_cnew < (unsigned)sel3(ax, L.n0, L.n1, L.n2);
       e_lin = L.lin + e_dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
       kpre = kappa_step[e_in ? e_lin : 0];
-      split = T.split_test(L, ax);
+      if constexpr (THIN) {
+        // optically thin in this cell: the optical depth on leaving it, in
+        // float64, below tau_thin
+        if (L.thin) {
+          const double dr64 = L.g.exit64(ax) - L.g.radius64();
+          tc64 = dr64 > 0.0 ? (double)L.kap * L.sig64 * dr64 : 0.0;
+          thin_here = L.tau + tc64 < L.tau_thin;
+        }
+        split = T.split_test(L, ax, thin_here);
+      } else {
+        split = T.split_test(L, ax);
+      }
     }
     const unsigned long long smask = __ballot(split);
     if (smask) {
@@ -1271,7 +1367,8 @@ void trace_level_kernel(TraceArgs<R> a) {
         stage.pix[e] = L.pix;
         stage.sg[e] = L.sg;
         stage.r[e] = L.g.radius64();
-        stage.P[e] = L.P;
+        // a thin ray's children carry its optical depth as -(1 + tau)
+        stage.P[e] = (THIN && L.thin) ? -4.0 * (1.0 + L.tau) : L.P;
         ended = 2;
         active = false;
       }
@@ -1293,9 +1390,28 @@ void trace_level_kernel(TraceArgs<R> a) {
           pos = dr > (R)0;
         }
       }
-      if (pos) {
+      if (THIN && pos && thin_here) {
+        // thin: no photons removed
+        if (T.holds_source(L)) {
+          double Pc = L.P;
+          dval = absorb(Pc, L.kap * L.sigma * dr);
+          if constexpr (COVER) {
+            if (L.cover) dval *= T.covering_factor(L, (double)dr);
+          }
+          dkey = L.slot0 + L.astride * (uint32_t)L.lin + 1u;
+          dep = true;
+        } else {
+          // the tree's mark on the cell (idempotent: any thin ray may set it)
+          __hip_atomic_fetch_or(a.mark + (L.mark_base + (long long)L.lin), L.mark_bit, __ATOMIC_RELAXED,
+                                __HIP_MEMORY_SCOPE_AGENT);
+        }
+        L.tau += tc64;
+        L.segs++;
+        L.g.advance(ax);
+      } else if (pos) {
         const R tau = L.kap * L.sigma * dr;
         dval = absorb(L.P, tau);
+        if constexpr (THIN) L.thin = false;
         if constexpr (RADP) {
           // the absorbed radiation itself, before any covering-factor scaling
           mval = dval * L.mscale;
@@ -1303,7 +1419,7 @@ void trace_level_kernel(TraceArgs<R> a) {
         if constexpr (COVER) {
           if (L.cover) dval *= T.covering_factor(L, (double)dr);
         }
-        dkey = RADP ? L.slot0 + L.astride * (uint32_t)L.lin : L.slot0 + (uint32_t)L.lin;
+        dkey = (RADP || THIN) ? L.slot0 + L.astride * (uint32_t)L.lin : L.slot0 + (uint32_t)L.lin;
         dep = true;
         L.segs++;
         if (HALT && halt) L.g.set_radius(L.rhalt);
@@ -1479,7 +1595,8 @@ __global__ void reset_stats_kernel(SgStats* stats, int first, int count) {
 // cells fill [cell_begin, cell_end) of the batch-wide numbering.
 template <typename R>
 __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, const ProblemDev* probs,
-                            long long cell_begin, long long cell_end, R* kappa, double* acc, Counters* ctr) {
+                            long long cell_begin, long long cell_end, R* kappa, double* acc, Counters* ctr,
+                            uint32_t* mark) {
   for (long long c = cell_begin + blockIdx.x * (long long)blockDim.x + threadIdx.x; c < cell_end;
        c += (long long)gridDim.x * blockDim.x) {
     const int g = grid_of(grids, n_grids, c);
@@ -1504,16 +1621,22 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
     const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
     for (int gr = 0; gr < P.n_groups; ++gr)
       for (int k = 0; k < P.acc_stride; ++k) acc[base + gr * gstride + k] = 0.0;
+    for (int w = 0; w < P.mark_words; ++w) mark[P.mark_off + w * P.n_cells + (c - P.cell_off)] = 0u;
   }
 }
 
 // k_ph = sum_g absorbed_g / (n_H x_HI V); heating = sum_g absorbed_g (E_g - E_ion) / (n_H x_HI V);
 // with radiation pressure, accel = (absorbed momentum rate) / (m_H n_H V) per component;
+// with the optically-thin approximation, the thin deposits in cells that hold a source join the
+// absorbed sums of k_ph and heating (not the absorbed total), and every tree marked on the cell
+// adds its rate thin_coef / r^2 (r from its source to the cell centre, root cells) to k_ph and
+// that times (E_g - E_ion) to the heating (section 2.4, Eq. optthin), whatever n_H x_HI is;
 // per-block sums of the absorbed rate (no atomics).
 __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* grids, const ProblemDev* probs,
                                                                const FinalBlock* blocks, const double* acc,
                                                                const double* eexc, double* partial,
-                                                               const Counters* ctr) {
+                                                               const Counters* ctr, const SgDev* sgs,
+                                                               const uint32_t* mark) {
   __shared__ double red[kFinalBlock / kWave];
   if (ctr->err & kErrBadInput) return;
   const FinalBlock B = blocks[blockIdx.x];
@@ -1525,20 +1648,45 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
     const long long local = B.first + t;
     const long long c = G.cell_off + local;
     const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
-    double ab = 0.0, he = 0.0;
+    double ab = 0.0, he = 0.0, tab = 0.0, the = 0.0;
     double mom[3] = {0.0, 0.0, 0.0};
     for (int gr = 0; gr < P.n_groups; ++gr) {
       const double v = acc[base + gr * gstride];
       ab += v;
       he += v * eexc[P.eexc_off + gr];
+      if (P.acc_stride == 2) {
+        const double w = acc[base + gr * gstride + 1];
+        tab += w;
+        the += w * eexc[P.eexc_off + gr];
+      }
       if (P.acc_stride == 4)
         for (int d = 0; d < 3; ++d) mom[d] += acc[base + gr * gstride + 1 + d];
     }
+    double kt = 0.0, ht = 0.0;
+    if (P.mark_words > 0) {
+      const int i = (int)(local % G.nx), j = (int)((local / G.nx) % G.ny);
+      const int kk = (int)(local / ((long long)G.nx * G.ny));
+      const double cx = G.is_child ? (double)G.ox + 0.5 * ((double)i + 0.5) : (double)i + 0.5;
+      const double cy = G.is_child ? (double)G.oy + 0.5 * ((double)j + 0.5) : (double)j + 0.5;
+      const double cz = G.is_child ? (double)G.oz + 0.5 * ((double)kk + 0.5) : (double)kk + 0.5;
+      for (int w = 0; w < P.mark_words; ++w) {
+        uint32_t bits = mark[P.mark_off + w * P.n_cells + (c - P.cell_off)];
+        while (bits) {
+          const int t = 32 * w + __ffs(bits) - 1;
+          bits &= bits - 1u;
+          const SgDev& S = sgs[P.sg_first + t];
+          const double dx0 = cx - S.sx, dx1 = cy - S.sy, dx2 = cz - S.sz;
+          const double kv = S.thin_coef / (dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+          kt += kv;
+          ht += kv * eexc[P.eexc_off + t % P.n_groups];
+        }
+      }
+    }
     const double nabs = (double)G.n_h[local] * (double)G.x_hi[local];
-    double k = 0.0, h = 0.0;
+    double k = kt, h = ht;
     if (nabs > 0.0) {
-      k = ab / (nabs * vol);
-      h = he / (nabs * vol);
+      k = (ab + tab) / (nabs * vol) + kt;
+      h = (he + the) / (nabs * vol) + ht;
     }
     G.out_kph[local] = k;
     G.out_heat[local] = h;
@@ -1587,12 +1735,12 @@ hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
 template <typename R>
 hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, int grid_base,
                        const ProblemDev* probs, long long cell_begin, long long cell_end, R* kappa, double* acc,
-                       Counters* ctr) {
+                       Counters* ctr, uint32_t* mark) {
   long long blocks = (cell_end - cell_begin + 255) / 256;
   if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(prep_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, grid_base, probs,
-                     cell_begin, cell_end, kappa, acc, ctr);
+                     cell_begin, cell_end, kappa, acc, ctr, mark);
   return hipGetLastError();
 }
 
@@ -1624,8 +1772,11 @@ static void launch_phys(hipStream_t s, int blocks, const TraceArgs<R>& args, boo
 
 template <typename R>
 hipError_t launch_trace_level(hipStream_t s, int blocks, const TraceArgs<R>& args, bool cache, bool cover,
-                              bool radp) {
-  if (cover && radp) launch_phys<R, kPhysCover | kPhysRadp>(s, blocks, args, cache);
+                              bool radp, bool thin) {
+  if (thin && radp) return hipErrorInvalidValue;
+  if (thin && cover) launch_phys<R, kPhysThin | kPhysCover>(s, blocks, args, cache);
+  else if (thin) launch_phys<R, kPhysThin>(s, blocks, args, cache);
+  else if (cover && radp) launch_phys<R, kPhysCover | kPhysRadp>(s, blocks, args, cache);
   else if (cover) launch_phys<R, kPhysCover>(s, blocks, args, cache);
   else if (radp) launch_phys<R, kPhysRadp>(s, blocks, args, cache);
   else launch_phys<R, 0>(s, blocks, args, cache);
@@ -1747,19 +1898,19 @@ hipError_t launch_prefill_level(hipStream_t s, int num_cu, const RayQueue& pool,
 
 hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, const ProblemDev* probs,
                            const FinalBlock* blocks, const double* acc, const double* eexc, double* partial,
-                           const Counters* ctr) {
+                           const Counters* ctr, const SgDev* sgs, const uint32_t* mark) {
   if (n_blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(n_blocks), dim3(kFinalBlock), 0, s, grids, probs, blocks, acc, eexc,
-                     partial, ctr);
+                     partial, ctr, sgs, mark);
   return hipGetLastError();
 }
 
 template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                       long long, float*, double*, Counters*);
+                                       long long, float*, double*, Counters*, uint32_t*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                        long long, double*, double*, Counters*);
-template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool);
-template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool);
+                                        long long, double*, double*, Counters*, uint32_t*);
+template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool, bool);
+template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool, bool);
 template hipError_t launch_trace_level_halt<float>(hipStream_t, int, const TraceArgs<float>&, bool);
 template hipError_t launch_trace_level_halt<double>(hipStream_t, int, const TraceArgs<double>&, bool);
 

@@ -267,6 +267,7 @@ moray_status validate(moray_ctx* c, const moray_problem& P, int pi) {
   if (T.level_init < 0 || T.level_init > T.level_max || T.level_max > kMaxLevel)
     return bad("need 0 <= level_init <= level_max <= 29");
   if (!(T.p_min_frac >= 0.0 && T.p_min_frac < 1.0)) return bad("p_min_frac must be in [0, 1)");
+  if (!finite_nonneg(T.tau_thin)) return bad("tau_thin must be finite and >= 0");
   return MORAY_OK;
 }
 
@@ -385,7 +386,7 @@ void moray_free(moray_ctx* c) {
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
   DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,
-                   &c->acc,     &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
+                   &c->acc,     &c->mark,   &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
                    &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx,  &c->ev_lim, &c->eq_skip};
   for (DevBuf* b : all) release(c, *b);
   for (int i = 0; i < 2; ++i) {
@@ -496,11 +497,18 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
   // not ask for the radiation-pressure acceleration; after them, from the
   // first 64-byte boundary (rec_base), a 32-byte record per (group, cell)
   // (absorbed rate and momentum x, y, z) for those that do.
+  // Problems with the optically-thin approximation keep a second sum per
+  // (group, cell) among the plain ones (stride 2), for the deposits of thin
+  // rays in cells that hold their source.
+  bool thin = false;
   long long n_plain = 0, n_rec = 0;
   for (int i = 0; i < n_probs; ++i)
     if (!outs[i].accel) {
+      const int stride = probs[i].params.tau_thin > 0.0 ? 2 : 1;
+      thin = thin || stride == 2;
+      pdev[i].acc_stride = stride;
       pdev[i].acc_off = n_plain;
-      n_plain += pdev[i].n_cells * pdev[i].n_groups;
+      n_plain += stride * pdev[i].n_cells * pdev[i].n_groups;
     }
   const long long rec_base = (n_plain + 7) & ~7LL;
   for (int i = 0; i < n_probs; ++i)
@@ -511,6 +519,22 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
     }
   const bool radp = n_rec > 0;
   const long long n_sums = radp ? rec_base + n_rec : n_plain;
+  for (int i = 0; i < n_probs; ++i)
+    if (outs[i].accel && probs[i].params.tau_thin > 0.0)
+      return fail(c, MORAY_EINVAL, "problem " + std::to_string(i) +
+                                       ": the optically-thin approximation does not take radiation pressure");
+  if (thin && radp)
+    return fail(c, MORAY_EINVAL, "a batch cannot mix the optically-thin approximation with radiation pressure");
+  // optically-thin marks: one bit per (source, group) tree and cell, in
+  // words of 32 trees, per problem that uses the approximation
+  long long n_mark = 0;
+  for (int i = 0; i < n_probs; ++i)
+    if (probs[i].params.tau_thin > 0.0) {
+      const long long trees = (long long)probs[i].n_sources * probs[i].spectrum->n_groups;
+      pdev[i].mark_words = (int)((trees + 31) / 32);
+      pdev[i].mark_off = n_mark;
+      n_mark += pdev[i].mark_words * pdev[i].n_cells;
+    }
   (void)n_acc;
   // the trace kernel addresses accumulators with 32-bit indices
   if (n_sums >= (long long)kNoSlot)
@@ -569,6 +593,18 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
     d.level_init = P.params.level_init;
     d.gen0 = P.params.level_init;     // one-shot solve: the launch generation is the HEALPix level
     d.level_max = P.params.phi_c > 0.0 ? P.params.level_max : P.params.level_init;
+    if (k == 0 || keys[k - 1].prob != K.prob) pdev[K.prob].sg_first = k;
+    if (P.params.tau_thin > 0.0) {
+      const double phi_thin = std::min(1.0, P.params.phi_c);
+      const int t = K.src * Sp.n_groups + K.grp;                  // the tree within its problem
+      const double dx_root = P.grids[0].dx_cm;
+      d.tau_thin = P.params.tau_thin;
+      d.four_pi_phi_thin = 4.0 * kPiConst * phi_thin;
+      d.split_t2_thin = phi_thin > 0.0 ? (float)(12.0 / (4.0 * kPiConst * phi_thin)) : FLT_MAX;
+      d.mark_bit = 1u << (t % 32);
+      d.mark_base = pd.mark_off + (long long)(t / 32) * pd.n_cells - pd.cell_off;
+      d.thin_coef = d.sigma64 * (d.P0 * npix0) / (4.0 * kPiConst * dx_root * dx_root);
+    }
     sg_bound[k] = level_rays_bound(P);
   }
 
@@ -578,7 +614,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
   size_t cap = c->queue_cap_user;
   const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
   const size_t out_stage = odev ? 0 : (size_t)n_cells * (radp ? 40 : 16);
-  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
+  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (size_t)n_mark * 4 + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
                        grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) +
                        (c->arena ? (size_t)(1 << 20) : (size_t)(64 << 20));
   if (!cap) {
@@ -598,6 +634,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       (st = ensure(c, c->ctr, sizeof(Counters), "counters")) ||
       (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
       (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_sums) * 8, "accumulators")) ||
+      (n_mark && (st = ensure(c, c->mark, (size_t)n_mark * 4, "optically-thin marks"))) ||
       (st = ensure(c, c->eexc, eexc.size() * 8, "group energies")) ||
       (st = ensure(c, c->fblocks, fblocks.size() * sizeof(FinalBlock), "finalize blocks")) ||
       (st = ensure(c, c->partial, fblocks.size() * 8, "partial sums")))
@@ -757,11 +794,13 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
     }
+    uint32_t* mark = n_mark ? (uint32_t*)c->mark.p : nullptr;
     hipError_t e = fp32 ? launch_prep<float>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
-                                             (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr)
+                                             (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr,
+                                             mark)
                         : launch_prep<double>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                               (ProblemDev*)c->probs.p, 0, n_cells, (double*)c->kappa.p,
-                                              (double*)c->acc.p, ctr);
+                                              (double*)c->acc.p, ctr, mark);
     if (!hip_ok(c, e, "prep")) {
       if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
@@ -788,7 +827,8 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<float>(strm, blocks, A, c->cache, cover, radp);
+          A.mark = mark;
+          e = launch_trace_level<float>(strm, blocks, A, c->cache, cover, radp, thin);
         } else {
           TraceArgs<double> A{};
           A.grids = (GridDev*)c->grids.p; A.probs = (ProblemDev*)c->probs.p; A.sgs = (SgDev*)c->sgs.p;
@@ -797,7 +837,8 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_level = l;
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
-          e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp);
+          A.mark = mark;
+          e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp, thin);
         }
         if (!hip_ok(c, e, "trace")) {
           launch_failed = true;
@@ -814,7 +855,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
     }
     if (!hip_ok(c, launch_finalize(strm, (int)fblocks.size(), (GridDev*)c->grids.p, (ProblemDev*)c->probs.p,
                                    (FinalBlock*)c->fblocks.p, (double*)c->acc.p, (double*)c->eexc.p,
-                                   (double*)c->partial.p, ctr),
+                                   (double*)c->partial.p, ctr, (SgDev*)c->sgs.p, mark),
                 "finalize")) {
       if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
@@ -905,7 +946,7 @@ moray_status moray_trace_noalloc(moray_ctx* c, const moray_problem* probs, int n
   // for later moray_trace calls); every buffer of this call is carved from
   // the scratch array, from its start, and graphs and profiling are off.
   DevBuf* bufs[] = {&c->grids,    &c->probs,    &c->sgs,      &c->stats,    &c->ctr,      &c->kappa,
-                    &c->acc,      &c->eexc,     &c->fblocks,  &c->partial,  &c->fields,   &c->outs,
+                    &c->acc,      &c->mark,     &c->eexc,     &c->fblocks,  &c->partial,  &c->fields,   &c->outs,
                     &c->q_pix[0], &c->q_sg[0],  &c->q_r[0],   &c->q_P[0],   &c->q_pix[1], &c->q_sg[1],
                     &c->q_r[1],   &c->q_P[1]};
   constexpr int nb = (int)(sizeof(bufs) / sizeof(bufs[0]));

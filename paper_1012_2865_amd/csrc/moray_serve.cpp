@@ -933,6 +933,8 @@ moray_status moray_trace_async(moray_ctx* c, const moray_problem* probs, int n_p
     if (s != MORAY_OK) return s;
     if (!outs[i].k_ph || !outs[i].heating) return fail(c, MORAY_EINVAL, "result buffers are NULL");
     if (outs[i].accel) return fail(c, MORAY_EINVAL, "radiation pressure is computed by moray_trace only");
+    if (probs[i].params.tau_thin > 0.0)
+      return fail(c, MORAY_EINVAL, "the optically-thin approximation is computed by moray_trace only");
     if (probs[i].spectrum->n_groups > kServeMaxGroups) return fail(c, MORAY_EINVAL, "more than 64 groups");
   }
   if (!c->engine) {

@@ -86,6 +86,8 @@ moray_status moray_td_create(moray_ctx* c, const moray_problem* prob, double c_d
   moray_status st = validate(c, *prob, 0);
   if (st != MORAY_OK) return st;
   if (prob->params.covering) return fail(c, MORAY_EINVAL, "time-dependent rays do not take the covering factor");
+  if (prob->params.tau_thin > 0.0)
+    return fail(c, MORAY_EINVAL, "time-dependent rays do not take the optically-thin approximation");
   if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
   const moray_grid& G = prob->grids[0];
   const double diag = std::sqrt((double)G.nx * G.nx + (double)G.ny * G.ny + (double)G.nz * G.nz);
@@ -313,6 +315,8 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   if (st != MORAY_OK) return st;
   if (!same_shape(t, *prob)) return fail(c, MORAY_EINVAL, "the problem's shape differs from the state's");
   if (prob->params.covering) return fail(c, MORAY_EINVAL, "time-dependent rays do not take the covering factor");
+  if (prob->params.tau_thin > 0.0)
+    return fail(c, MORAY_EINVAL, "time-dependent rays do not take the optically-thin approximation");
   if (engine_busy(c)) return fail(c, MORAY_EBUSY, "the context is serving asynchronous solves");
   if (!hip_ok(c, hipSetDevice(c->device), "hipSetDevice")) return MORAY_EDEVICE;
   const moray_problem& P = *prob;

@@ -57,7 +57,7 @@ class Grid(ctypes.Structure):
 
 class TraceParams(ctypes.Structure):
     _fields_ = [("phi_c", ctypes.c_double), ("level_init", ctypes.c_int), ("level_max", ctypes.c_int),
-                ("p_min_frac", ctypes.c_double), ("covering", ctypes.c_int)]
+                ("p_min_frac", ctypes.c_double), ("covering", ctypes.c_int), ("tau_thin", ctypes.c_double)]
 
 
 class Problem(ctypes.Structure):
@@ -258,7 +258,8 @@ def _marshal(problems: Sequence, out_on_device: bool, want_escaped_sg: bool, out
         pr = pb.params
         cprobs[i] = Problem(grids, len(pb.grids), srcs, len(S), ctypes.pointer(cspec),
                             TraceParams(float(pr.phi_c), int(pr.level_init), int(pr.level_max), float(pr.p_min_frac),
-                                        1 if getattr(pr, "covering", False) else 0))
+                                        1 if getattr(pr, "covering", False) else 0,
+                                        float(getattr(pr, "tau_thin", 0.0))))
         acc = None
         if outputs is not None:
             kph, heat = outputs[i][0], outputs[i][1]

@@ -102,6 +102,8 @@ int main() {
       {"levels", [](moray_problem& q, moray_grid*, moray_source*, moray_spectrum*) { q.params.level_init = 15; }},
       {"level_max", [](moray_problem& q, moray_grid*, moray_source*, moray_spectrum*) { q.params.level_max = 30; }},
       {"p_min", [](moray_problem& q, moray_grid*, moray_source*, moray_spectrum*) { q.params.p_min_frac = 1.0; }},
+      {"tau_thin", [](moray_problem& q, moray_grid*, moray_source*, moray_spectrum*) { q.params.tau_thin = NAN; }},
+      {"negative tau_thin", [](moray_problem& q, moray_grid*, moray_source*, moray_spectrum*) { q.params.tau_thin = -0.1; }},
   };
   for (const Case& k : cases) {
     moray_grid gg[2] = {g[0], g[1]};

@@ -1,0 +1,185 @@
+"""The optically-thin approximation (section 2.4, Eq. optthin and the
+per-source marker field) on the GPU, against the FP64 oracle, through the C
+ABI.
+
+* Per cell k_ph and heating within 1e-9 relative (float64 path) or 1e-4
+  (mixed path) of the oracle's wherever they exceed 1e-6 of its maximum, on
+  transparent, switching, ionised lognormal, nested, lattice-source,
+  covering-factor and many-tree (two marker words) problems; the absorbed,
+  escaped and truncated totals to the same bar; every ray count exactly in
+  float64 (the thin decisions and thin splits included), and on the mixed
+  path within 1e-4 (segments through cell edges, which it counts as plane
+  ties) plus the split-flip allowance of the other parity tests.
+* Every case's thin decisions lie farther than 1e-6 (relative) from tau_thin
+  in the oracle (the lognormal cases use seeds for which this holds), so the
+  float32 absorber columns of the mixed path, good to 6e-8 each, cannot turn
+  one (the decision is taken in float64 on both sides).
+* In one batch a thin problem, a plain one and a second thin one each give
+  what the oracle gives for them alone.
+* The serving engine, time-dependent rays and radiation pressure refuse the
+  approximation with MORAY_EINVAL.
+"""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_1012_2865_amd import moray as M
+from paper_1012_2865_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+COUNTS = ("segments", "splits", "rays_seeded", "rays_escaped", "rays_truncated")
+
+
+def _np(a):
+    return a.detach().cpu().numpy() if hasattr(a, "detach") else np.asarray(a)
+
+
+def _rel(got, want):
+    got, want = _np(got).ravel(), np.asarray(want).ravel()
+    if want.max() == 0.0:
+        return 0.0, float(np.abs(got).max())
+    m = want > 1e-6 * want.max()
+    return float(np.max(np.abs(got[m] - want[m]) / want[m])), float(np.max(np.abs(got - want)) / want.max())
+
+
+def _thin(p, tau_thin=0.1, **kw):
+    p.params = W.Params(**{**p.params.__dict__, "tau_thin": tau_thin, **kw})
+    return p
+
+
+def _uniform(n, n_h, sources, energies=(13.6,), x_hi=1.0, **kw):
+    g = W.uniform_grid(n, W.DX_C1, n_h, x_hi)
+    return _thin(W.Problem([g], np.asarray(sources, float), W.hydrogen_spectrum(list(energies)), W.Params()), **kw)
+
+
+def _ionised(item, n=32, n_src=3, x_scale=0.05, **kw):
+    p = W.lognormal_problem(131, item, n, n_src)
+    g = p.grids[0]
+    p.grids[0] = W.Grid(g.n_h, (g.x_hi * np.float32(x_scale)).astype(np.float32), g.dx_cm)
+    return _thin(p, **kw)
+
+
+def _nested(item, n=24, child_n=16, x_scale=0.05):
+    p = W.lognormal_problem(131, item, n, 3)
+    rng = W.rng_for(131, 100 + item, 0)
+    p.grids[0] = W.Grid(p.grids[0].n_h, (p.grids[0].x_hi * np.float32(x_scale)).astype(np.float32), p.grids[0].dx_cm)
+    child = W.Grid(n_h=(10 ** rng.uniform(-2.5, -1.0, (child_n,) * 3)).astype(np.float32),
+                   x_hi=(x_scale * rng.uniform(0.5, 1.0, (child_n,) * 3)).astype(np.float32),
+                   dx_cm=p.grids[0].dx_cm / 2, parent=0, offset=(6, 5, 7))
+    p.grids.append(child)
+    p.sources[0, :3] = [10.25, 9.5, 11.75]          # inside the child
+    return _thin(p)
+
+
+def _many_trees(item, n=24):
+    p = W.lognormal_problem(131, item, n, 12, energies=(13.6, 24.6, 54.4))   # 36 trees: two marker words
+    g = p.grids[0]
+    p.grids[0] = W.Grid(g.n_h, (g.x_hi * np.float32(0.05)).astype(np.float32), g.dx_cm)
+    return _thin(p)
+
+
+CASES = {
+    "transparent20_2src_2grp": lambda: _uniform(20, 1e-9, [[7.3, 11.6, 9.15, 1e48], [12.5, 5.25, 14.0, 3e48]],
+                                                energies=(13.6, 30.0)),
+    "uniform24_switch": lambda: _uniform(24, 4.7e-5, [[11.37, 12.61, 11.92, 1e49]], p_min_frac=1e-8),
+    "lattice16_corner_face": lambda: _uniform(16, 3e-5, [[8.0, 8.0, 8.0, 1e49], [4.5, 11.0, 6.0, 1e48]]),
+    "ionised32_s3": lambda: _ionised(15),
+    "ionised32_s3_cover": lambda: _ionised(13, covering=True),
+    "ionised40_s2_l0": lambda: _ionised(3, n=40, n_src=2, level_init=0),
+    "nested24": lambda: _nested(3),
+    "many_trees24": lambda: _many_trees(4),
+}
+
+
+@pytest.fixture(scope="module")
+def ctxs():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a visible GPU"
+    c = {M.MORAY_FP64: M.moray_init(device=0, precision=M.MORAY_FP64),
+         M.MORAY_FP32_ACC64: M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)}
+    yield c
+    for v in c.values():
+        M.moray_free(v)
+
+
+_REFS = {}
+
+
+def _ref(case):
+    if case not in _REFS:
+        p = CASES[case]()
+        _REFS[case] = (p, O.trace(p, n_threads=8))
+    return _REFS[case]
+
+
+def _check(res, ref, fp64, label):
+    tol = 1e-9 if fp64 else 1e-4
+    for q in range(len(ref["k_ph"])):
+        for f in ("k_ph", "heating"):
+            rel, absr = _rel(res[f][q], ref[f][q])
+            print(f"[thin {label}] grid {q} {f}: max rel {rel:.3e}, max abs/max {absr:.3e}", flush=True)
+            assert rel <= tol, (q, f, rel)
+            assert absr <= max(tol, 1e-6), (q, f, absr)
+    T = ref["totals"]
+    assert res["emitted"] == pytest.approx(T["emitted"], rel=1e-14)
+    for k in ("absorbed", "escaped", "truncated"):
+        assert res[k] == pytest.approx(T[k], rel=max(tol, 1e-12), abs=1e-12 * T["emitted"]), k
+    for k in COUNTS:
+        if fp64:
+            assert res[k] == T[k], (k, res[k], T[k])
+        else:
+            # the float path counts a segment shorter than 2^-40 of its radius
+            # (a ray through a cell edge) as a plane tie
+            flips = abs(res["splits"] - T["splits"])
+            assert abs(res[k] - T[k]) <= 1e-4 * T[k] + 2 + 3 * flips, (k, res[k], T[k])
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+@pytest.mark.parametrize("case", list(CASES))
+def test_thin_matches_oracle(ctxs, case, precision):
+    p, ref = _ref(case)
+    T = ref["totals"]
+    assert T["thin_segments"] > 0 and T["thin_marked"] > 0
+    assert T["thin_margin"] > 1e-6, T["thin_margin"]
+    res = M.moray_trace(ctxs[precision], [M.problem_to_device(p)])[0]
+    _check(res, ref, precision == M.MORAY_FP64, f"{case} prec {precision}")
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+def test_thin_and_plain_problems_share_a_batch(ctxs, precision):
+    names = ["ionised32_s3", None, "lattice16_corner_face"]
+    probs, refs = [], []
+    for nm in names:
+        if nm is None:
+            p = W.lognormal_problem(131, 9, 24, 2)
+            probs.append(p)
+            refs.append(O.trace(p, n_threads=8))
+        else:
+            p, r = _ref(nm)
+            probs.append(p)
+            refs.append(r)
+    res = M.moray_trace(ctxs[precision], [M.problem_to_device(p) for p in probs])
+    for i, (r, ref) in enumerate(zip(res, refs)):
+        _check(r, ref, precision == M.MORAY_FP64, f"batch item {i} prec {precision}")
+
+
+def test_refused_where_it_is_not_supported(ctxs):
+    ctx = ctxs[M.MORAY_FP32_ACC64]
+    p = CASES["lattice16_corner_face"]()
+    dev = M.problem_to_device(p)
+    with pytest.raises(M.MorayError) as e:
+        M.moray_trace(ctx, [dev], want_accel=True)
+    assert e.value.status == M.MORAY_EINVAL
+    with pytest.raises(M.MorayError) as e:
+        M.moray_trace(ctx, [dev, M.problem_to_device(W.lognormal_problem(131, 9, 24, 2))], want_accel=True)
+    assert e.value.status == M.MORAY_EINVAL
+    with pytest.raises(M.MorayError) as e:
+        M.moray_trace_async(ctx, [dev])
+    assert e.value.status == M.MORAY_EINVAL
+    with pytest.raises(M.MorayError) as e:
+        M.moray_td_create(ctx, dev, 4.0)
+    assert e.value.status == M.MORAY_EINVAL
+    # the context still traces
+    res = M.moray_trace(ctx, [dev])[0]
+    assert res["segments"] > 0
