@@ -17,7 +17,7 @@ over arrival rates, and the optional physics rows.
 
   python bench.py [--steps K] [--warmup W] [--workload c2|c1|c4] [--settings C,R,S,W]
   python bench.py --serve-only [--serve-rates 10,50,...] [--serve-requests N]
-  python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only | --td-only
+  python bench.py --equilibrium-only | --evolve-only | --covering-only | --radpres-only | --td-only | --thin-only
   python bench.py --counter-pass [--workload c2] [--counter-variant plain|radpres|td]   (under rocprofv3 --pmc)
   python bench.py --read-atomics ATOMIC_DIR LAUNCHES
   python bench.py --write-traffic FETCH_DIR WRITE_DIR LAUNCHES [--workload c2]
@@ -602,6 +602,61 @@ def _radpres_c1(M, steps, oracle_threads=0):
     return out
 
 
+THIN_BYTES_PER_SEGMENT = 12   # a thin segment: absorber read + the marker word's read-modify-write
+
+
+def _with_tau(p, tau):
+    from paper_1012_2865_amd import workloads as W
+    return W.Problem(p.grids, p.sources, p.spectrum, W.Params(**{**p.params.__dict__, "tau_thin": tau}), p.name)
+
+
+def _thin_workloads(M, steps, peaks=None, oracle_threads=0):
+    """The workloads of the optically-thin approximation (section 2.4): the
+    128^3 lognormal workload with its neutral fractions scaled by 1e-3
+    (ionised gas, thin out to tens of cells around each source) and the thin
+    box of the angular-resolution test (section 7.2, 128^3), each traced with
+    the approximation (tau_thin = 0.1) and without it, mixed precision,
+    library defaults, graph replay; the thin launch sequence's roofline from
+    HIP-event launch times (36 B per thick segment, 12 B per thin one)."""
+    import torch
+    out = {}
+    settings = {"chunk_rays": 256, "refill_lanes": 64, "reserve_rays": 0, "waves_per_cu": 0}
+    from paper_1012_2865_amd import workloads as W
+    for p in (W.config1_ionised(), W.thin_box()):
+        name = p.name
+        thin, plain = [M.problem_to_device(_with_tau(p, 0.1))], [M.problem_to_device(p)]
+        torch.cuda.synchronize()
+        ctx = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64)
+        try:
+            sp, segp, _ = _time_steps(M, ctx, plain, steps, 2)
+            st, segt, res = _time_steps(M, ctx, thin, steps, 2)
+        finally:
+            M.moray_free(ctx)
+        kms, launches, ksegs = _kernel_time(M, M.MORAY_FP32_ACC64, thin, settings)
+        tsegs = res[0]["thin_segments"]
+        algo = BYTES_PER_SEGMENT["fp32"] * (ksegs - tsegs) + THIN_BYTES_PER_SEGMENT * tsegs
+        achieved = algo / (kms * 1e-3) / 1e9
+        rec = {"workload": name, "ms_per_step": st * 1e3, "segments_per_step": segt, "thin_segments": tsegs,
+               "segments_per_s": segt / st, "plain_ms_per_step": sp * 1e3, "plain_segments_per_step": segp,
+               "speedup_over_plain": sp / st, "absorbed_over_emitted": res[0]["absorbed"] / res[0]["emitted"],
+               "dtype": "f32+f64acc",
+               "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "kernel": "trace_level_kernel<float, true, kPhysThin>", "launches_per_step": launches,
+                            "avg_launch_ms": kms / launches if launches else None,
+                            "algorithmic_bytes_per_launch": algo / launches if launches else None}}
+        if oracle_threads:
+            from oracle import oracle as O
+            t0 = time.perf_counter()
+            osegs = O.trace(_with_tau(p, 0.1), n_threads=oracle_threads)["totals"]["segments"]
+            dt = time.perf_counter() - t0
+            rec["cpu_oracle"] = {"value": osegs / dt, "unit": "segments/s", "cores": oracle_threads, "kind": "oracle",
+                                 "sample": f"full workload with the approximation: {osegs} segments in {dt:.1f} s",
+                                 "gpu_speedup": (segt / st) / (osegs / dt)}
+        out[name] = rec
+    return out
+
+
 def _td_c1(M, steps=10, c_dt=32.0, oracle=False):
     """Time-dependent rays on the 128^3 workload (section 2.1): rays halt after
     c dt_P = 32 root cells per step and continue in the next; `steps` steps
@@ -844,6 +899,8 @@ def main():
                     help="print the radiation-pressure measurement (128^3 workload) as one JSON line and exit")
     ap.add_argument("--covering-only", action="store_true",
                     help="print the covering-factor measurement (128^3 workload) as one JSON line and exit")
+    ap.add_argument("--thin-only", action="store_true",
+                    help="print the optically-thin measurements (two 128^3 workloads) as one JSON line and exit")
     ap.add_argument("--no-microbench", action="store_true",
                     help="skip the device-peak sweep (no atomic or copy peaks in the line)")
     ap.add_argument("--microbench-table", action="store_true",
@@ -897,6 +954,10 @@ def main():
         return
     if args.radpres_only:
         print(json.dumps(_radpres_c1(M, args.steps)), flush=True)
+        return
+    if args.thin_only:
+        print(json.dumps(_thin_workloads(M, args.steps, oracle_threads=0 if args.no_cpu_baseline
+                                         else args.cpu_threads)), flush=True)
         return
     if args.serve_only:
         for rate in (float(x) for x in args.serve_rates.split(",")):
@@ -961,6 +1022,10 @@ def main():
         extras["radpres"] = _radpres_c1(M, max(2, args.steps // 2), oth)
         print(f"# radiation pressure: {extras['radpres']['ms_per_step']:.2f} ms per step "
               f"({100 * extras['radpres']['overhead']:+.1f}%)", file=sys.stderr, flush=True)
+        extras["thin"] = _thin_workloads(M, max(2, args.steps // 2), oracle_threads=oth)
+        for nm, rec in extras["thin"].items():
+            print(f"# optically thin, {nm}: {rec['ms_per_step']:.2f} ms per step, "
+                  f"{rec['speedup_over_plain']:.2f}x the general trace", file=sys.stderr, flush=True)
         extras["td_rays"] = _td_c1(M, oracle=not args.no_cpu_baseline)
         print(f"# time-dependent rays: {extras['td_rays']['segments_per_s_late']:.3e} segments/s", file=sys.stderr,
               flush=True)

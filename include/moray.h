@@ -168,6 +168,8 @@ typedef struct {
                                  was admitted to the device and when its results were complete */
   int from_graph;             /* 1 when the call replayed the launch sequence captured for the
                                  same descriptors (device fields and results, see moray_trace) */
+  unsigned long long thin_segments;   /* of `segments`, those of rays that were optically thin in
+                                         their cell (params.tau_thin > 0; else 0) */
 } moray_result;
 
 typedef unsigned long long moray_ticket;

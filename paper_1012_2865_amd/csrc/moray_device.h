@@ -110,6 +110,7 @@ struct SgStats {
   double esc_P;            // escaped photon rate
   double trunc_P;          // photon rate left in truncated rays
   unsigned long long segs, splits, n_esc, n_trunc;
+  unsigned long long thin_segs;   // of segs, those of optically thin rays
 };
 
 // A level queue is split into up to kSegMax segments of seg_cap slots, each
@@ -170,6 +171,9 @@ struct TraceArgs {
   uint32_t tree_fold;                  // statistics of tree k are kept under k % tree_fold (the trees
                                        // of one batch), so the block tables hold one batch's trees
   uint32_t* mark;                      // optically-thin marker words (see ProblemDev), or NULL
+  uint32_t mark_key;                   // deposit key of marker word 0 (above every accumulator slot)
+  const double* kappa64;               // float kernels with the optically-thin approximation: the
+                                       // columns in float64 (same layout as kappa), else NULL
 };
 
 // One finalize block: cells [first, first + count) of one grid.

@@ -16,10 +16,11 @@ hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
 hipError_t launch_reset_levels(hipStream_t, Counters*);
 hipError_t launch_reset_generation(hipStream_t, Counters*, int cin, int cout);
 hipError_t launch_reset_stats(hipStream_t, SgStats*, int first, int count);
-// mark: the optically-thin marker words the prep pass clears (NULL: none)
+// mark: the optically-thin marker words the prep pass clears (NULL: none);
+// kappa64: where it also writes the columns in float64 (NULL: nowhere)
 template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
-                       Counters*, uint32_t* mark = nullptr);
+                       Counters*, uint32_t* mark = nullptr, double* kappa64 = nullptr);
 template <typename R>
 hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp,
                               bool thin = false);
@@ -98,7 +99,7 @@ struct moray_ctx {
   bool overflow_serve_once = false;  // test hook (MORAY_INJECT_SERVE_OVERFLOW=1 at moray_init): the serving
                                      // engine's first launch with two or more problems reports a queue overflow
   size_t allocated = 0;
-  moray::DevBuf grids, probs, sgs, stats, ctr, kappa, acc, mark, eexc, fblocks, partial, fields, outs;
+  moray::DevBuf grids, probs, sgs, stats, ctr, kappa, kappa64, acc, mark, eexc, fblocks, partial, fields, outs;
   moray::DevBuf q_pix[2], q_sg[2], q_r[2], q_P[2];
   size_t q_cap = 0;
   void* h_stage = nullptr;

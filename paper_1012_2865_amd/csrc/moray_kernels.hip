@@ -381,17 +381,18 @@ struct Ray {
   uint32_t astride;       // deposit key of cell lin: slot0 + astride * lin (4: a radiation-pressure record)
   double mscale;          // E_ph / c, 0 when the problem does not ask for the momentum
   double rhalt;           // time-dependent rays: radius where the tree's rays halt in this step
-  // optically-thin approximation (section 2.4): the ray's optical depth from
-  // its source while it is thin, and the tree's constants for it
+  // optically-thin approximation (section 2.4): while the ray is thin, the
+  // absorber column it may still cross before its optical depth from the
+  // source reaches tau_thin, rem = (tau_thin - tau) / sigma (units of kap x
+  // radius), and the tree's constants for it
   bool thin;
-  double tau;
-  double tau_thin;        // 0: the tree does not use it
-  double sig64;           // cross-section, float64 (the thin decision's optical depth)
-  double pthin;           // photon rate of a thin ray at this launch's level (nothing removed)
+  double rem;
+  double kap64;           // the current cell's column in float64 (the thin decision's optical depth)
   R split_t_thin;         // split thresholds of thin rays, as split_t and fpp
   double fpp_thin;
   long long mark_base;
   uint32_t mark_bit;
+  unsigned tsegs;         // the ray's thin segments
 };
 
 template <typename R>
@@ -535,9 +536,6 @@ struct Tracer {
   // The optically-thin constants of the lane's tree (after load_tree).
   __device__ void load_thin(Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
-    L.tau_thin = S.tau_thin;
-    L.sig64 = S.sigma64;
-    L.pthin = ldexp(S.P0, -2 * (L.level - S.level_init));
     L.mark_base = S.mark_base;
     L.mark_bit = S.mark_bit;
     const bool can_split = L.level < S.level_max;
@@ -551,18 +549,23 @@ struct Tracer {
   }
 
   // Thin state of a fetched ray (before locate). A thin ray has removed no
-  // photons, so its rate is pthin; its queue record holds -(1 + tau) in
-  // place of the rate (its parent staged -4 (1 + tau), which the child
-  // writer quarters like any rate). A seed is thin when its tree uses the
-  // approximation.
+  // photons, so its rate is its seed's, quartered per level; its queue
+  // record holds -(1 + rem) in place of the rate (its parent staged
+  // -4 (1 + rem), which the child writer quarters like any rate). A seed is
+  // thin when its tree uses the approximation. rem is capped at kRemMax (a
+  // zero cross-section), which keeps every record finite.
+  static constexpr double kRemMax = 1e300;
   __device__ void thin_start(Ray<R>& L) const {
-    L.tau = 0.0;
+    L.tsegs = 0;
+    const SgDev& S = a.sgs[L.sg];
     if (L.P == -__builtin_huge_val()) {
-      L.thin = L.tau_thin > 0.0;
+      L.thin = S.tau_thin > 0.0;
+      const double r = S.tau_thin / S.sigma64;
+      L.rem = r < kRemMax ? r : kRemMax;
     } else if (L.P < 0.0) {
       L.thin = true;
-      L.tau = -L.P - 1.0;
-      L.P = L.pthin;
+      L.rem = -L.P - 1.0;
+      L.P = ldexp(S.P0, -2 * (L.level - S.level_init));
     } else {
       L.thin = false;
     }
@@ -826,26 +829,60 @@ __device__ __forceinline__ uint32_t cache_index(uint32_t key) {
 // Within an iteration every lane first compares its key, matching lanes add,
 // and only then may a lane claim the entry for a new key (one winner per
 // entry via compare-and-swap), so every deposit lands in its own cell's sum.
-template <bool CACHE>
+//
+// With MARKS (the optically-thin approximation) the same table also combines
+// marker words: keys from mbase on are words mark[key - mbase], and their
+// entries hold the bits set so far (in the sum's 8 bytes) and are combined
+// by OR, so the marks of rays of other trees on the same cell reach HBM as
+// one atomic OR.
+template <bool CACHE, bool MARKS = false>
 struct DepositCache;
 
-template <>
-struct DepositCache<false> {
+template <bool MARKS>
+struct DepositCache<false, MARKS> {
+  uint32_t mbase = kNoSlot;
+  uint32_t* mark = nullptr;
   __device__ void init(int) {}
-  __device__ void add(double* acc, uint32_t key, double v, bool has, int) { if (has) unsafeAtomicAdd(&acc[key], v); }
+  __device__ void init(int, uint32_t mb, uint32_t* m) { mbase = mb; mark = m; }
+  __device__ void add(double* acc, uint32_t key, double v, bool has, int) {
+    if (!has) return;
+    if (MARKS && key >= mbase) atomicOr(&mark[key - mbase], (uint32_t)__double_as_longlong(v));
+    else unsafeAtomicAdd(&acc[key], v);
+  }
   __device__ bool want_drain() const { return false; }
   __device__ void drain(double*, int) {}
   __device__ void flush(double*, int) {}
 };
 
-template <>
-struct DepositCache<true> {
+template <bool MARKS>
+struct DepositCache<true, MARKS> {
   uint32_t* key;
   double* val;
   uint32_t* ekey;         // evicted sums waiting for their global atomic
   double* eval;
   int ecount;             // wave-uniform
+  uint32_t mbase = kNoSlot;
+  uint32_t* mark = nullptr;
 
+  // one global atomic: a float64 add, or an OR of a marker word
+  __device__ void put(double* acc, uint32_t k, double v) const {
+    if (MARKS && k >= mbase) atomicOr(&mark[k - mbase], (uint32_t)__double_as_longlong(v));
+    else unsafeAtomicAdd(&acc[k], v);
+  }
+  // combine into an entry of the table
+  __device__ void combine(uint32_t h, uint32_t k, double v) {
+    if (MARKS && k >= mbase)
+      __hip_atomic_fetch_or((unsigned long long*)&val[h], (unsigned long long)__double_as_longlong(v),
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    else
+      __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+  }
+
+  __device__ void init(int lane, uint32_t mb, uint32_t* m) {
+    mbase = mb;
+    mark = m;
+    init(lane);
+  }
   __device__ void init(int lane) {
     __shared__ uint32_t skey[kTraceBlock / kWave][kCacheEntries];
     __shared__ double sval[kTraceBlock / kWave][kCacheEntries];
@@ -864,7 +901,7 @@ struct DepositCache<true> {
   // one global atomic instruction per 64 buffered sums
   __device__ void drain(double* acc, int lane) {
     __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < ecount; i += kWave) unsafeAtomicAdd(&acc[ekey[i]], eval[i]);
+    for (int i = lane; i < ecount; i += kWave) put(acc, ekey[i], eval[i]);
     ecount = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -890,7 +927,7 @@ struct DepositCache<true> {
       match = k == k_new;
     }
     __builtin_amdgcn_wave_barrier();
-    if (match) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (match) combine(h, k_new, v);
     __builtin_amdgcn_wave_barrier();
     const bool claim = has && !match;
     bool won = false, join = false;
@@ -911,7 +948,7 @@ struct DepositCache<true> {
       ok = k;
     }
     __builtin_amdgcn_wave_barrier();
-    if (join) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    if (join) combine(h, k_new, v);
     if (out) {
       const int e = ecount + __popcll(omask & below);
       ekey[e] = ok;
@@ -924,7 +961,7 @@ struct DepositCache<true> {
     drain(acc, lane);
     for (int e = lane; e < kCacheEntries; e += kWave) {
       const uint32_t k = key[e];
-      if (k != kNoSlot) unsafeAtomicAdd(&acc[k], val[e]);
+      if (k != kNoSlot) put(acc, k, val[e]);
     }
   }
 };
@@ -1193,8 +1230,9 @@ void trace_level_kernel(TraceArgs<R> a) {
   Ray<R> L;
   int ended = -1;          // kind of the lane's ray that ended and is not yet tallied
   // with radiation pressure one deposit carries four sums (one table entry each)
-  std::conditional_t<RADP, DepositCache4<CACHE>, DepositCache<CACHE>> cache;
+  std::conditional_t<RADP, DepositCache4<CACHE>, DepositCache<CACHE, THIN>> cache;
   if constexpr (RADP) cache.init(lane, a.rec_base);
+  else if constexpr (THIN) cache.init(lane, a.mark_key, a.mark);
   else cache.init(lane);
   SplitStage stage;
   stage.init(home);
@@ -1217,10 +1255,21 @@ void trace_level_kernel(TraceArgs<R> a) {
   unsigned max_steps_v = a.max_steps;
   if constexpr (sizeof(R) == 4) asm volatile("" : "+v"(kappa_v), "+v"(max_steps_v));
   const __attribute__((address_space(1))) R* const kappa_step = (const __attribute__((address_space(1))) R*)kappa_v;
+  // the float kernel with the optically-thin approximation gathers the
+  // float64 columns instead (the same values before rounding to float), so
+  // that its thin decisions see the optical depth the float64 path sees
+  constexpr bool K64 = THIN && sizeof(R) == 4;
+  uint64_t kappa64_v = (uint64_t)a.kappa64;
+  if constexpr (K64) asm volatile("" : "+v"(kappa64_v));
+  const __attribute__((address_space(1))) double* const kappa64_step =
+      (const __attribute__((address_space(1))) double*)kappa64_v;
 
   for (;;) {
     if (ended >= 0) {
       tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
+      if constexpr (THIN) {
+        if (L.tsegs) atomicAdd(&a.stats[L.sg].thin_segs, (unsigned long long)L.tsegs);
+      }
       ended = -1;
     }
     // ---- refill idle lanes from the wave's claim on the level queue ----
@@ -1316,6 +1365,8 @@ void trace_level_kernel(TraceArgs<R> a) {
           R k;
           if (T.locate(L, r64, k)) {
             T.begin(L, k);
+            if constexpr (K64) L.kap64 = a.kappa64[L.lin];
+            else if constexpr (THIN) L.kap64 = (double)L.kap;
             active = true;
             steps = 0;
           } else {
@@ -1335,6 +1386,7 @@ void trace_level_kernel(TraceArgs<R> a) {
     int e_dir = 0, e_cnew = 0, e_lin = 0;
     bool e_in = false;
     R kpre = (R)0;
+    double kpre64 = 0.0;
     bool thin_here = false;
     double tc64 = 0.0;
     if (active) {
@@ -1346,14 +1398,18 @@ void trace_level_kernel(TraceArgs<R> a) {
       e_cnew = sel3(ax, L.c0, L.c1, L.c2) + e_dir;
       e_in = (unsigned)e_cnew < (unsigned)sel3(ax, L.n0, L.n1, L.n2);
       e_lin = L.lin + e_dir * sel3(ax, 1, L.n0, L.n0 * L.n1);
-      kpre = kappa_step[e_in ? e_lin : 0];
+      if constexpr (K64) {
+        kpre64 = kappa64_step[e_in ? e_lin : 0];
+      } else {
+        kpre = kappa_step[e_in ? e_lin : 0];
+      }
       if constexpr (THIN) {
         // optically thin in this cell: the optical depth on leaving it, in
         // float64, below tau_thin
         if (L.thin) {
           const double dr64 = L.g.exit64(ax) - L.g.radius64();
-          tc64 = dr64 > 0.0 ? (double)L.kap * L.sig64 * dr64 : 0.0;
-          thin_here = L.tau + tc64 < L.tau_thin;
+          tc64 = dr64 > 0.0 ? L.kap64 * dr64 : 0.0;
+          thin_here = tc64 < L.rem;
         }
         split = T.split_test(L, ax, thin_here);
       } else {
@@ -1367,8 +1423,8 @@ void trace_level_kernel(TraceArgs<R> a) {
         stage.pix[e] = L.pix;
         stage.sg[e] = L.sg;
         stage.r[e] = L.g.radius64();
-        // a thin ray's children carry its optical depth as -(1 + tau)
-        stage.P[e] = (THIN && L.thin) ? -4.0 * (1.0 + L.tau) : L.P;
+        // a thin ray's children carry its remaining column as -(1 + rem)
+        stage.P[e] = (THIN && L.thin) ? -4.0 * (1.0 + L.rem) : L.P;
         ended = 2;
         active = false;
       }
@@ -1401,12 +1457,15 @@ void trace_level_kernel(TraceArgs<R> a) {
           dkey = L.slot0 + L.astride * (uint32_t)L.lin + 1u;
           dep = true;
         } else {
-          // the tree's mark on the cell (idempotent: any thin ray may set it)
-          __hip_atomic_fetch_or(a.mark + (L.mark_base + (long long)L.lin), L.mark_bit, __ATOMIC_RELAXED,
-                                __HIP_MEMORY_SCOPE_AGENT);
+          // the tree's mark on the cell (idempotent: any thin ray may set
+          // it), combined in the deposit table with the marks of other trees
+          dkey = a.mark_key + (uint32_t)(L.mark_base + (long long)L.lin);
+          dval = __longlong_as_double((long long)L.mark_bit);
+          dep = true;
         }
-        L.tau += tc64;
+        L.rem -= tc64;
         L.segs++;
+        L.tsegs++;
         L.g.advance(ax);
       } else if (pos) {
         const R tau = L.kap * L.sigma * dr;
@@ -1504,12 +1563,26 @@ void trace_level_kernel(TraceArgs<R> a) {
     // flight across the loop's back edge
     // the gather completes here, on every path: left in flight across the
     // loop's back edge it would make the compiler drain the whole counter
-    asm volatile("" ::"v"(kpre));
+    if constexpr (K64) {
+      asm volatile("" ::"v"(kpre64));
+      kpre = (R)kpre64;
+    } else {
+      asm volatile("" ::"v"(kpre));
+    }
     const bool kneg = moved && (!e_in || kpre < (R)0);
     L.kap = (moved && !kneg) ? kpre : L.kap;
+    if constexpr (THIN) L.kap64 = (moved && !kneg) ? (K64 ? kpre64 : (double)kpre) : L.kap64;
     if (kneg && !T.settle(L, s_ax, s_dir)) {
       ended = 0;
       active = false;
+    }
+    if constexpr (K64) {
+      if (kneg && active) {
+        L.kap64 = a.kappa64[L.lin];
+        finish_vector_loads();
+      }
+    } else if constexpr (THIN) {
+      if (kneg) L.kap64 = (double)L.kap;
     }
     // bulk writes, only when a buffer is nearly full
     if (stage.count >= kStageFlush) stage.write(a, lane);
@@ -1517,7 +1590,12 @@ void trace_level_kernel(TraceArgs<R> a) {
   }
   if (stage.count) stage.write(a, lane);
   cache.flush(a.acc, lane);
-  if (ended >= 0) tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
+  if (ended >= 0) {
+    tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
+    if constexpr (THIN) {
+      if (L.tsegs) atomicAdd(&a.stats[L.sg].thin_segs, (unsigned long long)L.tsegs);
+    }
+  }
   if constexpr (HALT) {
     // the unfilled rest of the wave's last block: empty records (no photons,
     // a level above every real one); the level's count once per wave
@@ -1596,7 +1674,7 @@ __global__ void reset_stats_kernel(SgStats* stats, int first, int count) {
 template <typename R>
 __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, const ProblemDev* probs,
                             long long cell_begin, long long cell_end, R* kappa, double* acc, Counters* ctr,
-                            uint32_t* mark) {
+                            uint32_t* mark, double* kappa64) {
   for (long long c = cell_begin + blockIdx.x * (long long)blockDim.x + threadIdx.x; c < cell_end;
        c += (long long)gridDim.x * blockDim.x) {
     const int g = grid_of(grids, n_grids, c);
@@ -1606,7 +1684,7 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
     const float nh = G.n_h[local], xh = G.x_hi[local];
     if (!(nh >= 0.0f) || !(xh >= 0.0f) || !(xh <= 1.0f) || !isfinite(nh)) atomicOr(&ctr->err, kErrBadInput);
     const double dx_root = G.is_child ? 2.0 * G.dx_cm : G.dx_cm;
-    R k = (R)((double)nh * (double)xh * dx_root);
+    double k64 = (double)nh * (double)xh * dx_root;
     // children follow their root in the grid table
     if (!G.is_child && g + 1 < n_grids && grids[g + 1].is_child && grids[g + 1].problem == G.problem) {
       // a root cell under a child grid carries -(child + 1)
@@ -1614,10 +1692,11 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
       for (int q = g + 1; q < n_grids && grids[q].is_child && grids[q].problem == G.problem; ++q) {
         const GridDev& C = grids[q];
         if (i >= C.ox && i < C.ox + C.nx / 2 && j >= C.oy && j < C.oy + C.ny / 2 && kk >= C.oz && kk < C.oz + C.nz / 2)
-          k = (R)(-(grid_base + q + 1));
+          k64 = (double)(-(grid_base + q + 1));
       }
     }
-    kappa[c] = k;
+    kappa[c] = (R)k64;
+    if (kappa64) kappa64[c] = k64;
     const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
     for (int gr = 0; gr < P.n_groups; ++gr)
       for (int k = 0; k < P.acc_stride; ++k) acc[base + gr * gstride + k] = 0.0;
@@ -1735,12 +1814,12 @@ hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
 template <typename R>
 hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, int grid_base,
                        const ProblemDev* probs, long long cell_begin, long long cell_end, R* kappa, double* acc,
-                       Counters* ctr, uint32_t* mark) {
+                       Counters* ctr, uint32_t* mark, double* kappa64) {
   long long blocks = (cell_end - cell_begin + 255) / 256;
   if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
   if (blocks < 1) blocks = 1;
   hipLaunchKernelGGL(prep_kernel<R>, dim3((unsigned)blocks), dim3(256), 0, s, grids, n_grids, grid_base, probs,
-                     cell_begin, cell_end, kappa, acc, ctr, mark);
+                     cell_begin, cell_end, kappa, acc, ctr, mark, kappa64);
   return hipGetLastError();
 }
 
@@ -1906,9 +1985,9 @@ hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, co
 }
 
 template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                       long long, float*, double*, Counters*, uint32_t*);
+                                       long long, float*, double*, Counters*, uint32_t*, double*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                        long long, double*, double*, Counters*, uint32_t*);
+                                        long long, double*, double*, Counters*, uint32_t*, double*);
 template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool, bool);
 template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool, bool);
 template hipError_t launch_trace_level_halt<float>(hipStream_t, int, const TraceArgs<float>&, bool);

@@ -107,6 +107,7 @@ void collect(moray_ctx* c, const PlanHost& ph, const moray_problem* probs, int n
     moray_result& R = outs[i];
     R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
     R.segments = R.rays_seeded = R.splits = R.rays_escaped = R.rays_truncated = 0;
+    R.thin_segments = 0;
     R.peak_level_rays = peak;
     R.trace_ms = trace_ms;
     R.trace_launches = ph.launches;
@@ -126,6 +127,7 @@ void collect(moray_ctx* c, const PlanHost& ph, const moray_problem* probs, int n
     R.splits += S.splits;
     R.rays_escaped += S.n_esc;
     R.rays_truncated += S.n_trunc;
+    R.thin_segments += S.thin_segs;
     R.rays_seeded += (unsigned long long)std::ldexp(12.0, 2 * P.params.level_init);
     if (R.escaped_sg) R.escaped_sg[K.src * P.spectrum->n_groups + K.grp] = S.esc_P;
   }
@@ -385,7 +387,7 @@ void moray_free(moray_ctx* c) {
   (void)hipSetDevice(c->device);
   if (c->stream) (void)hipStreamSynchronize(c->stream);
   else (void)hipDeviceSynchronize();
-  DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,
+  DevBuf* all[] = {&c->grids,   &c->probs,  &c->sgs,   &c->stats,  &c->ctr,     &c->kappa,  &c->kappa64,
                    &c->acc,     &c->mark,   &c->eexc,   &c->fblocks, &c->partial, &c->fields, &c->outs,
                    &c->eq_x,    &c->eq_kph, &c->eq_heat, &c->eq_dx,  &c->ev_lim, &c->eq_skip};
   for (DevBuf* b : all) release(c, *b);
@@ -526,7 +528,8 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
   if (thin && radp)
     return fail(c, MORAY_EINVAL, "a batch cannot mix the optically-thin approximation with radiation pressure");
   // optically-thin marks: one bit per (source, group) tree and cell, in
-  // words of 32 trees, per problem that uses the approximation
+  // words of 32 trees, per problem that uses the approximation; the trace
+  // combines them in its deposit table under keys n_sums + word
   long long n_mark = 0;
   for (int i = 0; i < n_probs; ++i)
     if (probs[i].params.tau_thin > 0.0) {
@@ -535,6 +538,9 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       pdev[i].mark_off = n_mark;
       n_mark += pdev[i].mark_words * pdev[i].n_cells;
     }
+  if (n_sums + n_mark >= (long long)kNoSlot)
+    return fail(c, MORAY_EINVAL, "a batch with the optically-thin approximation needs fewer than 2^32 - 1 "
+                                 "accumulators and marker words together");
   (void)n_acc;
   // the trace kernel addresses accumulators with 32-bit indices
   if (n_sums >= (long long)kNoSlot)
@@ -614,7 +620,8 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
   size_t cap = c->queue_cap_user;
   const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
   const size_t out_stage = odev ? 0 : (size_t)n_cells * (radp ? 40 : 16);
-  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (size_t)n_mark * 4 + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
+  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (size_t)n_mark * 4 +
+                       (thin && fp32 ? (size_t)n_cells * 8 : 0) + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
                        grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) +
                        (c->arena ? (size_t)(1 << 20) : (size_t)(64 << 20));
   if (!cap) {
@@ -635,6 +642,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
       (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_sums) * 8, "accumulators")) ||
       (n_mark && (st = ensure(c, c->mark, (size_t)n_mark * 4, "optically-thin marks"))) ||
+      (thin && fp32 && (st = ensure(c, c->kappa64, (size_t)n_cells * 8, "float64 absorber columns"))) ||
       (st = ensure(c, c->eexc, eexc.size() * 8, "group energies")) ||
       (st = ensure(c, c->fblocks, fblocks.size() * sizeof(FinalBlock), "finalize blocks")) ||
       (st = ensure(c, c->partial, fblocks.size() * 8, "partial sums")))
@@ -795,9 +803,10 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       return MORAY_EDEVICE;
     }
     uint32_t* mark = n_mark ? (uint32_t*)c->mark.p : nullptr;
+    double* kappa64 = thin && fp32 ? (double*)c->kappa64.p : nullptr;
     hipError_t e = fp32 ? launch_prep<float>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                              (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr,
-                                             mark)
+                                             mark, kappa64)
                         : launch_prep<double>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                               (ProblemDev*)c->probs.p, 0, n_cells, (double*)c->kappa.p,
                                               (double*)c->acc.p, ctr, mark);
@@ -828,6 +837,8 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           A.mark = mark;
+          A.mark_key = (uint32_t)n_sums;
+          A.kappa64 = kappa64;
           e = launch_trace_level<float>(strm, blocks, A, c->cache, cover, radp, thin);
         } else {
           TraceArgs<double> A{};
@@ -838,6 +849,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           A.mark = mark;
+          A.mark_key = (uint32_t)n_sums;
           e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp, thin);
         }
         if (!hip_ok(c, e, "trace")) {
@@ -945,7 +957,7 @@ moray_status moray_trace_noalloc(moray_ctx* c, const moray_problem* probs, int n
   // The context's own buffers step aside for the call (they stay allocated
   // for later moray_trace calls); every buffer of this call is carved from
   // the scratch array, from its start, and graphs and profiling are off.
-  DevBuf* bufs[] = {&c->grids,    &c->probs,    &c->sgs,      &c->stats,    &c->ctr,      &c->kappa,
+  DevBuf* bufs[] = {&c->grids,    &c->probs,    &c->sgs,      &c->stats,    &c->ctr,      &c->kappa,    &c->kappa64,
                     &c->acc,      &c->mark,     &c->eexc,     &c->fblocks,  &c->partial,  &c->fields,   &c->outs,
                     &c->q_pix[0], &c->q_sg[0],  &c->q_r[0],   &c->q_P[0],   &c->q_pix[1], &c->q_sg[1],
                     &c->q_r[1],   &c->q_P[1]};

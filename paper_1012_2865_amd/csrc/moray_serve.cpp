@@ -485,6 +485,7 @@ moray_status retire(Engine* E, std::vector<ServeProblem*>& done) {
     const moray_problem& P = p->prob;
     R.emitted = R.absorbed = R.escaped = R.truncated = 0.0;
     R.segments = R.rays_seeded = R.splits = R.rays_escaped = R.rays_truncated = 0;
+    R.thin_segments = 0;
     for (int b = first[i]; b < first[i + 1]; ++b) R.absorbed += hpart[b];
     int k = 0;
     for (int si = 0; si < P.n_sources; ++si) {

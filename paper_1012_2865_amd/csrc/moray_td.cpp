@@ -511,6 +511,7 @@ moray_status moray_td_step(moray_ctx* c, moray_td* t, const moray_problem* prob,
   moray_result& Rr = *out;
   Rr.emitted = Rr.absorbed = Rr.escaped = Rr.truncated = 0.0;
   Rr.segments = Rr.rays_seeded = Rr.splits = Rr.rays_escaped = Rr.rays_truncated = 0;
+  Rr.thin_segments = 0;
   if (emit)
     for (int si = 0; si < t->n_src; ++si)
       for (int g = 0; g < t->n_grp; ++g) Rr.emitted += Sp.photon_frac[g] * P.sources[si].ndot;

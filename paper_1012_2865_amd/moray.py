@@ -72,7 +72,7 @@ class Result(ctypes.Structure):
                 ("splits", ctypes.c_ulonglong), ("rays_escaped", ctypes.c_ulonglong),
                 ("rays_truncated", ctypes.c_ulonglong), ("peak_level_rays", ctypes.c_ulonglong),
                 ("trace_ms", ctypes.c_double), ("trace_launches", ctypes.c_int), ("t_admit", ctypes.c_double),
-                ("t_done", ctypes.c_double), ("from_graph", ctypes.c_int)]
+                ("t_done", ctypes.c_double), ("from_graph", ctypes.c_int), ("thin_segments", ctypes.c_ulonglong)]
 
 
 class EquilibriumParams(ctypes.Structure):

@@ -196,6 +196,27 @@ def config1() -> Problem:
     return lognormal_problem(1, 0, 128, 16)
 
 
+def config1_ionised(tau_thin: float = 0.0) -> Problem:
+    """config1 with every neutral fraction scaled by 1e-3: ionised gas around
+    the sources, optically thin for tens of cells (the regime the optically-thin
+    approximation of section 2.4 is for); tau_thin as given."""
+    p = config1()
+    g = p.grids[0]
+    p.grids[0] = Grid(g.n_h, (g.x_hi * np.float32(1e-3)).astype(np.float32), g.dx_cm)
+    p.params = Params(**{**p.params.__dict__, "tau_thin": tau_thin})
+    p.name = "ionised_lognormal128_16src_4grp"
+    return p
+
+
+def thin_box(n: int = 128, tau_thin: float = 0.0) -> Problem:
+    """The optically thin medium of the angular-resolution test (section 7.2):
+    a 6.6 kpc box of n^3 cells, n_H = 1e-3, x_HI = 1e-4, one 5e48 ph/s 13.6 eV
+    source at the corner (as in Test 1), phi_c = 5.1; tau_thin as given."""
+    g = uniform_grid(n, 6.6 * KPC_CM / n, 1e-3, 1e-4)
+    return Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), hydrogen_spectrum([13.6]),
+                   Params(phi_c=5.1, level_init=1, tau_thin=tau_thin), name=f"thin_box{n}_corner_source")
+
+
 C2_EDGES = (32, 48, 64, 96)
 
 

@@ -4,6 +4,11 @@ mixed path's bar (1e-4 relative wherever the oracle's value exceeds 1e-6 of
 its maximum):
 
 * the covering-factor correction (section 2.3) on the whole workload;
+* the optically-thin approximation (section 2.4) on the workload with its
+  neutral fractions scaled by 1e-3 (thin out to tens of cells; the oracle's
+  closest thin-or-thick decision lies 2e-10 from tau_thin) in both
+  precisions, float64 to 1e-9 with every count exact, and on the thin box of
+  the angular-resolution test (section 7.2, 128^3);
 * the radiation-pressure acceleration (section 2.5.4) on the whole workload;
 * time-dependent rays (section 2.1) on a two-source subset for three steps
   of c dt_P = 32 cells (the oracle's time-dependent step runs on one thread),
@@ -55,6 +60,36 @@ def test_covering_factor_at_full_size(ctx):
         print(f"[covering 128^3] {f}: max rel {rel:.2e}, max abs/max {absr:.2e}", flush=True)
         assert rel <= 1e-4 and absr <= 1e-4
     assert res["absorbed"] == pytest.approx(ref["totals"]["absorbed"], rel=1e-4)
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP64, M.MORAY_FP32_ACC64])
+@pytest.mark.parametrize("workload", ["ionised128", "thin_box128"])
+def test_optically_thin_at_full_size(workload, precision):
+    p = W.config1_ionised(0.1) if workload == "ionised128" else W.thin_box(128, 0.1)
+    c = M.moray_init(device=0, precision=precision)
+    try:
+        res = M.moray_trace(c, [M.problem_to_device(p)])[0]
+    finally:
+        M.moray_free(c)
+    ref = O.trace(p, n_threads=16)
+    T = ref["totals"]
+    fp64 = precision == M.MORAY_FP64
+    tol = 1e-9 if fp64 else 1e-4
+    for f in ("k_ph", "heating"):
+        if ref[f][0].max() == 0.0:               # a 13.6 eV source heats nothing
+            assert float(np.abs(_np(res[f][0])).max()) == 0.0
+            continue
+        rel, absr = _rel(res[f][0], ref[f][0])
+        print(f"[thin {workload} prec {precision}] {f}: max rel {rel:.2e}, max abs/max {absr:.2e}", flush=True)
+        assert rel <= tol and absr <= max(tol, 1e-6)
+    for k in ("absorbed", "escaped", "truncated"):
+        assert res[k] == pytest.approx(T[k], rel=max(tol, 1e-12), abs=1e-12 * T["emitted"]), k
+    for k in ("segments", "thin_segments", "splits", "rays_escaped", "rays_truncated"):
+        print(f"[thin {workload} prec {precision}] {k}: {res[k]} vs {T[k]}", flush=True)
+        if fp64:
+            assert res[k] == T[k], k
+        else:
+            assert abs(res[k] - T[k]) <= 1e-4 * T[k] + 2 + 3 * abs(res["splits"] - T["splits"]), k
 
 
 def test_radiation_pressure_at_full_size(ctx):

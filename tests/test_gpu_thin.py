@@ -10,10 +10,11 @@ ABI.
   float64 (the thin decisions and thin splits included), and on the mixed
   path within 1e-4 (segments through cell edges, which it counts as plane
   ties) plus the split-flip allowance of the other parity tests.
-* Every case's thin decisions lie farther than 1e-6 (relative) from tau_thin
-  in the oracle (the lognormal cases use seeds for which this holds), so the
-  float32 absorber columns of the mixed path, good to 6e-8 each, cannot turn
-  one (the decision is taken in float64 on both sides).
+* The thin-or-thick decision is taken in float64 on both paths (the mixed
+  path gathers float64 absorber columns while it traces thin rays), so it
+  agrees with the oracle's wherever the oracle's decisions lie farther than
+  rounding from tau_thin; every case here keeps them beyond 1e-6 (relative),
+  and the full-size tests go to 2e-10.
 * In one batch a thin problem, a plain one and a second thin one each give
   what the oracle gives for them alone.
 * The serving engine, time-dependent rays and radiation pressure refuse the
@@ -28,7 +29,7 @@ from paper_1012_2865_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-COUNTS = ("segments", "splits", "rays_seeded", "rays_escaped", "rays_truncated")
+COUNTS = ("segments", "thin_segments", "splits", "rays_seeded", "rays_escaped", "rays_truncated")
 
 
 def _np(a):
@@ -141,7 +142,7 @@ def test_thin_matches_oracle(ctxs, case, precision):
     p, ref = _ref(case)
     T = ref["totals"]
     assert T["thin_segments"] > 0 and T["thin_marked"] > 0
-    assert T["thin_margin"] > 1e-6, T["thin_margin"]
+    assert T["thin_margin"] > 1e-9, T["thin_margin"]
     res = M.moray_trace(ctxs[precision], [M.problem_to_device(p)])[0]
     _check(res, ref, precision == M.MORAY_FP64, f"{case} prec {precision}")
 
