@@ -65,9 +65,9 @@ struct ProblemDev {
                            // 4 (radiation pressure asked for): a 32-byte record per (group, cell) at
                            //   acc_off + 4*(g*n_cells + (c - cell_off)): absorbed rate, then the three
                            //   components of the absorbed momentum rate
-  // optically-thin approximation: the marks of (source, group) tree t = sg_first + w*32 + b of the
-  // problem on cell c are bit b of mark[mark_off + w*n_cells + (c - cell_off)], w < mark_words
-  int mark_words = 0;      // 0: the problem does not use the approximation
+  // optically-thin approximation: the mark of the problem's (source, group) tree t (tree table
+  // index sg_first + t) on cell c is the byte mark[mark_off + t*n_cells + (c - cell_off)], t < mark_trees
+  int mark_trees = 0;      // 0: the problem does not use the approximation
   int sg_first = 0;        // its first tree in the tree table (its trees are consecutive)
   long long mark_off = 0;
 };
@@ -101,8 +101,7 @@ struct SgDev {
   double tau_thin = 0.0;   // a ray is thin in a cell while its optical depth on leaving it is below this
   double four_pi_phi_thin; // 4 pi min(1, phi_c): the split threshold of thin rays
   float split_t2_thin;     // 12 / (4 pi min(1, phi_c)), float; FLT_MAX when the problem never splits
-  uint32_t mark_bit;       // its bit in the marker words
-  long long mark_base;     // its marker word of cell c (batch numbering) is mark[mark_base + c]
+  long long mark_base;     // its mark on cell c (batch numbering) is the byte mark[mark_base + c]
   double thin_coef;        // sigma Ndot_g / (4 pi dx_root^2): the thin rate at r root cells is thin_coef / r^2
 };
 
@@ -170,8 +169,7 @@ struct TraceArgs {
   unsigned long long halt_cap;
   uint32_t tree_fold;                  // statistics of tree k are kept under k % tree_fold (the trees
                                        // of one batch), so the block tables hold one batch's trees
-  uint32_t* mark;                      // optically-thin marker words (see ProblemDev), or NULL
-  uint32_t mark_key;                   // deposit key of marker word 0 (above every accumulator slot)
+  uint8_t* mark;                       // optically-thin marks (see ProblemDev), or NULL
   const double* kappa64;               // float kernels with the optically-thin approximation: the
                                        // columns in float64 (same layout as kappa), else NULL
 };

@@ -16,11 +16,11 @@ hipError_t launch_reset(hipStream_t, Counters*, SgStats*, int);
 hipError_t launch_reset_levels(hipStream_t, Counters*);
 hipError_t launch_reset_generation(hipStream_t, Counters*, int cin, int cout);
 hipError_t launch_reset_stats(hipStream_t, SgStats*, int first, int count);
-// mark: the optically-thin marker words the prep pass clears (NULL: none);
+// mark: the optically-thin marks the prep pass clears (NULL: none);
 // kappa64: where it also writes the columns in float64 (NULL: nowhere)
 template <typename R>
 hipError_t launch_prep(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long, long long, R*, double*,
-                       Counters*, uint32_t* mark = nullptr, double* kappa64 = nullptr);
+                       Counters*, uint8_t* mark = nullptr, double* kappa64 = nullptr);
 template <typename R>
 hipError_t launch_trace_level(hipStream_t, int, const TraceArgs<R>&, bool cache, bool cover, bool radp,
                               bool thin = false);
@@ -42,10 +42,10 @@ hipError_t launch_td_sort(hipStream_t, int num_cu, const RayQueue& pool, const i
 hipError_t launch_prefill_sorted(hipStream_t, int num_cu, const RayQueue& pool, const uint32_t* order,
                                  unsigned long long first, unsigned long long count, const RayQueue& q,
                                  unsigned long long seg_cap, int nseg, Counters* ctr, int row);
-// sgs, mark: the tree table and the optically-thin marker words (NULL when no problem uses them)
+// sgs, mark: the tree table and the optically-thin marks (NULL when no problem uses them)
 hipError_t launch_finalize(hipStream_t, int, const GridDev*, const ProblemDev*, const FinalBlock*, const double*,
                            const double*, double*, const Counters*, const SgDev* sgs = nullptr,
-                           const uint32_t* mark = nullptr);
+                           const uint8_t* mark = nullptr);
 hipError_t trace_occupancy(int precision, bool cache, int* blocks_per_cu);
 // photo-ionisation equilibrium (moray_equilibrium.hip)
 // dx: 1 + kEqMaxBlocks doubles; dx[0] receives the largest change of the pass

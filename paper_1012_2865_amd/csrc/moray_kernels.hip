@@ -391,7 +391,6 @@ struct Ray {
   R split_t_thin;         // split thresholds of thin rays, as split_t and fpp
   double fpp_thin;
   long long mark_base;
-  uint32_t mark_bit;
   unsigned tsegs;         // the ray's thin segments
 };
 
@@ -537,7 +536,6 @@ struct Tracer {
   __device__ void load_thin(Ray<R>& L) const {
     const SgDev& S = a.sgs[L.sg];
     L.mark_base = S.mark_base;
-    L.mark_bit = S.mark_bit;
     const bool can_split = L.level < S.level_max;
     if constexpr (sizeof(R) == 4) {
       L.split_t_thin = can_split ? ldexpf(S.split_t2_thin, 2 * L.level) : FLT_MAX;
@@ -829,60 +827,26 @@ __device__ __forceinline__ uint32_t cache_index(uint32_t key) {
 // Within an iteration every lane first compares its key, matching lanes add,
 // and only then may a lane claim the entry for a new key (one winner per
 // entry via compare-and-swap), so every deposit lands in its own cell's sum.
-//
-// With MARKS (the optically-thin approximation) the same table also combines
-// marker words: keys from mbase on are words mark[key - mbase], and their
-// entries hold the bits set so far (in the sum's 8 bytes) and are combined
-// by OR, so the marks of rays of other trees on the same cell reach HBM as
-// one atomic OR.
-template <bool CACHE, bool MARKS = false>
+template <bool CACHE>
 struct DepositCache;
 
-template <bool MARKS>
-struct DepositCache<false, MARKS> {
-  uint32_t mbase = kNoSlot;
-  uint32_t* mark = nullptr;
+template <>
+struct DepositCache<false> {
   __device__ void init(int) {}
-  __device__ void init(int, uint32_t mb, uint32_t* m) { mbase = mb; mark = m; }
-  __device__ void add(double* acc, uint32_t key, double v, bool has, int) {
-    if (!has) return;
-    if (MARKS && key >= mbase) atomicOr(&mark[key - mbase], (uint32_t)__double_as_longlong(v));
-    else unsafeAtomicAdd(&acc[key], v);
-  }
+  __device__ void add(double* acc, uint32_t key, double v, bool has, int) { if (has) unsafeAtomicAdd(&acc[key], v); }
   __device__ bool want_drain() const { return false; }
   __device__ void drain(double*, int) {}
   __device__ void flush(double*, int) {}
 };
 
-template <bool MARKS>
-struct DepositCache<true, MARKS> {
+template <>
+struct DepositCache<true> {
   uint32_t* key;
   double* val;
   uint32_t* ekey;         // evicted sums waiting for their global atomic
   double* eval;
   int ecount;             // wave-uniform
-  uint32_t mbase = kNoSlot;
-  uint32_t* mark = nullptr;
 
-  // one global atomic: a float64 add, or an OR of a marker word
-  __device__ void put(double* acc, uint32_t k, double v) const {
-    if (MARKS && k >= mbase) atomicOr(&mark[k - mbase], (uint32_t)__double_as_longlong(v));
-    else unsafeAtomicAdd(&acc[k], v);
-  }
-  // combine into an entry of the table
-  __device__ void combine(uint32_t h, uint32_t k, double v) {
-    if (MARKS && k >= mbase)
-      __hip_atomic_fetch_or((unsigned long long*)&val[h], (unsigned long long)__double_as_longlong(v),
-                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-    else
-      __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-  }
-
-  __device__ void init(int lane, uint32_t mb, uint32_t* m) {
-    mbase = mb;
-    mark = m;
-    init(lane);
-  }
   __device__ void init(int lane) {
     __shared__ uint32_t skey[kTraceBlock / kWave][kCacheEntries];
     __shared__ double sval[kTraceBlock / kWave][kCacheEntries];
@@ -901,7 +865,7 @@ struct DepositCache<true, MARKS> {
   // one global atomic instruction per 64 buffered sums
   __device__ void drain(double* acc, int lane) {
     __builtin_amdgcn_wave_barrier();
-    for (int i = lane; i < ecount; i += kWave) put(acc, ekey[i], eval[i]);
+    for (int i = lane; i < ecount; i += kWave) unsafeAtomicAdd(&acc[ekey[i]], eval[i]);
     ecount = 0;
     __builtin_amdgcn_wave_barrier();
   }
@@ -927,7 +891,7 @@ struct DepositCache<true, MARKS> {
       match = k == k_new;
     }
     __builtin_amdgcn_wave_barrier();
-    if (match) combine(h, k_new, v);
+    if (match) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     __builtin_amdgcn_wave_barrier();
     const bool claim = has && !match;
     bool won = false, join = false;
@@ -948,7 +912,7 @@ struct DepositCache<true, MARKS> {
       ok = k;
     }
     __builtin_amdgcn_wave_barrier();
-    if (join) combine(h, k_new, v);
+    if (join) __hip_atomic_fetch_add(&val[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
     if (out) {
       const int e = ecount + __popcll(omask & below);
       ekey[e] = ok;
@@ -961,7 +925,7 @@ struct DepositCache<true, MARKS> {
     drain(acc, lane);
     for (int e = lane; e < kCacheEntries; e += kWave) {
       const uint32_t k = key[e];
-      if (k != kNoSlot) put(acc, k, val[e]);
+      if (k != kNoSlot) unsafeAtomicAdd(&acc[k], val[e]);
     }
   }
 };
@@ -1193,10 +1157,10 @@ struct SplitStage {
 // kPhysThin applies the optically-thin approximation (section 2.4, Eq.
 // optthin): a ray whose optical depth from its source stays below tau_thin
 // through a cell removes no photons there, is split against min(1, phi_c)
-// rays per cell face, and sets its tree's bit in the cell's marker word (the
-// rate sigma P / (Omega_ray r_cell^2) is the same for every thin ray of a
-// tree, so finalize adds it once per set bit); in a cell that holds the
-// source it adds its general deposit to the cell's second sum instead.
+// rays per cell face, and sets its tree's mark on the cell (a byte; the rate
+// sigma P / (Omega_ray r_cell^2) is the same for every thin ray of a tree,
+// so finalize adds it once per marked tree); in a cell that holds the source
+// it adds its general deposit to the cell's second sum instead.
 // PHYS = 0 is the plain trace.
 constexpr int kPhysCover = 1, kPhysRadp = 2, kPhysHalt = 4, kPhysThin = 8;
 
@@ -1230,9 +1194,8 @@ void trace_level_kernel(TraceArgs<R> a) {
   Ray<R> L;
   int ended = -1;          // kind of the lane's ray that ended and is not yet tallied
   // with radiation pressure one deposit carries four sums (one table entry each)
-  std::conditional_t<RADP, DepositCache4<CACHE>, DepositCache<CACHE, THIN>> cache;
+  std::conditional_t<RADP, DepositCache4<CACHE>, DepositCache<CACHE>> cache;
   if constexpr (RADP) cache.init(lane, a.rec_base);
-  else if constexpr (THIN) cache.init(lane, a.mark_key, a.mark);
   else cache.init(lane);
   SplitStage stage;
   stage.init(home);
@@ -1457,11 +1420,9 @@ void trace_level_kernel(TraceArgs<R> a) {
           dkey = L.slot0 + L.astride * (uint32_t)L.lin + 1u;
           dep = true;
         } else {
-          // the tree's mark on the cell (idempotent: any thin ray may set
-          // it), combined in the deposit table with the marks of other trees
-          dkey = a.mark_key + (uint32_t)(L.mark_base + (long long)L.lin);
-          dval = __longlong_as_double((long long)L.mark_bit);
-          dep = true;
+          // the tree's mark on the cell: a plain byte store (every thin ray
+          // of the tree that crosses the cell stores the same 1)
+          a.mark[L.mark_base + (long long)L.lin] = 1;
         }
         L.rem -= tc64;
         L.segs++;
@@ -1674,7 +1635,7 @@ __global__ void reset_stats_kernel(SgStats* stats, int first, int count) {
 template <typename R>
 __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, const ProblemDev* probs,
                             long long cell_begin, long long cell_end, R* kappa, double* acc, Counters* ctr,
-                            uint32_t* mark, double* kappa64) {
+                            uint8_t* mark, double* kappa64) {
   for (long long c = cell_begin + blockIdx.x * (long long)blockDim.x + threadIdx.x; c < cell_end;
        c += (long long)gridDim.x * blockDim.x) {
     const int g = grid_of(grids, n_grids, c);
@@ -1700,7 +1661,7 @@ __global__ void prep_kernel(const GridDev* grids, int n_grids, int grid_base, co
     const long long base = P.acc_off + P.acc_stride * (c - P.cell_off), gstride = P.acc_stride * P.n_cells;
     for (int gr = 0; gr < P.n_groups; ++gr)
       for (int k = 0; k < P.acc_stride; ++k) acc[base + gr * gstride + k] = 0.0;
-    for (int w = 0; w < P.mark_words; ++w) mark[P.mark_off + w * P.n_cells + (c - P.cell_off)] = 0u;
+    for (int t = 0; t < P.mark_trees; ++t) mark[P.mark_off + t * P.n_cells + (c - P.cell_off)] = 0;
   }
 }
 
@@ -1715,7 +1676,7 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
                                                                const FinalBlock* blocks, const double* acc,
                                                                const double* eexc, double* partial,
                                                                const Counters* ctr, const SgDev* sgs,
-                                                               const uint32_t* mark) {
+                                                               const uint8_t* mark) {
   __shared__ double red[kFinalBlock / kWave];
   if (ctr->err & kErrBadInput) return;
   const FinalBlock B = blocks[blockIdx.x];
@@ -1742,23 +1703,19 @@ __global__ __launch_bounds__(kFinalBlock) void finalize_kernel(const GridDev* gr
         for (int d = 0; d < 3; ++d) mom[d] += acc[base + gr * gstride + 1 + d];
     }
     double kt = 0.0, ht = 0.0;
-    if (P.mark_words > 0) {
+    if (P.mark_trees > 0) {
       const int i = (int)(local % G.nx), j = (int)((local / G.nx) % G.ny);
       const int kk = (int)(local / ((long long)G.nx * G.ny));
       const double cx = G.is_child ? (double)G.ox + 0.5 * ((double)i + 0.5) : (double)i + 0.5;
       const double cy = G.is_child ? (double)G.oy + 0.5 * ((double)j + 0.5) : (double)j + 0.5;
       const double cz = G.is_child ? (double)G.oz + 0.5 * ((double)kk + 0.5) : (double)kk + 0.5;
-      for (int w = 0; w < P.mark_words; ++w) {
-        uint32_t bits = mark[P.mark_off + w * P.n_cells + (c - P.cell_off)];
-        while (bits) {
-          const int t = 32 * w + __ffs(bits) - 1;
-          bits &= bits - 1u;
-          const SgDev& S = sgs[P.sg_first + t];
-          const double dx0 = cx - S.sx, dx1 = cy - S.sy, dx2 = cz - S.sz;
-          const double kv = S.thin_coef / (dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
-          kt += kv;
-          ht += kv * eexc[P.eexc_off + t % P.n_groups];
-        }
+      for (int t = 0; t < P.mark_trees; ++t) {
+        if (!mark[P.mark_off + t * P.n_cells + (c - P.cell_off)]) continue;
+        const SgDev& S = sgs[P.sg_first + t];
+        const double dx0 = cx - S.sx, dx1 = cy - S.sy, dx2 = cz - S.sz;
+        const double kv = S.thin_coef / (dx0 * dx0 + dx1 * dx1 + dx2 * dx2);
+        kt += kv;
+        ht += kv * eexc[P.eexc_off + t % P.n_groups];
       }
     }
     const double nabs = (double)G.n_h[local] * (double)G.x_hi[local];
@@ -1814,7 +1771,7 @@ hipError_t launch_reset_levels(hipStream_t s, Counters* ctr) {
 template <typename R>
 hipError_t launch_prep(hipStream_t s, int num_cu, const GridDev* grids, int n_grids, int grid_base,
                        const ProblemDev* probs, long long cell_begin, long long cell_end, R* kappa, double* acc,
-                       Counters* ctr, uint32_t* mark, double* kappa64) {
+                       Counters* ctr, uint8_t* mark, double* kappa64) {
   long long blocks = (cell_end - cell_begin + 255) / 256;
   if (blocks > 32LL * num_cu) blocks = 32LL * num_cu;
   if (blocks < 1) blocks = 1;
@@ -1977,7 +1934,7 @@ hipError_t launch_prefill_level(hipStream_t s, int num_cu, const RayQueue& pool,
 
 hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, const ProblemDev* probs,
                            const FinalBlock* blocks, const double* acc, const double* eexc, double* partial,
-                           const Counters* ctr, const SgDev* sgs, const uint32_t* mark) {
+                           const Counters* ctr, const SgDev* sgs, const uint8_t* mark) {
   if (n_blocks < 1) return hipSuccess;
   hipLaunchKernelGGL(finalize_kernel, dim3(n_blocks), dim3(kFinalBlock), 0, s, grids, probs, blocks, acc, eexc,
                      partial, ctr, sgs, mark);
@@ -1985,9 +1942,9 @@ hipError_t launch_finalize(hipStream_t s, int n_blocks, const GridDev* grids, co
 }
 
 template hipError_t launch_prep<float>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                       long long, float*, double*, Counters*, uint32_t*, double*);
+                                       long long, float*, double*, Counters*, uint8_t*, double*);
 template hipError_t launch_prep<double>(hipStream_t, int, const GridDev*, int, int, const ProblemDev*, long long,
-                                        long long, double*, double*, Counters*, uint32_t*, double*);
+                                        long long, double*, double*, Counters*, uint8_t*, double*);
 template hipError_t launch_trace_level<float>(hipStream_t, int, const TraceArgs<float>&, bool, bool, bool, bool);
 template hipError_t launch_trace_level<double>(hipStream_t, int, const TraceArgs<double>&, bool, bool, bool, bool);
 template hipError_t launch_trace_level_halt<float>(hipStream_t, int, const TraceArgs<float>&, bool);

@@ -527,20 +527,16 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
                                        ": the optically-thin approximation does not take radiation pressure");
   if (thin && radp)
     return fail(c, MORAY_EINVAL, "a batch cannot mix the optically-thin approximation with radiation pressure");
-  // optically-thin marks: one bit per (source, group) tree and cell, in
-  // words of 32 trees, per problem that uses the approximation; the trace
-  // combines them in its deposit table under keys n_sums + word
+  // optically-thin marks: one byte per (source, group) tree and cell, per
+  // problem that uses the approximation (the paper's marker field holds a
+  // bit per source; a byte takes a plain store where a bit needs an atomic)
   long long n_mark = 0;
   for (int i = 0; i < n_probs; ++i)
     if (probs[i].params.tau_thin > 0.0) {
-      const long long trees = (long long)probs[i].n_sources * probs[i].spectrum->n_groups;
-      pdev[i].mark_words = (int)((trees + 31) / 32);
+      pdev[i].mark_trees = probs[i].n_sources * probs[i].spectrum->n_groups;
       pdev[i].mark_off = n_mark;
-      n_mark += pdev[i].mark_words * pdev[i].n_cells;
+      n_mark += pdev[i].mark_trees * pdev[i].n_cells;
     }
-  if (n_sums + n_mark >= (long long)kNoSlot)
-    return fail(c, MORAY_EINVAL, "a batch with the optically-thin approximation needs fewer than 2^32 - 1 "
-                                 "accumulators and marker words together");
   (void)n_acc;
   // the trace kernel addresses accumulators with 32-bit indices
   if (n_sums >= (long long)kNoSlot)
@@ -607,8 +603,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       d.tau_thin = P.params.tau_thin;
       d.four_pi_phi_thin = 4.0 * kPiConst * phi_thin;
       d.split_t2_thin = phi_thin > 0.0 ? (float)(12.0 / (4.0 * kPiConst * phi_thin)) : FLT_MAX;
-      d.mark_bit = 1u << (t % 32);
-      d.mark_base = pd.mark_off + (long long)(t / 32) * pd.n_cells - pd.cell_off;
+      d.mark_base = pd.mark_off + (long long)t * pd.n_cells - pd.cell_off;
       d.thin_coef = d.sigma64 * (d.P0 * npix0) / (4.0 * kPiConst * dx_root * dx_root);
     }
     sg_bound[k] = level_rays_bound(P);
@@ -620,7 +615,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
   size_t cap = c->queue_cap_user;
   const size_t per_ray = 2 * (sizeof(uint64_t) + sizeof(uint32_t) + 2 * sizeof(double));
   const size_t out_stage = odev ? 0 : (size_t)n_cells * (radp ? 40 : 16);
-  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (size_t)n_mark * 4 +
+  const size_t fixed = (size_t)n_cells * rsz + (size_t)n_sums * 8 + (size_t)n_mark +
                        (thin && fp32 ? (size_t)n_cells * 8 : 0) + (fdev ? 0 : (size_t)n_cells * 8) + out_stage + (size_t)n_sg * (sizeof(SgDev) + sizeof(SgStats)) +
                        grids.size() * sizeof(GridDev) + fblocks.size() * (sizeof(FinalBlock) + 8) +
                        (c->arena ? (size_t)(1 << 20) : (size_t)(64 << 20));
@@ -641,7 +636,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       (st = ensure(c, c->ctr, sizeof(Counters), "counters")) ||
       (st = ensure(c, c->kappa, (size_t)n_cells * rsz, "absorber columns")) ||
       (st = ensure(c, c->acc, (size_t)std::max<long long>(1, n_sums) * 8, "accumulators")) ||
-      (n_mark && (st = ensure(c, c->mark, (size_t)n_mark * 4, "optically-thin marks"))) ||
+      (n_mark && (st = ensure(c, c->mark, (size_t)n_mark, "optically-thin marks"))) ||
       (thin && fp32 && (st = ensure(c, c->kappa64, (size_t)n_cells * 8, "float64 absorber columns"))) ||
       (st = ensure(c, c->eexc, eexc.size() * 8, "group energies")) ||
       (st = ensure(c, c->fblocks, fblocks.size() * sizeof(FinalBlock), "finalize blocks")) ||
@@ -802,7 +797,7 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
       if (capturing) { abandon_capture(strm); continue; }
       return MORAY_EDEVICE;
     }
-    uint32_t* mark = n_mark ? (uint32_t*)c->mark.p : nullptr;
+    uint8_t* mark = n_mark ? (uint8_t*)c->mark.p : nullptr;
     double* kappa64 = thin && fp32 ? (double*)c->kappa64.p : nullptr;
     hipError_t e = fp32 ? launch_prep<float>(strm, c->num_cu, (GridDev*)c->grids.p, n_grids_tot, 0,
                                              (ProblemDev*)c->probs.p, 0, n_cells, (float*)c->kappa.p, (double*)c->acc.p, ctr,
@@ -837,7 +832,6 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           A.mark = mark;
-          A.mark_key = (uint32_t)n_sums;
           A.kappa64 = kappa64;
           e = launch_trace_level<float>(strm, blocks, A, c->cache, cover, radp, thin);
         } else {
@@ -849,7 +843,6 @@ moray_status trace_impl(moray_ctx* c, const moray_problem* probs, int n_probs, u
           A.seed_sg_begin = lo < hi ? lo : 0; A.seed_sg_end = lo < hi ? hi : 0;
           A.chunk = c->chunk; A.refill = c->refill; A.max_steps = max_steps; A.reserve = reserve;
           A.mark = mark;
-          A.mark_key = (uint32_t)n_sums;
           e = launch_trace_level<double>(strm, blocks, A, c->cache, cover, radp, thin);
         }
         if (!hip_ok(c, e, "trace")) {
