@@ -2,7 +2,9 @@
 against moray_trace on the same inputs, through the C ABI: two calls in a
 row, the second with a smaller batch (the fixed scratch array keeps the first
 call's contents, so anything left over would show), in both precisions, and
-a batch too large for the array rejected with MORAY_ENOMEM. Results must
+a batch too large for the array rejected with MORAY_ENOMEM, and batches
+with the optically-thin approximation (its marks and float64 columns live in
+the array as well). Results must
 equal moray_trace's to summation order: counts exactly, k_ph and heating to
 1e-9 relative (1e-4 is the oracle bar of the mixed path; both calls run the
 same kernels on the same inputs)."""
@@ -14,7 +16,7 @@ from paper_1012_2865_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-COUNTS = ("segments", "splits", "rays_seeded", "rays_escaped", "rays_truncated")
+COUNTS = ("segments", "thin_segments", "splits", "rays_seeded", "rays_escaped", "rays_truncated")
 
 
 def _outputs(problems, device=True):
@@ -74,6 +76,34 @@ def test_noalloc_equals_trace_twice_second_smaller(precision):
         got = M.moray_trace_noalloc(ctx, probs, _outputs(probs, device=False), out_on_device=False)
         want = M.moray_trace(ref, probs, out_on_device=False)
         _same(got[0], want[0], f"noalloc p{precision} host io")
+    finally:
+        M.moray_free(ctx)
+        M.moray_free(ref)
+
+
+def _thin(item, n, n_src):
+    """ionised lognormal gas with the optically-thin approximation: its marks
+    and float64 columns come from the scratch array too"""
+    p = W.lognormal_problem(93, item, n, n_src)
+    g = p.grids[0]
+    p.grids[0] = W.Grid(g.n_h, (g.x_hi * np.float32(0.05)).astype(np.float32), g.dx_cm)
+    p.params = W.Params(**{**p.params.__dict__, "tau_thin": 0.1})
+    return p
+
+
+@pytest.mark.parametrize("precision", [M.MORAY_FP32_ACC64, M.MORAY_FP64])
+def test_noalloc_optically_thin_twice_second_smaller(precision):
+    ctx = M.moray_init(device=0, precision=precision)
+    ref = M.moray_init(device=0, precision=precision)
+    try:
+        for call, probs in enumerate(([_thin(7, 32, 3), W.lognormal_problem(93, 8, 24, 2)], [_thin(9, 24, 2)])):
+            dev = [M.problem_to_device(p) for p in probs]
+            print(f"[noalloc thin p{precision}] call {call}: {len(probs)} problems", flush=True)
+            got = M.moray_trace_noalloc(ctx, dev, _outputs(probs))
+            want = M.moray_trace(ref, dev)
+            assert want[0]["thin_segments"] > 0
+            for i, (g, w) in enumerate(zip(got, want)):
+                _same(g, w, f"noalloc thin p{precision} call {call} problem {i}")
     finally:
         M.moray_free(ctx)
         M.moray_free(ref)
