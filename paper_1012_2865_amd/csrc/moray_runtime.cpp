@@ -331,9 +331,8 @@ moray_status moray_init(moray_ctx** out, const moray_init_params* p) {
   hipError_t he = hipGetDeviceCount(&n);
   if (he != hipSuccess || n < 1)
     return init_fail(MORAY_EDEVICE, std::string("no usable GPU: hipGetDeviceCount: ") + hipGetErrorString(he) +
-                                        " (if this process ran a many-threaded OpenMP region before its first HIP "
-                                        "call, create the context before that region: such a first HIP "
-                                        "initialisation has been seen to report no device)");
+                                        " (a process that loads a second HIP runtime, such as PyTorch's, after this "
+                                        "library's leaves one of them without a device: load the other one first)");
   if (p->device < 0 || p->device >= n) return init_fail(MORAY_EINVAL, "device ordinal out of range");
   if ((he = hipSetDevice(p->device)) != hipSuccess)
     return init_fail(MORAY_EDEVICE, std::string("hipSetDevice: ") + hipGetErrorString(he));

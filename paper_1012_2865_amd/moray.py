@@ -108,6 +108,14 @@ def load_library(path: str = LIB_PATH):
     if _lib is None:
         if not os.path.exists(path):
             raise ImportError(f"{path} is missing: build it with `python -m paper_1012_2865_amd.build`")
+        # PyTorch carries its own HIP runtime. Loaded first, it also serves the
+        # library (same soname); loaded after the library's runtime it brings a
+        # second one into the process, and whichever initialises last finds no
+        # device. So torch, when it is installed, is imported before the library.
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         lib = ctypes.CDLL(path)
         lib.moray_init.argtypes = [ctypes.POINTER(ctypes.c_void_p), ctypes.POINTER(InitParams)]
         lib.moray_init.restype = ctypes.c_int

@@ -23,10 +23,12 @@ def oracle_lib():
 
 
 @pytest.fixture(autouse=True, scope="session")
-def _hip_runtime_before_oracle():
-    """Initialise the library's HIP runtime before any test runs the oracle
-    with many OpenMP threads: on the MI355X machine a first HIP initialisation
-    after a 16-thread OpenMP region reported no device."""
+def _one_hip_runtime():
+    """Load torch's HIP runtime, then create and free one library context, at
+    the start of a GPU session: the library then runs on torch's runtime (the
+    binding imports torch before it loads the library; a second HIP runtime
+    loaded into the same process leaves the one initialised last without a
+    device)."""
     try:
         import torch
         if torch.cuda.is_available():
