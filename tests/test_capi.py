@@ -70,10 +70,10 @@ int main(void) {
   S(moray_init_params) O(moray_init_params, hip_stream) O(moray_init_params, profile) O(moray_init_params, deposit_cache) O(moray_init_params, reserve_rays)
   S(moray_source) S(moray_spectrum) O(moray_spectrum, e_ion_ev)
   S(moray_grid) O(moray_grid, offset) O(moray_grid, n_h) O(moray_grid, x_hi)
-  S(moray_trace_params) O(moray_trace_params, p_min_frac) O(moray_trace_params, covering)
+  S(moray_trace_params) O(moray_trace_params, p_min_frac) O(moray_trace_params, covering) O(moray_trace_params, tau_thin)
   S(moray_problem) O(moray_problem, params)
   S(moray_result) O(moray_result, accel) O(moray_result, emitted) O(moray_result, segments) O(moray_result, peak_level_rays)
-  O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph)
+  O(moray_result, trace_ms) O(moray_result, trace_launches) O(moray_result, t_admit) O(moray_result, t_done) O(moray_result, from_graph) O(moray_result, thin_segments)
   S(moray_equilibrium_params) O(moray_equilibrium_params, tol) O(moray_equilibrium_params, max_iter)
   S(moray_evolve_params) O(moray_evolve_params, tau_front) O(moray_evolve_params, t_end) O(moray_evolve_params, max_steps)
   return 0;
@@ -169,3 +169,11 @@ def test_prepared_batch_descriptors_match_a_fresh_marshal():
         assert b.results[i].k_ph == res[i].k_ph == outs[i][0].ctypes.data
         view = b.views[i]["k_ph"][0]
         assert view.shape == probs[i].grids[0].n_h.shape and np.shares_memory(view, outs[i][0])
+
+
+def test_binding_loads_torch_before_the_library():
+    """PyTorch's HIP runtime must be in the process before the library's, so
+    that the library shares it (a second runtime leaves one without a device)."""
+    code = "import sys; from paper_1012_2865_amd import moray as M; M.load_library(); print('torch' in sys.modules)"
+    out = subprocess.check_output(["python", "-c", code], cwd=ROOT, text=True).strip().splitlines()[-1]
+    assert out == "True"
