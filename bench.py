@@ -286,10 +286,17 @@ def _counter_pass(workload, variant="plain", settings=None):
     microbenchmark whose known atomic count calibrates TCC_EA0_ATOMIC. Meant
     to run under `rocprofv3 --pmc`. The variant "radpres" traces with the
     radiation-pressure sums; "td" runs six time-dependent steps (c dt_P = 32
-    cells), the last of which is the measured one."""
+    cells), the last of which is the measured one; "thin" traces the 128^3
+    workload in ionised gas with the optically-thin approximation."""
     import torch
     from paper_1012_2865_amd import moray as M
+    from paper_1012_2865_amd import workloads as W
     problems, config = _workload(workload)
+    if variant == "thin":
+        if workload != "c1":
+            raise SystemExit("the thin variant's counter pass runs on the 128^3 workload (--workload c1)")
+        problems = [W.config1_ionised(0.1)]
+        config = {"workload": problems[0].name}
     dev = [M.problem_to_device(p) for p in problems]
     if settings is None and workload == "c1":
         ctx, settings = M.moray_init(device=0, precision=M.MORAY_FP32_ACC64), {"source": "library defaults"}
@@ -335,7 +342,7 @@ def _read_counter_csv(folder, counter):
     return [(k, v) for _, k, v in rows]
 
 
-def _write_traffic(fetch_dir, write_dir, workload, launches):
+def _write_traffic(fetch_dir, write_dir, workload, launches, variant="plain"):
     """Turn two counter passes into HBM bytes per trace-kernel launch. The
     trace kernel's dispatches of the second (measured) trace are averaged; the
     1 GiB copy's reading calibrates KiB per byte moved."""
@@ -356,7 +363,7 @@ def _write_traffic(fetch_dir, write_dir, workload, launches):
         factor = COPY_BYTES / (copy_kib * 1024.0)
         out[name] = {"kib_per_launch": sum(measured) / launches, "copy_kib": copy_kib, "bytes_per_byte": factor,
                      "bytes_per_launch": sum(measured) / launches * 1024.0 * factor}
-    key = f"{workload}/fp32"
+    key = f"{workload}/fp32" if variant == "plain" else f"{workload}/fp32/{variant}"
     rec["per_launch_bytes"][key] = out["fetch"]["bytes_per_launch"] + out["write"]["bytes_per_launch"]
     rec.setdefault("detail", {})[key] = out
     with open(TRAFFIC_FILE, "w") as f:
@@ -602,7 +609,7 @@ def _radpres_c1(M, steps, oracle_threads=0):
     return out
 
 
-THIN_BYTES_PER_SEGMENT = 12   # a thin segment: absorber read + the marker word's read-modify-write
+THIN_BYTES_PER_SEGMENT = 5    # a thin segment: absorber read (4 B) + the mark (a 1 B store)
 
 
 def _with_tau(p, tau):
@@ -617,7 +624,7 @@ def _thin_workloads(M, steps, peaks=None, oracle_threads=0):
     box of the angular-resolution test (section 7.2, 128^3), each traced with
     the approximation (tau_thin = 0.1) and without it, mixed precision,
     library defaults, graph replay; the thin launch sequence's roofline from
-    HIP-event launch times (36 B per thick segment, 12 B per thin one)."""
+    HIP-event launch times (36 B per thick segment, 5 B per thin one)."""
     import torch
     out = {}
     settings = {"chunk_rays": 256, "refill_lanes": 64, "reserve_rays": 0, "waves_per_cu": 0}
@@ -636,12 +643,19 @@ def _thin_workloads(M, steps, peaks=None, oracle_threads=0):
         tsegs = res[0]["thin_segments"]
         algo = BYTES_PER_SEGMENT["fp32"] * (ksegs - tsegs) + THIN_BYTES_PER_SEGMENT * tsegs
         achieved = algo / (kms * 1e-3) / 1e9
+        traffic = _traffic("c1", "fp32/thin") if name.startswith("ionised") else None
+        apl = _atomics_per_launch("c1", "fp32/thin") if name.startswith("ionised") else None
         rec = {"workload": name, "ms_per_step": st * 1e3, "segments_per_step": segt, "thin_segments": tsegs,
                "segments_per_s": segt / st, "plain_ms_per_step": sp * 1e3, "plain_segments_per_step": segp,
                "speedup_over_plain": sp / st, "absorbed_over_emitted": res[0]["absorbed"] / res[0]["emitted"],
                "dtype": "f32+f64acc",
                "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                            "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                            "traffic_source": "FETCH_SIZE + WRITE_SIZE counter passes of this kernel source "
+                                              "(--counter-variant thin), per launch, read from "
+                                              "profiles/traffic_trace_level.json (null: none for this workload "
+                                              "or kernel changed since)",
+                            "float64_atomics_per_launch": apl,
                             "kernel": "trace_level_kernel<float, true, kPhysThin>", "launches_per_step": launches,
                             "avg_launch_ms": kms / launches if launches else None,
                             "algorithmic_bytes_per_launch": algo / launches if launches else None}}
@@ -907,8 +921,9 @@ def main():
                     help="run the device-peak microbenchmark sweep, print its summary as markdown and exit")
     ap.add_argument("--counter-pass", action="store_true",
                     help="run one traced workload and a 1 GiB copy for rocprofv3 --pmc, then exit")
-    ap.add_argument("--counter-variant", choices=("plain", "radpres", "td"), default="plain",
-                    help="with --counter-pass: trace with radiation pressure, or time-dependent steps")
+    ap.add_argument("--counter-variant", choices=("plain", "radpres", "td", "thin"), default="plain",
+                    help="with --counter-pass: trace with radiation pressure, time-dependent steps or the "
+                         "optically-thin approximation (ionised 128^3 workload)")
     ap.add_argument("--read-atomics", nargs=2, metavar=("ATOMIC_DIR", "LAUNCHES"),
                     help="host only: print the float64 atomics per launch of the last LAUNCHES trace "
                          "dispatches of a TCC_EA0_ATOMIC_sum pass, calibrated like --write-atomics")
@@ -919,7 +934,8 @@ def main():
     args = ap.parse_args()
     settings = _parse_settings(args.settings) if args.settings else None
     if args.write_traffic:
-        _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]))
+        _write_traffic(args.write_traffic[0], args.write_traffic[1], args.workload, int(args.write_traffic[2]),
+                       args.counter_variant)
         return
     if args.write_atomics:
         _write_atomics(args.write_atomics[0], args.workload, int(args.write_atomics[1]), args.counter_variant)
