@@ -52,7 +52,9 @@
  *     k_ph and k (E - E_ion) to the heating, where Omega_ray = 4 pi / N_pix(l)
  *     is the ray's solid angle and r_cell the distance (cm) from the source
  *     to the cell centre, and marks the cell for that item (a byte per cell
- *     here, one bit per item of a 32-bit field in the paper);
+ *     here, one bit per item of a 32-bit field in the paper); a ray that only
+ *     grazes the cell, along a segment shorter than 2^-40 of its exit radius
+ *     (through an edge or a corner), does not count as crossing it;
  *   - in a cell that holds the source (inside or on its boundary, where
  *     r_cell can vanish), adds the general deposit P (1 - e^-tau_cell) to the
  *     cell's rate instead, still removing no photons, and marks nothing. (A
@@ -368,7 +370,7 @@ static void march(const job* J, int si, int gi, oray first, acc* A, csum* esc, c
             const double fc = J->par->covering ? covering_factor(sl, n, c, R.r, dr, h, R.level) : 1.0;
             A->thin_dep[o] += dP * fc;
             A->thin_energy[o] += dP * fc * eexc;
-          } else if (!A->mark[o]) {
+          } else if (!A->mark[o] && dr > ldexp(t_exit, -40)) {
             /* Eq. optthin: the ray's flux P / (Omega_ray r^2) taken at the
                cell centre, once per cell for this (source, group) */
             double r2 = 0.0;
