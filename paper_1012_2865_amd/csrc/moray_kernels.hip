@@ -1419,9 +1419,12 @@ void trace_level_kernel(TraceArgs<R> a) {
           }
           dkey = L.slot0 + L.astride * (uint32_t)L.lin + 1u;
           dep = true;
-        } else {
+        } else if (sizeof(R) == 4 || (double)dr > L.g.exit64(ax) * 0x1p-40) {
           // the tree's mark on the cell: a plain byte store (every thin ray
-          // of the tree that crosses the cell stores the same 1)
+          // of the tree that crosses the cell stores the same 1); a segment
+          // shorter than 2^-40 of its exit radius (a ray through an edge or
+          // a corner) does not cross the cell, which the float path's
+          // plane-tie test already decides
           a.mark[L.mark_base + (long long)L.lin] = 1;
         }
         L.rem -= tc64;
