@@ -217,6 +217,17 @@ def thin_box(n: int = 128, tau_thin: float = 0.0) -> Problem:
                    Params(phi_c=5.1, level_init=1, tau_thin=tau_thin), name=f"thin_box{n}_corner_source")
 
 
+def angular_box(n: int, phi_c: float, covering: bool = True) -> Problem:
+    """The angular-resolution test (section 7.2): Test 1's 6.6 kpc box of n^3
+    cells in optically thin gas (n_H = 1e-3, x_HI = 1e-4) with its 5e48 ph/s
+    13.6 eV source on the box's corner, traced once at the given phi_c, with
+    the covering-factor correction (section 2.3) on unless asked otherwise."""
+    g = uniform_grid(n, 6.6 * KPC_CM / n, 1e-3, 1e-4)
+    return Problem([g], np.array([[0.0, 0.0, 0.0, 5e48]]), hydrogen_spectrum([13.6]),
+                   Params(phi_c=phi_c, level_init=1, level_max=14, p_min_frac=1e-8, covering=covering),
+                   name=f"angular_box{n}_phi{phi_c}")
+
+
 C2_EDGES = (32, 48, 64, 96)
 
 

@@ -60,3 +60,24 @@ def check(res, ref, rel_tol, name="", fp64=False, count_rtol=1e-5):
             # one flipped split decision turns one ray into four
             assert abs(res[k] - T[k]) <= count_rtol * T[k] + 2 + 3 * flips, (k, res[k], T[k])
     return worst
+
+
+def inverse_square_deviation(k_ph, problem, r_min=4.0):
+    """k_ph / k_exact - 1 over the root cells whose centres lie farther than
+    r_min cells from the problem's one source, where k_exact =
+    sigma Ndot e^{-kappa r} / (4 pi r^2) is the rate of an unsplit point source
+    in a uniform medium (Eqs. flux and kph with the column kappa r of a
+    uniform medium). The angular-resolution test takes the standard deviation
+    of this field."""
+    import math
+    g = problem.grids[0]
+    n_h, x_hi = float(np.asarray(g.n_h).flat[0]), float(np.asarray(g.x_hi).flat[0])
+    nz, ny, nx = np.asarray(g.n_h).shape
+    sx, sy, sz, ndot = (float(v) for v in problem.sources[0])
+    sigma = float(problem.spectrum.sigma_cm2[0])
+    kappa = sigma * n_h * x_hi * g.dx_cm
+    R = np.sqrt(((np.arange(nx) + 0.5) - sx)[None, None, :] ** 2 + ((np.arange(ny) + 0.5) - sy)[None, :, None] ** 2 +
+                ((np.arange(nz) + 0.5) - sz)[:, None, None] ** 2)
+    m = R > r_min
+    want = sigma * ndot * np.exp(-kappa * R[m]) / (4.0 * math.pi * (R[m] * g.dx_cm) ** 2)
+    return np_(k_ph).reshape(nz, ny, nx)[m] / want - 1.0
