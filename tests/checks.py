@@ -32,10 +32,13 @@ def field_err(got, want, floor=1e-6):
     return rel, absr
 
 
-def check(res, ref, rel_tol, name="", fp64=False, count_rtol=1e-5):
+def check(res, ref, rel_tol, name="", fp64=False, count_rtol=1e-5, conserving=True):
     """Hold one GPU result to the oracle's: fields per cell, totals, ledger and
     counts. Returns the worst relative field error. count_rtol bounds the
-    relative difference of the mixed-precision counts (near-ties)."""
+    relative difference of the mixed-precision counts (near-ties). With the
+    covering factor (conserving=False) the absorbed total is scaled cell by
+    cell and no longer balances the photons emitted; it is held to the
+    oracle's instead."""
     T = ref["totals"]
     worst = 0.0
     for q in range(len(ref["k_ph"])):
@@ -48,7 +51,10 @@ def check(res, ref, rel_tol, name="", fp64=False, count_rtol=1e-5):
     bal = res["absorbed"] + res["escaped"] + res["truncated"] - res["emitted"]
     print(f"[{name}] conservation {bal / res['emitted']:.3e}; segments gpu {res['segments']} oracle {T['segments']}; "
           f"splits {res['splits']}/{T['splits']}", flush=True)
-    assert abs(bal) <= 1e-9 * res["emitted"]
+    if conserving:
+        assert abs(bal) <= 1e-9 * res["emitted"]
+    else:
+        assert res["absorbed"] == pytest.approx(T["absorbed"], rel=max(rel_tol, 1e-12), abs=1e-12 * T["emitted"])
     assert res["emitted"] == pytest.approx(T["emitted"], rel=1e-14)
     assert res["rays_seeded"] + 4 * res["splits"] == res["splits"] + res["rays_escaped"] + res["rays_truncated"]
     assert res["escaped"] == pytest.approx(T["escaped"], rel=max(rel_tol, 1e-12), abs=1e-12 * T["emitted"])
