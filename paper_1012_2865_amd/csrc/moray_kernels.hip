@@ -1188,6 +1188,26 @@ void trace_level_kernel(TraceArgs<R> a) {
   const unsigned long long n_seeds = (unsigned long long)(a.seed_sg_end - a.seed_sg_begin) * npix;
   const unsigned long long* cnt_in = a.ctr->count[a.cin];
   unsigned long long* head_in = a.ctr->head[a.cin];
+  // rays claimed per atomic: the launch's setting, halved while the level
+  // holds less than one claim for every wave of the launch, down to one ray
+  // per lane, so that a level of few rays spreads over the waves instead of
+  // queueing several rays behind each lane of a few of them
+  // (kept in LDS: the claim path alone reads it, and a scalar register held
+  // through the step loop would push the loop's own values out of theirs)
+  __shared__ unsigned s_chunk[kTraceBlock / kWave];
+  {
+    unsigned long long n = lane < K ? min(cnt_in[lane], a.seg_cap) : 0ull;
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) {
+      const unsigned lo = __shfl_xor((unsigned)n, o), hi = __shfl_xor((unsigned)(n >> 32), o);
+      n += ((unsigned long long)hi << 32) | lo;
+    }
+    n += n_seeds;
+    const unsigned long long waves = (unsigned long long)gridDim.x * (kTraceBlock / kWave);
+    unsigned chunk = (unsigned)a.chunk;
+    while (chunk >= 2u * kWave && (unsigned long long)chunk * waves > n) chunk >>= 1;
+    s_chunk[threadIdx.x / kWave] = chunk;   // every lane holds the same sum and stores the same value
+  }
   // the wave's home segment: it claims there first and writes children there
   const int home = (int)((blockIdx.x * (kTraceBlock / kWave) + threadIdx.x / kWave) % (unsigned)K);
   const Tracer<R> T(a);
@@ -1263,13 +1283,14 @@ void trace_level_kernel(TraceArgs<R> a) {
                   uniform64(__hip_atomic_load(&head_in[w_seg], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
               if (seen < c_size) {
                 unsigned long long b = 0;
-                if (lane == 0) b = atomicAdd(&head_in[w_seg], (unsigned long long)a.chunk);
+                const unsigned long long chunk = uniform32((int)s_chunk[threadIdx.x / kWave]);
+                if (lane == 0) b = atomicAdd(&head_in[w_seg], chunk);
                 b = bcast64(b, 0);
                 if (b < c_size) {
                   w_nch = c_nch;
                   w_slo = c_slo;
                   w_next = b;
-                  w_end = min(b + (unsigned long long)a.chunk, c_size);
+                  w_end = min(b + chunk, c_size);
                   got = true;
                   break;
                 }
@@ -1291,14 +1312,15 @@ void trace_level_kernel(TraceArgs<R> a) {
             const unsigned long long s_slo = ((unsigned long long)sg * n_seeds) >> kshift;
             const unsigned long long s_size = s_nch + ((((unsigned long long)sg + 1) * n_seeds) >> kshift) - s_slo;
             unsigned long long b = 0;
-            if (lane == 0) b = atomicAdd(&head_in[sg], (unsigned long long)a.chunk);
+            const unsigned long long chunk = uniform32((int)s_chunk[threadIdx.x / kWave]);
+            if (lane == 0) b = atomicAdd(&head_in[sg], chunk);
             b = bcast64(b, 0);
             w_seg = sg;
             if (b < s_size) {
               w_nch = s_nch;
               w_slo = s_slo;
               w_next = b;
-              w_end = min(b + (unsigned long long)a.chunk, s_size);
+              w_end = min(b + chunk, s_size);
               got = true;
               break;
             }
