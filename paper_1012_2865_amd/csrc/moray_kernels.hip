@@ -714,27 +714,32 @@ struct Tracer {
 // Consecutive rays of a lane seldom share a tree, and a global atomic per ray
 // end would sit in the same in-order memory counter as the next absorber
 // gather. A tree that finds no free entry among its two probes adds to the
-// global counters directly.
+// global counters directly. THIN adds a fifth count, the ray's optically thin
+// segments (the rays of one tree tend to end together, and one global atomic
+// per ray end on the tree's counter serialised at the memory side).
+template <bool THIN>
 struct TallyTable {
+  static constexpr int kRows = THIN ? 5 : 4;
   uint32_t* key;                 // kTallySlots tree indices (kNoTree: free)
-  unsigned long long* cnt;       // [4][kTallySlots]: segs, splits, n_esc, n_trunc
+  unsigned long long* cnt;       // [kRows][kTallySlots]: segs, splits, n_esc, n_trunc(, thin_segs)
   double* sum;                   // [2][kTallySlots]: esc_P, trunc_P
 
   // all threads of the block; followed by a block barrier
   __device__ void init() {
     __shared__ uint32_t skey[kTallySlots];
-    __shared__ unsigned long long scnt[4 * kTallySlots];
+    __shared__ unsigned long long scnt[kRows * kTallySlots];
     __shared__ double ssum[2 * kTallySlots];
     key = skey; cnt = scnt; sum = ssum;
     for (int i = threadIdx.x; i < kTallySlots; i += blockDim.x) {
       key[i] = kNoTree;
-      cnt[i] = cnt[kTallySlots + i] = cnt[2 * kTallySlots + i] = cnt[3 * kTallySlots + i] = 0ull;
+#pragma unroll
+      for (int r = 0; r < kRows; ++r) cnt[r * kTallySlots + i] = 0ull;
       sum[i] = sum[kTallySlots + i] = 0.0;
     }
   }
   // kind: 0 escaped, 1 truncated, 2 split, 3 halted (its segments only: the
   // photons it holds are summed from the halt list)
-  __device__ void add(SgStats* stats, uint32_t sg, unsigned segs, double P, int kind) {
+  __device__ void add(SgStats* stats, uint32_t sg, unsigned segs, double P, int kind, unsigned tsegs = 0u) {
     const uint32_t h0 = (sg * 0x9E3779B1u) >> (32 - kTallyLog2);
     int slot = -1;
 #pragma unroll
@@ -759,9 +764,13 @@ struct TallyTable {
         __hip_atomic_fetch_add(&cnt[c * kTallySlots + slot], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       if (kind < 2)
         __hip_atomic_fetch_add(&sum[kind * kTallySlots + slot], P, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+      if (THIN && tsegs)
+        __hip_atomic_fetch_add(&cnt[4 * kTallySlots + slot], (unsigned long long)tsegs, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_WORKGROUP);
     } else {
       SgStats& st = stats[sg];
       if (segs) atomicAdd(&st.segs, (unsigned long long)segs);
+      if (THIN && tsegs) atomicAdd(&st.thin_segs, (unsigned long long)tsegs);
       if (kind == 2) {
         atomicAdd(&st.splits, 1ull);
       } else if (kind == 3) {
@@ -790,6 +799,7 @@ struct TallyTable {
         atomicAdd(&st.n_trunc, cnt[3 * kTallySlots + i]);
         unsafeAtomicAdd(&st.trunc_P, sum[kTallySlots + i]);
       }
+      if (THIN && cnt[4 * kTallySlots + i]) atomicAdd(&st.thin_segs, cnt[4 * kTallySlots + i]);
     }
   }
 };
@@ -1177,7 +1187,7 @@ void trace_level_kernel(TraceArgs<R> a) {
   const int lane = threadIdx.x & (kWave - 1);
   const unsigned long long below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
   __shared__ int s_bad;
-  TallyTable tally;
+  TallyTable<THIN> tally;
   tally.init();
   if (threadIdx.x == 0) s_bad = (a.ctr->err & kErrBadInput) != 0;
   __syncthreads();
@@ -1249,10 +1259,7 @@ void trace_level_kernel(TraceArgs<R> a) {
 
   for (;;) {
     if (ended >= 0) {
-      tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
-      if constexpr (THIN) {
-        if (L.tsegs) atomicAdd(&a.stats[L.sg].thin_segs, (unsigned long long)L.tsegs);
-      }
+      tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended, THIN ? L.tsegs : 0u);
       ended = -1;
     }
     // ---- refill idle lanes from the wave's claim on the level queue ----
@@ -1577,10 +1584,7 @@ void trace_level_kernel(TraceArgs<R> a) {
   if (stage.count) stage.write(a, lane);
   cache.flush(a.acc, lane);
   if (ended >= 0) {
-    tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended);
-    if constexpr (THIN) {
-      if (L.tsegs) atomicAdd(&a.stats[L.sg].thin_segs, (unsigned long long)L.tsegs);
-    }
+    tally.add(a.stats, HALT ? L.sg % a.tree_fold : L.sg, L.segs, L.P, ended, THIN ? L.tsegs : 0u);
   }
   if constexpr (HALT) {
     // the unfilled rest of the wave's last block: empty records (no photons,
