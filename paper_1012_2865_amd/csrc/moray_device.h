@@ -34,6 +34,7 @@ constexpr double kLightCms = 2.99792458e10;        // speed of light, cm/s
 constexpr int kEvictCap = 128;                 // per-wave buffer of evicted sums (drained at > 64)
 constexpr int kTallyLog2 = 7;                  // per-block LDS table of per-tree statistics: 128 entries
 constexpr int kTallySlots = 1 << kTallyLog2;
+constexpr int kTallyProbes = 16;               // entries a tree tries before it adds to global counters
 constexpr int kStageFlush = 16;                // split parents staged before their children are written
 constexpr int kStageCap = kStageFlush + kWave; // one iteration adds at most 64 parents
 

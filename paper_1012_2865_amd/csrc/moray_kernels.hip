@@ -713,8 +713,12 @@ struct Tracer {
 // each entry to the tree's global counters once, when all its waves are done.
 // Consecutive rays of a lane seldom share a tree, and a global atomic per ray
 // end would sit in the same in-order memory counter as the next absorber
-// gather. A tree that finds no free entry among its two probes adds to the
-// global counters directly. THIN adds a fifth count, the ray's optically thin
+// gather. A tree that finds no free entry among its kTallyProbes probes adds
+// to the global counters directly: those are atomics on its tree's counters,
+// one address that every ray end of the tree on the device then shares (two
+// probes left enough trees of the 64-grid batch without an entry to take its
+// step from 37.1 to 42.5 ms; 16 and 32 probes measured alike, a probe of
+// the whole table slower). THIN adds a fifth count, the ray's optically thin
 // segments (the rays of one tree tend to end together, and one global atomic
 // per ray end on the tree's counter serialised at the memory side).
 template <bool THIN>
@@ -743,7 +747,7 @@ struct TallyTable {
     const uint32_t h0 = (sg * 0x9E3779B1u) >> (32 - kTallyLog2);
     int slot = -1;
 #pragma unroll
-    for (int probe = 0; probe < 2; ++probe) {
+    for (int probe = 0; probe < kTallyProbes; ++probe) {
       const uint32_t h = (h0 + probe) & (kTallySlots - 1);
       uint32_t k = __hip_atomic_load(&key[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
       if (k == kNoTree) {
