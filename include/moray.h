@@ -73,7 +73,9 @@ typedef struct {
   int waves_per_cu;           /* persistent trace waves per compute unit; 0 = default */
   int refill_lanes;           /* a wave refetches rays once this many of its 64 lanes are idle; 0 = default (64:
                                  once the whole wave is idle, so new rays start together) */
-  int chunk_rays;             /* rays a wave claims from the level queue per atomic; 0 = default (256) */
+  int chunk_rays;             /* rays a wave claims from the level queue per atomic; 0 = default (256);
+                                 the largest claim: on a level with fewer rays than one claim for
+                                 every wave of the launch, waves halve it, down to 64 */
   void* hip_stream;           /* hipStream_t for every launch; NULL = the null stream */
   int profile;                /* nonzero: time every trace-kernel launch with HIP events */
   int deposit_cache;          /* >= 0: combine deposits in a per-wave LDS table (default);
